@@ -1,0 +1,189 @@
+/*
+ * hgv.h -- C ABI of the MI355X (gfx950) Hermitian-definite generalized
+ * eigensolver:  A x = lambda B x,  A Hermitian, B Hermitian positive definite.
+ *
+ * The solve follows Algorithm 1 of the paper (Cholesky of B, reduction to the
+ * standard form A' = L^-1 A L^-H, standard eigensolve, back-substitution
+ * x = L^-H y) with the two-stage standard eigensolver of Algorithm 2 /
+ * Sec. 4.2 (dense -> band by block Householder panels, band -> tridiagonal
+ * by column-wise bulge chasing), the divide-and-conquer tridiagonal solver of
+ * Sec. 4.3 (only the wanted eigenvectors at the last merge), and the two-step
+ * eigenvector back-transformation of Sec. 4.2 (through Q2, then Q1).
+ *
+ * Conventions shared by every call
+ *  - Matrices are column-major: element (i, j) of a matrix with leading
+ *    dimension ld is at index i + j*ld.  Complex numbers are interleaved
+ *    (re, im) pairs (hgv_c128 / hgv_c64).
+ *  - Every matrix/vector pointer is a DEVICE pointer owned by the caller.  The
+ *    library never allocates or frees caller memory and allocates no device
+ *    memory of its own: scratch space is the caller's `work` buffer, whose
+ *    size comes from the matching *_bufsize query.  `work` must be 256-byte
+ *    aligned.
+ *  - All calls are asynchronous on the stream set with hgv_set_stream (the
+ *    null stream by default) and return once the work is enqueued.  Only the
+ *    optional hgv_stats output synchronizes the stream.
+ *  - Return value = host status: HGV_OK, a negative value -i when argument i
+ *    (1-based, counting the context as argument 1) is invalid (checked on the
+ *    host before anything is launched), or one of the HGV_E_* codes.
+ *    Numerical failures are written to the device integer *d_info with the
+ *    LAPACK xHEGV meaning (0 ok; k in [1,n]: the tridiagonal solver failed on
+ *    eigenvalue k; n+k: the leading minor of order k of B is not positive
+ *    definite).  d_info may be NULL.
+ *  - Only the lower triangles of A and B are read; their strict upper
+ *    triangles may be overwritten (they are workspace).
+ */
+#ifndef HGV_H
+#define HGV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hgv_c128;
+typedef struct { float re, im; } hgv_c64;
+
+typedef struct hgv_ctx_s *hgv_ctx_t;
+
+enum {
+    HGV_OK = 0,
+    HGV_E_HIP = 1001,        /* a HIP runtime call failed (see hgv_last_hip_error) */
+    HGV_E_WORKSPACE = 1002,  /* work_bytes smaller than the *_bufsize query */
+    HGV_E_CTX = 1003,        /* null or destroyed context */
+    HGV_E_NOTSUP = 1004      /* option combination not supported */
+};
+
+enum { HGV_FP64 = 0, HGV_MIXED = 1 };
+
+/* Solver options.  A NULL opts pointer means all defaults. */
+typedef struct {
+    int precision;         /* HGV_FP64 (default) or HGV_MIXED: complex64 band
+                              reduction / back-transforms + fp64 refinement */
+    int nb;                /* band width = panel width; 0 picks the tuned default */
+    int max_refine_iters;  /* HGV_MIXED only; 0 -> 3 */
+    double refine_tol;     /* HGV_MIXED only; target residual, 0 -> 1e-15 */
+} hgv_opts;
+
+/* Stage indices of hgv_stats.ms / flops. */
+enum {
+    HGV_ST_POTRF = 0, HGV_ST_HEGST, HGV_ST_HE2HB, HGV_ST_HB2ST, HGV_ST_STEDC,
+    HGV_ST_Q2, HGV_ST_Q1, HGV_ST_TRSM, HGV_ST_REFINE, HGV_NSTAGES
+};
+
+/* Optional per-call statistics.  Filling it records HIP events on the stream
+ * and synchronizes it at the end of the call. */
+typedef struct {
+    float ms[HGV_NSTAGES];       /* elapsed time per stage (HIP events)           */
+    double flops[HGV_NSTAGES];   /* algorithmic flops per stage (LAPACK counts)   */
+    double gemm_ms;              /* summed duration of every MFMA GEMM launch     */
+    double gemm_flops;           /* algorithmic flops of those launches           */
+    int gemm_launches;
+    int refine_iters;            /* HGV_MIXED: refinement iterations performed    */
+    int nb;                      /* band width used                               */
+} hgv_stats;
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds a context to HIP device `device` (made current by every call). */
+int hgv_create(hgv_ctx_t *ctx, int device);
+int hgv_destroy(hgv_ctx_t ctx);
+/* `stream` is a hipStream_t (e.g. torch.cuda.current_stream().cuda_stream). */
+int hgv_set_stream(hgv_ctx_t ctx, void *stream);
+const char *hgv_status_string(int status);
+/* Last HIP error code seen by the context (0 if none). */
+int hgv_last_hip_error(hgv_ctx_t ctx);
+/* Band width the solver uses for order n and precision when opts->nb == 0. */
+int hgv_default_nb(int n, int precision);
+
+/* ---- full generalized solve (Algorithm 1) -------------------------------- */
+/* Workspace bytes needed by hgv_zhegvx for these arguments. */
+int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts,
+                       size_t *bytes);
+
+/* Eigenpairs il..iu (1-based, inclusive; 1 <= il <= iu <= n; ascending
+ * eigenvalues) of the pencil (A, B), n >= 0.
+ *   A [in, destroyed]  n x n, lda >= max(1,n); lower triangle read.
+ *   B [in/out]         n x n, ldb >= max(1,n); lower triangle read; on exit
+ *                      its lower triangle holds the Cholesky factor L.
+ *   W [out]            m = iu-il+1 doubles.
+ *   X [out]            n x m, ldx >= max(1,n); X^H B X = I.
+ * Argument numbers for -i: ctx 1, n 2, A 3, lda 4, B 5, ldb 6, il 7, iu 8,
+ * W 9, X 10, ldx 11, work 12, work_bytes 13, opts 14. */
+int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
+               int il, int iu, double *W, hgv_c128 *X, int ldx,
+               void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
+               hgv_stats *stats);
+
+/* ---- stages (each one step of Algorithm 1 / Algorithm 2) ----------------- */
+/* Workspace bytes of one stage call below (stage = HGV_ST_*; m = number of
+ * eigenvector columns where it matters, nb = band width where it matters). */
+int hgv_stage_bufsize(hgv_ctx_t ctx, int stage, int n, int nb, int m, size_t *bytes);
+
+/* Alg. 1 step 1: B = L L^H in place (lower), L_ii real > 0.  d_info gets k
+ * (1-based) when the leading minor of order k is not positive definite;
+ * the factor is then incomplete. */
+int hgv_zpotrf(hgv_ctx_t ctx, int n, hgv_c128 *B, int ldb, void *work, size_t work_bytes,
+               int *d_info);
+
+/* Alg. 1 step 2: A <- L^-1 A L^-H (lower triangle of A in/out, L from
+ * hgv_zpotrf).  The strict upper triangle of A is used as scratch. */
+int hgv_zhegst(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, const hgv_c128 *L, int ldl,
+               void *work, size_t work_bytes);
+
+/* Alg. 2 step 1, first stage (Sec. 4.2, Fig. 1): A = Q1 Band Q1^H.
+ * On exit the lower band of A (0 <= i-j <= nb) holds Band; the Householder
+ * vectors of panel p (columns p*nb .. p*nb+nb-1) sit below the band (unit
+ * leading element implicit), and T1 (ceil(n/nb) blocks of nb x nb, block p at
+ * T1 + p*nb*nb, column-major, upper triangular) holds the compact-WY factors:
+ * panel p's transform is I - V_p T_p V_p^H.  Every reflector maps its column
+ * onto a real multiple of e_1, so the band's first subdiagonal inside a panel
+ * is real. */
+int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1,
+               void *work, size_t work_bytes);
+
+/* Alg. 2 step 1, second stage (Sec. 4.2): column-wise bulge chasing of the
+ * band held in the lower band of A (as left by hgv_zhe2hb; A is not modified)
+ * to the real symmetric tridiagonal (d[n], e[n-1]) with Band = Q2 T Q2^H.
+ * V2 receives the reflectors (hgv_v2_elems(n, nb) complex entries) and tau2
+ * their scalars (hgv_v2_taus(n, nb) entries), in the layout hgv_zunmtr_q2
+ * reads. */
+int hgv_zhb2st(hgv_ctx_t ctx, int n, int nb, const hgv_c128 *A, int lda, double *d,
+               double *e, hgv_c128 *V2, hgv_c128 *tau2, void *work, size_t work_bytes);
+size_t hgv_v2_elems(int n, int nb);
+size_t hgv_v2_taus(int n, int nb);
+
+/* Alg. 2 step 2 (Sec. 4.3): divide and conquer on the real symmetric
+ * tridiagonal (d, e) -> all n eigenvalues ascending in lambda[n], and the
+ * eigenvectors il..iu in Z (n x m real, ldz >= n; only the needed columns are
+ * formed in the last merge).  d_info gets k >= 1 on failure. */
+int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu,
+               double *lambda, double *Z, int ldz, void *work, size_t work_bytes,
+               int *d_info);
+
+/* Alg. 2 step 3, first part: Y <- Q2 Y (Y n x m complex, ldy >= n). */
+int hgv_zunmtr_q2(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *V2,
+                  const hgv_c128 *tau2, hgv_c128 *Y, int ldy, void *work, size_t work_bytes);
+
+/* Alg. 2 step 3, second part: Y <- Q1 Y, with Q1 from hgv_zhe2hb (reflectors in
+ * A below the band, factors in T1). */
+int hgv_zunmtr_q1(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *A, int lda,
+                  const hgv_c128 *T1, hgv_c128 *Y, int ldy, void *work, size_t work_bytes);
+
+/* Alg. 1 step 4: X <- L^-H X (X n x m, L lower from hgv_zpotrf). */
+int hgv_ztrsm_lh(hgv_ctx_t ctx, int n, int m, const hgv_c128 *L, int ldl, hgv_c128 *X,
+                 int ldx, void *work, size_t work_bytes);
+
+/* ---- building block -------------------------------------------------------- */
+/* C <- alpha op(A) op(B) + beta C on the MFMA tiles the stages use.
+ * opa/opb: 'N', 'T' (transpose) or 'C' (conjugate transpose).  C is m x n,
+ * op(A) m x k, op(B) k x n.  `work` (hgv_stage_bufsize(HGV_ST_NSTAGES...) not
+ * needed: may be NULL) is unused for these shapes. */
+int hgv_zgemm(hgv_ctx_t ctx, char opa, char opb, int m, int n, int k, hgv_c128 alpha,
+              const hgv_c128 *A, int lda, const hgv_c128 *B, int ldb, hgv_c128 beta,
+              hgv_c128 *C, int ldc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGV_H */

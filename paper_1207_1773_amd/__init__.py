@@ -1,0 +1,203 @@
+"""Python binding of libhgv.so, the gfx950 Hermitian-definite generalized eigensolver.
+
+The ``hgv_*`` functions mirror the C ABI in ``include/hgv.h`` one to one (raw device
+pointers as integers, status codes turned into exceptions).  ``eigh`` and friends
+marshal torch tensors: they make column-major copies of the inputs, allocate the
+workspace the library asks for, pass the current HIP stream and view the outputs.
+Every arithmetic step of the solve runs in the library's HIP kernels; when the
+library is not built this module raises instead of computing anything itself.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgv.so")
+
+HGV_OK = 0
+HGV_E_HIP = 1001
+HGV_E_WORKSPACE = 1002
+HGV_E_CTX = 1003
+HGV_E_NOTSUP = 1004
+HGV_FP64 = 0
+HGV_MIXED = 1
+(HGV_ST_POTRF, HGV_ST_HEGST, HGV_ST_HE2HB, HGV_ST_HB2ST, HGV_ST_STEDC, HGV_ST_Q2, HGV_ST_Q1,
+ HGV_ST_TRSM, HGV_ST_REFINE, HGV_NSTAGES) = range(10)
+STAGE_NAMES = ["potrf", "hegst", "he2hb", "hb2st", "stedc", "q2", "q1", "trsm", "refine"]
+
+EXPORTS = [
+    "hgv_create", "hgv_destroy", "hgv_set_stream", "hgv_status_string", "hgv_last_hip_error",
+    "hgv_default_nb", "hgv_zhegvx_bufsize", "hgv_zhegvx", "hgv_stage_bufsize", "hgv_zpotrf",
+    "hgv_zhegst", "hgv_zhe2hb", "hgv_zhb2st", "hgv_v2_elems", "hgv_v2_taus", "hgv_dstedc",
+    "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm",
+]
+
+
+class c128(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int),
+                ("max_refine_iters", ctypes.c_int), ("refine_tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_float * HGV_NSTAGES), ("flops", ctypes.c_double * HGV_NSTAGES),
+                ("gemm_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
+                ("gemm_launches", ctypes.c_int), ("refine_iters", ctypes.c_int), ("nb", ctypes.c_int)]
+
+    def as_dict(self):
+        return {
+            "ms": {STAGE_NAMES[i]: float(self.ms[i]) for i in range(HGV_NSTAGES)},
+            "flops": {STAGE_NAMES[i]: float(self.flops[i]) for i in range(HGV_NSTAGES)},
+            "gemm_ms": float(self.gemm_ms), "gemm_flops": float(self.gemm_flops),
+            "gemm_launches": int(self.gemm_launches), "refine_iters": int(self.refine_iters),
+            "nb": int(self.nb),
+        }
+
+
+class HgvError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = _lib.hgv_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__("%s: status %d (%s)" % (where, status, msg))
+
+
+_lib = None
+P = ctypes.c_void_p
+I = ctypes.c_int
+SZ = ctypes.c_size_t
+
+
+def load():
+    """Load libhgv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhgv.so is not built (run paper_1207_1773_amd.build.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "hgv_create": (I, [ctypes.POINTER(P), I]),
+        "hgv_destroy": (I, [P]),
+        "hgv_set_stream": (I, [P, P]),
+        "hgv_status_string": (ctypes.c_char_p, [I]),
+        "hgv_last_hip_error": (I, [P]),
+        "hgv_default_nb": (I, [I, I]),
+        "hgv_zhegvx_bufsize": (I, [P, I, I, I, ctypes.POINTER(Opts), ctypes.POINTER(SZ)]),
+        "hgv_zhegvx": (I, [P, I, P, I, P, I, I, I, P, P, I, P, SZ, ctypes.POINTER(Opts), P,
+                           ctypes.POINTER(Stats)]),
+        "hgv_stage_bufsize": (I, [P, I, I, I, I, ctypes.POINTER(SZ)]),
+        "hgv_zpotrf": (I, [P, I, P, I, P, SZ, P]),
+        "hgv_zhegst": (I, [P, I, P, I, P, I, P, SZ]),
+        "hgv_zhe2hb": (I, [P, I, I, P, I, P, P, SZ]),
+        "hgv_zhb2st": (I, [P, I, I, P, I, P, P, P, P, P, SZ]),
+        "hgv_v2_elems": (SZ, [I, I]),
+        "hgv_v2_taus": (SZ, [I, I]),
+        "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
+        "hgv_zunmtr_q2": (I, [P, I, I, I, P, P, P, I, P, SZ]),
+        "hgv_zunmtr_q1": (I, [P, I, I, I, P, I, P, P, I, P, SZ]),
+        "hgv_ztrsm_lh": (I, [P, I, I, P, I, P, I, P, SZ]),
+        "hgv_zgemm": (I, [P, ctypes.c_char, ctypes.c_char, I, I, I, c128, P, I, P, I, c128, P, I]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, where):
+    if status != HGV_OK:
+        raise HgvError(status, where)
+
+
+# ---- one-to-one wrappers of the C ABI (pointers as Python ints) ------------------------
+def hgv_create(device=0):
+    h = P()
+    _check(load().hgv_create(ctypes.byref(h), device), "hgv_create")
+    return h
+
+
+def hgv_destroy(ctx):
+    _check(load().hgv_destroy(ctx), "hgv_destroy")
+
+
+def hgv_set_stream(ctx, stream):
+    _check(load().hgv_set_stream(ctx, stream), "hgv_set_stream")
+
+
+def hgv_default_nb(n, precision=HGV_FP64):
+    return load().hgv_default_nb(n, precision)
+
+
+def hgv_zhegvx_bufsize(ctx, n, il, iu, opts=None):
+    out = SZ()
+    _check(load().hgv_zhegvx_bufsize(ctx, n, il, iu, ctypes.byref(opts) if opts else None, ctypes.byref(out)),
+           "hgv_zhegvx_bufsize")
+    return out.value
+
+
+def hgv_zhegvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes, opts=None, d_info=None, stats=None):
+    st = load().hgv_zhegvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes,
+                           ctypes.byref(opts) if opts else None, d_info,
+                           ctypes.byref(stats) if stats is not None else None)
+    _check(st, "hgv_zhegvx")
+
+
+def hgv_stage_bufsize(ctx, stage, n, nb=0, m=0):
+    out = SZ()
+    _check(load().hgv_stage_bufsize(ctx, stage, n, nb, m, ctypes.byref(out)), "hgv_stage_bufsize")
+    return out.value
+
+
+def hgv_zpotrf(ctx, n, B, ldb, work, work_bytes, d_info):
+    _check(load().hgv_zpotrf(ctx, n, B, ldb, work, work_bytes, d_info), "hgv_zpotrf")
+
+
+def hgv_zhegst(ctx, n, A, lda, L, ldl, work, work_bytes):
+    _check(load().hgv_zhegst(ctx, n, A, lda, L, ldl, work, work_bytes), "hgv_zhegst")
+
+
+def hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes):
+    _check(load().hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes), "hgv_zhe2hb")
+
+
+def hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes):
+    _check(load().hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes), "hgv_zhb2st")
+
+
+def hgv_v2_elems(n, nb):
+    return load().hgv_v2_elems(n, nb)
+
+
+def hgv_v2_taus(n, nb):
+    return load().hgv_v2_taus(n, nb)
+
+
+def hgv_dstedc(ctx, n, d, e, il, iu, lam, Z, ldz, work, work_bytes, d_info):
+    _check(load().hgv_dstedc(ctx, n, d, e, il, iu, lam, Z, ldz, work, work_bytes, d_info), "hgv_dstedc")
+
+
+def hgv_zunmtr_q2(ctx, n, nb, m, V2, tau2, Y, ldy, work, work_bytes):
+    _check(load().hgv_zunmtr_q2(ctx, n, nb, m, V2, tau2, Y, ldy, work, work_bytes), "hgv_zunmtr_q2")
+
+
+def hgv_zunmtr_q1(ctx, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes):
+    _check(load().hgv_zunmtr_q1(ctx, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes), "hgv_zunmtr_q1")
+
+
+def hgv_ztrsm_lh(ctx, n, m, L, ldl, X, ldx, work, work_bytes):
+    _check(load().hgv_ztrsm_lh(ctx, n, m, L, ldl, X, ldx, work, work_bytes), "hgv_ztrsm_lh")
+
+
+def hgv_zgemm(ctx, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
+    a = c128(alpha.real, alpha.imag)
+    b = c128(beta.real, beta.imag)
+    _check(load().hgv_zgemm(ctx, opa.encode(), opb.encode(), m, n, k, a, A, lda, B, ldb, b, C, ldc), "hgv_zgemm")
+
+
+# ---- torch marshalling ---------------------------------------------------------------------
+from . import tensors  # noqa: E402  (torch-facing helpers)
+from .tensors import Context, eigh, colmajor, from_colmajor  # noqa: E402,F401

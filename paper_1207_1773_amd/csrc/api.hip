@@ -1,0 +1,528 @@
+// api.hip -- the extern "C" entry points declared in include/hgv.h: argument
+// checks (before any launch), workspace planning, stage sequencing for the
+// full solve of Algorithm 1, optional per-stage event timing.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "hgv_internal.h"
+
+using namespace hgv;
+
+namespace {
+
+constexpr int kMagic = 0x68677631;
+
+bool ctx_ok(hgv_ctx_t c) { return c != nullptr && c->magic == kMagic; }
+
+struct NotSupported {};
+
+// Wraps an entry point body: selects the device, converts internal
+// exceptions into status codes.
+template <class F>
+int guarded(hgv_ctx_t ctx, F &&body) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    try {
+        HGV_HIP(hipSetDevice(ctx->device));
+        return body();
+    } catch (const HipFail &f) {
+        ctx->last_hip_error = (int)f.err;
+        return HGV_E_HIP;
+    } catch (const WorkspaceShort &) {
+        return HGV_E_WORKSPACE;
+    } catch (const NotSupported &) {
+        return HGV_E_NOTSUP;
+    } catch (const std::bad_alloc &) {
+        return HGV_E_HIP;
+    }
+}
+
+int resolve_nb(int n, const hgv_opts *o) {
+    int nb = (o && o->nb > 0) ? o->nb : hgv_default_nb(n, o ? o->precision : HGV_FP64);
+    return std::max(1, nb);
+}
+
+// Event pairs around stages when statistics are requested.
+struct StageTimer {
+    hgv_ctx_s *ctx;
+    hgv_stats *st;
+    hipEvent_t ev[HGV_NSTAGES + 1][2] = {};
+    bool used[HGV_NSTAGES] = {};
+    StageTimer(hgv_ctx_s *c, hgv_stats *s) : ctx(c), st(s) {
+        if (!st) return;
+        std::memset(st, 0, sizeof(*st));
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            HGV_HIP(hipEventCreate(&ev[i][0]));
+            HGV_HIP(hipEventCreate(&ev[i][1]));
+        }
+        ctx->time_gemm = true;
+        ctx->gemm_ms = 0.0;
+        ctx->gemm_flops = 0.0;
+        ctx->gemm_launches = 0;
+    }
+    void begin(int s) {
+        if (st) HGV_HIP(hipEventRecord(ev[s][0], ctx->stream));
+    }
+    void end(int s, double flops) {
+        if (!st) return;
+        HGV_HIP(hipEventRecord(ev[s][1], ctx->stream));
+        used[s] = true;
+        st->flops[s] += flops;
+    }
+    void finish() {
+        if (!st) return;
+        HGV_HIP(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            if (used[i]) HGV_HIP(hipEventElapsedTime(&st->ms[i], ev[i][0], ev[i][1]));
+        }
+        double ms = 0.0, fl = 0.0;
+        for (size_t i = 0; i < ctx->ev_pending.size(); ++i) {
+            float t = 0.f;
+            HGV_HIP(hipEventElapsedTime(&t, ctx->ev_pending[i].first, ctx->ev_pending[i].second));
+            ms += t;
+            fl += ctx->ev_flops[i];
+            ctx->ev_free.push_back(ctx->ev_pending[i].first);
+            ctx->ev_free.push_back(ctx->ev_pending[i].second);
+        }
+        st->gemm_ms = ms;
+        st->gemm_flops = fl;
+        st->gemm_launches = (int)ctx->ev_pending.size();
+        ctx->ev_pending.clear();
+        ctx->ev_flops.clear();
+        ctx->time_gemm = false;
+    }
+    ~StageTimer() {
+        if (!st) return;
+        ctx->time_gemm = false;
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            (void)hipEventDestroy(ev[i][0]);
+            (void)hipEventDestroy(ev[i][1]);
+        }
+    }
+};
+
+// Complex copy of a real n x m matrix (Z -> Y).
+__global__ void real_to_complex_kernel(int n, int m, const double *Z, int ldz, double2 *Y, int ldy) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < n && j < m) Y[i + (size_t)j * ldy] = make_double2(Z[i + (size_t)j * ldz], 0.0);
+}
+
+__global__ void copy_doubles_kernel(int n, const double *a, double *b) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Full solve (Algorithm 1 with the two-stage Algorithm 2), FP64.  Shared by
+// the size query (arena without base) and the run.
+void zhegvx_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb, int il, int iu,
+                 double *W, double2 *X, int ldx, Arena &ar, int nb, int *d_info, StageTimer *tm) {
+    const int m = iu - il + 1;
+    const int np = cdiv(n, nb);
+    double2 *T1 = ar.take<double2>((size_t)np * nb * nb);
+    double *d = ar.take<double>(n);
+    double *e = ar.take<double>(std::max(n - 1, 1));
+    double *lambda = ar.take<double>(n);
+    double2 *V2 = ar.take<double2>(v2_elems(n, nb));
+    double2 *tau2 = ar.take<double2>(v2_taus(n, nb));
+    double *Z = ar.take<double>((size_t)n * m);
+    const size_t mk = ar.mark();
+    const bool run = !ar.measuring();
+    const double N = n, M = m;
+
+    if (run) set_info(ctx, d_info, 0);
+    if (tm) tm->begin(HGV_ST_POTRF);
+    potrf_run(ctx, n, B, ldb, ar, d_info, n);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_POTRF, 4.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_HEGST);
+    hegst_run(ctx, n, A, lda, B, ldb, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_HEGST, 4.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_HE2HB);
+    he2hb_run(ctx, n, nb, A, lda, T1, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_HB2ST);
+    hb2st_run(ctx, n, nb, A, lda, d, e, V2, tau2, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+
+    if (tm) tm->begin(HGV_ST_STEDC);
+    stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info);
+    ar.release(mk);
+    if (run) {
+        hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,
+                           lambda + (il - 1), W);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(real_to_complex_kernel, dim3(cdiv(n, 64), cdiv(m, 4)), dim3(256), 0, ctx->stream, n,
+                           m, Z, n, X, ldx);
+        HGV_LAUNCH_CHECK();
+    }
+    if (tm) tm->end(HGV_ST_STEDC, 4.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_Q2);
+    unmtr_q2_run(ctx, n, nb, m, V2, tau2, X, ldx, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_Q2, 8.0 * N * N * M);
+
+    if (tm) tm->begin(HGV_ST_Q1);
+    unmtr_q1_run(ctx, n, nb, m, A, lda, T1, X, ldx, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_Q1, 8.0 * N * N * M);
+
+    if (tm) tm->begin(HGV_ST_TRSM);
+    trsm_lh_run(ctx, n, m, B, ldb, X, ldx, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_TRSM, 4.0 * N * N * M);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hgv_create(hgv_ctx_t *ctx, int device) {
+    if (!ctx) return -1;
+    *ctx = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return -2;
+    hgv_ctx_s *c = new (std::nothrow) hgv_ctx_s();
+    if (!c) return HGV_E_HIP;
+    c->device = device;
+    c->magic = kMagic;
+    *ctx = c;
+    return HGV_OK;
+}
+
+int hgv_destroy(hgv_ctx_t ctx) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    (void)hipSetDevice(ctx->device);
+    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+    for (auto &p : ctx->ev_pending) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    ctx->magic = 0;
+    delete ctx;
+    return HGV_OK;
+}
+
+int hgv_set_stream(hgv_ctx_t ctx, void *stream) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return HGV_OK;
+}
+
+int hgv_last_hip_error(hgv_ctx_t ctx) { return ctx_ok(ctx) ? ctx->last_hip_error : 0; }
+
+const char *hgv_status_string(int status) {
+    if (status == HGV_OK) return "success";
+    if (status < 0) return "invalid argument";
+    switch (status) {
+        case HGV_E_HIP: return "HIP runtime error";
+        case HGV_E_WORKSPACE: return "workspace too small";
+        case HGV_E_CTX: return "invalid context";
+        case HGV_E_NOTSUP: return "unsupported option";
+    }
+    return "unknown status";
+}
+
+int hgv_default_nb(int n, int precision) {
+    (void)precision;
+    if (n <= 1024) return 32;
+    return 64;
+}
+
+int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && (il < 1 || il > n)) return -3;
+    if (n > 0 && (iu < il || iu > n)) return -4;
+    if (!bytes) return -6;
+    *bytes = 0;
+    if (n == 0) return HGV_OK;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -5;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        zhegvx_fp64(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts),
+                    nullptr, nullptr);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb, int il, int iu, double *W,
+               hgv_c128 *X, int ldx, void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
+               hgv_stats *stats) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    const int nn = std::max(1, n);
+    if (n > 0 && !A) return -3;
+    if (lda < nn) return -4;
+    if (n > 0 && !B) return -5;
+    if (ldb < nn) return -6;
+    if (n > 0 && (il < 1 || il > n)) return -7;
+    if (n > 0 && (iu < il || iu > n)) return -8;
+    if (n > 0 && !W) return -9;
+    if (n > 0 && !X) return -10;
+    if (ldx < nn) return -11;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
+    if (opts && opts->nb < 0) return -14;
+    if (n == 0) return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        return HGV_OK;
+    });
+    size_t need = 0;
+    int st = hgv_zhegvx_bufsize(ctx, n, il, iu, opts, &need);
+    if (st != HGV_OK) return st;
+    if (n > 0 && !work) return -12;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(work) & 255) return -12;
+    if (opts && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    return guarded(ctx, [&]() {
+        StageTimer tm(ctx, stats);
+        Arena ar(work, work_bytes);
+        int nb = resolve_nb(n, opts);
+        zhegvx_fp64(ctx, n, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(B), ldb, il, iu,
+                    W, reinterpret_cast<double2 *>(X), ldx, ar, nb, d_info, stats ? &tm : nullptr);
+        if (stats) {
+            tm.finish();
+            stats->nb = nb;
+        }
+        return HGV_OK;
+    });
+}
+
+// ---- stage entry points -----------------------------------------------------------
+static void stage_plan(hgv_ctx_s *ctx, int stage, int n, int nb, int m, Arena &ar) {
+    switch (stage) {
+        case HGV_ST_POTRF: potrf_run(ctx, n, nullptr, n, ar, nullptr, 0); break;
+        case HGV_ST_HEGST: hegst_run(ctx, n, nullptr, n, nullptr, n, ar); break;
+        case HGV_ST_HE2HB: he2hb_run(ctx, n, nb, nullptr, n, nullptr, ar); break;
+        case HGV_ST_HB2ST: hb2st_run(ctx, n, nb, nullptr, n, nullptr, nullptr, nullptr, nullptr, ar); break;
+        case HGV_ST_STEDC: stedc_run(ctx, n, nullptr, nullptr, 1, std::max(m, 1), nullptr, nullptr, n, ar, nullptr); break;
+        case HGV_ST_Q2: unmtr_q2_run(ctx, n, nb, m, nullptr, nullptr, nullptr, n, ar); break;
+        case HGV_ST_Q1: unmtr_q1_run(ctx, n, nb, m, nullptr, n, nullptr, nullptr, n, ar); break;
+        case HGV_ST_TRSM: trsm_lh_run(ctx, n, m, nullptr, n, nullptr, n, ar); break;
+        default: throw NotSupported{};
+    }
+}
+
+int hgv_stage_bufsize(hgv_ctx_t ctx, int stage, int n, int nb, int m, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (stage < 0 || stage >= HGV_NSTAGES) return -2;
+    if (n < 0) return -3;
+    if (nb < 0) return -4;
+    if (m < 0) return -5;
+    if (!bytes) return -6;
+    *bytes = 0;
+    if (n == 0) return HGV_OK;
+    if (nb == 0) nb = hgv_default_nb(n, HGV_FP64);
+    return guarded(ctx, [&]() {
+        Arena ar;
+        stage_plan(ctx, stage, n, nb, m, ar);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+static int check_work(hgv_ctx_t ctx, int stage, int n, int nb, int m, void *work, size_t work_bytes,
+                      int argno) {
+    size_t need = 0;
+    int st = hgv_stage_bufsize(ctx, stage, n, nb, m, &need);
+    if (st != HGV_OK) return st;
+    if (need > 256 && !work) return -argno;
+    if (work && (reinterpret_cast<uintptr_t>(work) & 255)) return -argno;
+    if (work_bytes < need && need > 256) return HGV_E_WORKSPACE;
+    return HGV_OK;
+}
+
+int hgv_zpotrf(hgv_ctx_t ctx, int n, hgv_c128 *B, int ldb, void *work, size_t work_bytes, int *d_info) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && !B) return -3;
+    if (ldb < std::max(1, n)) return -4;
+    int st = check_work(ctx, HGV_ST_POTRF, n, 0, 0, work, work_bytes, 5);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        Arena ar(work, work_bytes);
+        potrf_run(ctx, n, reinterpret_cast<double2 *>(B), ldb, ar, d_info, 0);
+        return HGV_OK;
+    });
+}
+
+int hgv_zhegst(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, const hgv_c128 *L, int ldl, void *work,
+               size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max(1, n)) return -4;
+    if (n > 0 && !L) return -5;
+    if (ldl < std::max(1, n)) return -6;
+    int st = check_work(ctx, HGV_ST_HEGST, n, 0, 0, work, work_bytes, 7);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        hegst_run(ctx, n, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<const double2 *>(L), ldl, ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1, void *work,
+               size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < std::max(1, n)) return -5;
+    if (n > 0 && !T1) return -6;
+    int st = check_work(ctx, HGV_ST_HE2HB, n, nb, 0, work, work_bytes, 7);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        he2hb_run(ctx, n, nb, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(T1), ar);
+        return HGV_OK;
+    });
+}
+
+size_t hgv_v2_elems(int n, int nb) { return (n > 0 && nb > 0) ? v2_elems(n, nb) : 0; }
+size_t hgv_v2_taus(int n, int nb) { return (n > 0 && nb > 0) ? v2_taus(n, nb) : 0; }
+
+int hgv_zhb2st(hgv_ctx_t ctx, int n, int nb, const hgv_c128 *A, int lda, double *d, double *e, hgv_c128 *V2,
+               hgv_c128 *tau2, void *work, size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < std::max(1, n)) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (n > 0 && !V2) return -8;
+    if (n > 0 && !tau2) return -9;
+    int st = check_work(ctx, HGV_ST_HB2ST, n, nb, 0, work, work_bytes, 10);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        hb2st_run(ctx, n, nb, reinterpret_cast<const double2 *>(A), lda, d, e, reinterpret_cast<double2 *>(V2),
+                  reinterpret_cast<double2 *>(tau2), ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *lambda, double *Z,
+               int ldz, void *work, size_t work_bytes, int *d_info) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && !d) return -3;
+    if (n > 1 && !e) return -4;
+    if (n > 0 && (il < 1 || il > n)) return -5;
+    if (n > 0 && (iu < il || iu > n)) return -6;
+    if (n > 0 && !lambda) return -7;
+    if (n > 0 && !Z) return -8;
+    if (ldz < std::max(1, n)) return -9;
+    const int m = n > 0 ? iu - il + 1 : 0;
+    int st = check_work(ctx, HGV_ST_STEDC, n, 0, m, work, work_bytes, 10);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        if (n == 0) return HGV_OK;
+        Arena ar(work, work_bytes);
+        stedc_run(ctx, n, d, e, il, iu, lambda, Z, ldz, ar, d_info);
+        return HGV_OK;
+    });
+}
+
+int hgv_zunmtr_q2(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *V2, const hgv_c128 *tau2, hgv_c128 *Y,
+                  int ldy, void *work, size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1) return -3;
+    if (m < 0) return -4;
+    if (n > 0 && !V2) return -5;
+    if (n > 0 && !tau2) return -6;
+    if (n > 0 && m > 0 && !Y) return -7;
+    if (ldy < std::max(1, n)) return -8;
+    int st = check_work(ctx, HGV_ST_Q2, n, nb, m, work, work_bytes, 9);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        unmtr_q2_run(ctx, n, nb, m, reinterpret_cast<const double2 *>(V2), reinterpret_cast<const double2 *>(tau2),
+                     reinterpret_cast<double2 *>(Y), ldy, ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_zunmtr_q1(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *A, int lda, const hgv_c128 *T1,
+                  hgv_c128 *Y, int ldy, void *work, size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1) return -3;
+    if (m < 0) return -4;
+    if (n > 0 && !A) return -5;
+    if (lda < std::max(1, n)) return -6;
+    if (n > 0 && !T1) return -7;
+    if (n > 0 && m > 0 && !Y) return -8;
+    if (ldy < std::max(1, n)) return -9;
+    int st = check_work(ctx, HGV_ST_Q1, n, nb, m, work, work_bytes, 10);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        unmtr_q1_run(ctx, n, nb, m, reinterpret_cast<const double2 *>(A), lda,
+                     reinterpret_cast<const double2 *>(T1), reinterpret_cast<double2 *>(Y), ldy, ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_ztrsm_lh(hgv_ctx_t ctx, int n, int m, const hgv_c128 *L, int ldl, hgv_c128 *X, int ldx, void *work,
+                 size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (m < 0) return -3;
+    if (n > 0 && !L) return -4;
+    if (ldl < std::max(1, n)) return -5;
+    if (n > 0 && m > 0 && !X) return -6;
+    if (ldx < std::max(1, n)) return -7;
+    int st = check_work(ctx, HGV_ST_TRSM, n, 0, m, work, work_bytes, 8);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        trsm_lh_run(ctx, n, m, reinterpret_cast<const double2 *>(L), ldl, reinterpret_cast<double2 *>(X), ldx, ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_zgemm(hgv_ctx_t ctx, char opa, char opb, int m, int n, int k, hgv_c128 alpha, const hgv_c128 *A, int lda,
+              const hgv_c128 *B, int ldb, hgv_c128 beta, hgv_c128 *C, int ldc) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    auto okop = [](char o) { return o == 'N' || o == 'T' || o == 'C'; };
+    if (!okop(opa)) return -2;
+    if (!okop(opb)) return -3;
+    if (m < 0) return -4;
+    if (n < 0) return -5;
+    if (k < 0) return -6;
+    const int ra = (opa == 'N') ? m : k, rb = (opb == 'N') ? k : n;
+    if (m > 0 && k > 0 && !A) return -8;
+    if (lda < std::max(1, ra)) return -9;
+    if (n > 0 && k > 0 && !B) return -10;
+    if (ldb < std::max(1, rb)) return -11;
+    if (m > 0 && n > 0 && !C) return -13;
+    if (ldc < std::max(1, m)) return -14;
+    return guarded(ctx, [&]() {
+        ZGemm g;
+        g.m = m; g.n = n; g.k = k;
+        g.opa = opa; g.opb = opb;
+        g.A = reinterpret_cast<const double2 *>(A); g.lda = lda;
+        g.B = reinterpret_cast<const double2 *>(B); g.ldb = ldb;
+        g.alpha = make_double2(alpha.re, alpha.im);
+        g.beta = make_double2(beta.re, beta.im);
+        g.C = reinterpret_cast<double2 *>(C); g.ldc = ldc;
+        zgemm(ctx, g, nullptr, 0);
+        return HGV_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// gemm.hip -- MFMA matrix-multiply tiles for gfx950.
+//
+// Every level-3 operation of the solver (the herk/her2k/hemm/trsm updates of
+// the Cholesky and reduction to standard form, the two-sided trailing update
+// of the band reduction, the block-reflector back-transformations, the
+// divide-and-conquer eigenvector merges) is issued as one of these GEMMs.
+//
+// Design (CDNA4):
+//  * workgroup = 4 wave64s arranged 2 x 2; each wave owns a (BM/2) x (BN/2)
+//    sub-tile made of 16x16 MFMA blocks;
+//  * complex double: four real v_mfma_f64_16x16x4f64 per 16x16x4 complex block
+//    (re*re, -im*im into the real accumulator, re*im, im*re into the
+//    imaginary one); real double: one; complex float: four
+//    v_mfma_f32_16x16x4f32 with fp32 accumulation;
+//  * A and B tiles of depth 16 are staged through LDS (interleaved complex,
+//    one padding element per row against bank conflicts) with the next
+//    tile's global loads issued before the current tile's MFMAs;
+//  * the block index is remapped so that consecutive tiles land on the same
+//    XCD (workgroups are dealt round-robin over the 8 XCDs) and tiles are
+//    walked in column groups of 8 row-tiles so one XCD's L2 sees the same
+//    operand panels;
+//  * split-K (deterministic: partial tiles summed in a fixed order by a
+//    second kernel) for outputs with too few tiles to fill 256 CUs.
+#include "hgv_internal.h"
+
+namespace hgv {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---- element traits -----------------------------------------------------------
+struct TZ {  // complex double
+    typedef double2 E;
+    typedef v4d Acc;
+    typedef double S;
+    static constexpr bool cplx = true;
+    __device__ static E zero() { return make_double2(0.0, 0.0); }
+    __device__ static E conj(E a) { return make_double2(a.x, -a.y); }
+    __device__ static E realpart(E a) { return make_double2(a.x, 0.0); }
+    __device__ static Acc mfma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // output layout of v_mfma_f64_16x16x4f64: lane l, register r -> row l/16 + 4r, column l%16
+    __device__ static int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+struct TD {  // real double
+    typedef double E;
+    typedef v4d Acc;
+    typedef double S;
+    static constexpr bool cplx = false;
+    __device__ static E zero() { return 0.0; }
+    __device__ static E conj(E a) { return a; }
+    __device__ static E realpart(E a) { return a; }
+    __device__ static Acc mfma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+struct TC {  // complex float
+    typedef float2 E;
+    typedef v4f Acc;
+    typedef float S;
+    static constexpr bool cplx = true;
+    __device__ static E zero() { return make_float2(0.0f, 0.0f); }
+    __device__ static E conj(E a) { return make_float2(a.x, -a.y); }
+    __device__ static E realpart(E a) { return make_float2(a.x, 0.0f); }
+    __device__ static Acc mfma(S a, S b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // output layout of v_mfma_f32_16x16x4f32: lane l, register r -> row 4(l/16) + r, column l%16
+    __device__ static int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <class T>
+struct GemmDev {
+    typedef typename T::E E;
+    int m, n, k;
+    const E *A; int lda; int opa;
+    const E *B; int ldb; int opb;
+    const E *A2; int lda2; int opa2;
+    const E *B2; int ldb2; int opb2;
+    int nseg;
+    E alpha, beta;
+    int beta_zero;
+    E *C; int ldc;
+    int lower;
+    int splits;        // split-K factor (gridDim.y)
+    E *P;              // partial tiles when splits > 1: splits x (m x n), ld m
+    int tiles_m, tiles_n;
+};
+
+constexpr int BK = 16;
+constexpr int PAD = 1;
+
+__device__ inline int remap_xcd(int bid, int total) {
+    int full = (total / 8) * 8;
+    if (bid < full) return (bid % 8) * (total / 8) + bid / 8;
+    return bid;
+}
+
+// Load the BM x BK tile of op(A) (rows m0.., cols k0..) into registers; idx
+// receives the LDS slot of every element.  op: 0 N, 1 T, 2 C, 3 H.
+template <class T, int BM>
+__device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int op, int M, int K,
+                              int m0, int k0, int tid, typename T::E (&r)[BM * BK / 256],
+                              int (&idx)[BM * BK / 256]) {
+    typedef typename T::E E;
+    constexpr int NE = BM * BK / 256;
+    bool mirrored = (op == 1 || op == 2) || (op == 3 && m0 + BM - 1 < k0);
+    if (!mirrored) {
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+            int e = tid + t * 256;
+            int mm = e % BM, kk = e / BM;
+            int gm = m0 + mm, gk = k0 + kk;
+            E v = T::zero();
+            if (gm < M && gk < K) {
+                if (op == 0 || gm > gk) v = A[gm + (size_t)gk * lda];
+                else if (gm == gk) v = T::realpart(A[gm + (size_t)gm * lda]);
+                else v = T::conj(A[gk + (size_t)gm * lda]);
+            }
+            r[t] = v;
+            idx[t] = kk * (BM + PAD) + mm;
+        }
+    } else {
+        bool cj = (op == 2 || op == 3);
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+            int e = tid + t * 256;
+            int kk = e % BK, mm = e / BK;
+            int gm = m0 + mm, gk = k0 + kk;
+            E v = T::zero();
+            if (gm < M && gk < K) {
+                v = A[gk + (size_t)gm * lda];
+                if (cj) v = T::conj(v);
+            }
+            r[t] = v;
+            idx[t] = kk * (BM + PAD) + mm;
+        }
+    }
+}
+
+// Load the BK x BN tile of op(B) (rows k0.., cols n0..).  op: 0 N, 1 T, 2 C.
+template <class T, int BN>
+__device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int op, int K, int N,
+                              int k0, int n0, int tid, typename T::E (&r)[BN * BK / 256],
+                              int (&idx)[BN * BK / 256]) {
+    typedef typename T::E E;
+    constexpr int NE = BN * BK / 256;
+    if (op == 0) {
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+            int e = tid + t * 256;
+            int kk = e % BK, nn = e / BK;
+            int gk = k0 + kk, gn = n0 + nn;
+            E v = T::zero();
+            if (gk < K && gn < N) v = B[gk + (size_t)gn * ldb];
+            r[t] = v;
+            idx[t] = kk * (BN + PAD) + nn;
+        }
+    } else {
+        bool cj = (op == 2);
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+            int e = tid + t * 256;
+            int nn = e % BN, kk = e / BN;
+            int gk = k0 + kk, gn = n0 + nn;
+            E v = T::zero();
+            if (gk < K && gn < N) {
+                v = B[gn + (size_t)gk * ldb];
+                if (cj) v = T::conj(v);
+            }
+            r[t] = v;
+            idx[t] = kk * (BN + PAD) + nn;
+        }
+    }
+}
+
+template <class T>
+__device__ inline void mfma_step(typename T::E a, typename T::E b, typename T::Acc &ar, typename T::Acc &ai);
+
+template <>
+__device__ inline void mfma_step<TZ>(double2 a, double2 b, v4d &ar, v4d &ai) {
+    ar = TZ::mfma(a.x, b.x, ar);
+    ar = TZ::mfma(-a.y, b.y, ar);
+    ai = TZ::mfma(a.x, b.y, ai);
+    ai = TZ::mfma(a.y, b.x, ai);
+}
+template <>
+__device__ inline void mfma_step<TC>(float2 a, float2 b, v4f &ar, v4f &ai) {
+    ar = TC::mfma(a.x, b.x, ar);
+    ar = TC::mfma(-a.y, b.y, ar);
+    ai = TC::mfma(a.x, b.y, ai);
+    ai = TC::mfma(a.y, b.x, ai);
+}
+template <>
+__device__ inline void mfma_step<TD>(double a, double b, v4d &ar, v4d &ai) {
+    (void)ai;
+    ar = TD::mfma(a, b, ar);
+}
+
+template <class T>
+__device__ inline typename T::E make_e(typename T::S re, typename T::S im);
+template <>
+__device__ inline double2 make_e<TZ>(double re, double im) { return make_double2(re, im); }
+template <>
+__device__ inline float2 make_e<TC>(float re, float im) { return make_float2(re, im); }
+template <>
+__device__ inline double make_e<TD>(double re, double im) { (void)im; return re; }
+
+__device__ inline double2 e_mul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline float2 e_mul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double e_mul(double a, double b) { return a * b; }
+__device__ inline double2 e_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 e_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline double e_add(double a, double b) { return a + b; }
+
+template <class T, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmDev<T> g) {
+    typedef typename T::E E;
+    typedef typename T::Acc Acc;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+    __shared__ E As[BK * (BM + PAD)];
+    __shared__ E Bs[BK * (BN + PAD)];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    // tile selection: XCD-aware remap, then column groups of 8 row tiles
+    const int total = g.tiles_m * g.tiles_n;
+    int id = remap_xcd(blockIdx.x, total);
+    constexpr int GROUP = 8;
+    int per_group = GROUP * g.tiles_n;
+    int grp = id / per_group;
+    int first_m = grp * GROUP;
+    int gm_cnt = min(g.tiles_m - first_m, GROUP);
+    int within = id % per_group;
+    int tm = first_m + within % gm_cnt;
+    int tn = within / gm_cnt;
+    const int m0 = tm * BM, n0 = tn * BN;
+    if (g.lower && m0 + BM - 1 < n0) return;  // tile entirely above the diagonal
+
+    // K range of this split (chunks of BK over the concatenated segments)
+    const int cps = (g.k + BK - 1) / BK;  // chunks per segment
+    const int nchunks = cps * g.nseg;
+    const int z = blockIdx.y;
+    const int per = (nchunks + g.splits - 1) / g.splits;
+    const int c_beg = z * per;
+    const int c_end = min(nchunks, c_beg + per);
+
+    Acc accR[FM][FN], accI[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            accR[i][j] = Acc{0, 0, 0, 0};
+            accI[i][j] = Acc{0, 0, 0, 0};
+        }
+
+    E ra[NA], rb[NB];
+    int ia[NA], ib[NB];
+    auto fetch = [&](int c) {
+        int seg = c / cps;
+        int k0 = (c % cps) * BK;
+        if (seg == 0) {
+            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, ia);
+            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ib);
+        } else {
+            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, ia);
+            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ib);
+        }
+    };
+
+    if (c_beg < c_end) fetch(c_beg);
+    for (int c = c_beg; c < c_end; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NA; ++t) As[ia[t]] = ra[t];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) Bs[ib[t]] = rb[t];
+        __syncthreads();
+        if (c + 1 < c_end) fetch(c + 1);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kl = ks * 4 + (lane >> 4);
+            E af[FM], bf[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) af[i] = As[kl * (BM + PAD) + wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) bf[j] = Bs[kl * (BN + PAD) + wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) mfma_step<T>(af[i], bf[j], accR[i][j], accI[i][j]);
+        }
+    }
+
+    // epilogue: each lane holds four rows (T::out_row) of column lane%16 of each block
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = m0 + wm * WM + i * 16 + T::out_row(lane, r);
+                int col = n0 + wn * WN + j * 16 + (lane & 15);
+                if (row >= g.m || col >= g.n) continue;
+                if (g.lower && row < col) continue;
+                E v = make_e<T>(accR[i][j][r], accI[i][j][r]);
+                if (g.splits > 1) {
+                    g.P[(size_t)z * g.m * g.n + row + (size_t)col * g.m] = v;
+                } else {
+                    E o = e_mul(g.alpha, v);
+                    if (!g.beta_zero) o = e_add(o, e_mul(g.beta, g.C[row + (size_t)col * g.ldc]));
+                    g.C[row + (size_t)col * g.ldc] = o;
+                }
+            }
+}
+
+// C = alpha * sum_z P[z] + beta * C  (fixed summation order)
+template <class T>
+__global__ __launch_bounds__(256) void splitk_reduce(GemmDev<T> g) {
+    typedef typename T::E E;
+    size_t total = (size_t)g.m * g.n;
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+        int row = (int)(t % g.m), col = (int)(t / g.m);
+        if (g.lower && row < col) continue;
+        E s = g.P[t];
+        for (int z = 1; z < g.splits; ++z) s = e_add(s, g.P[(size_t)z * total + t]);
+        E o = e_mul(g.alpha, s);
+        if (!g.beta_zero) o = e_add(o, e_mul(g.beta, g.C[row + (size_t)col * g.ldc]));
+        g.C[row + (size_t)col * g.ldc] = o;
+    }
+}
+
+static int op_code(char op) {
+    switch (op) {
+        case 'N': case 'n': return 0;
+        case 'T': case 't': return 1;
+        case 'C': case 'c': return 2;
+        case 'H': case 'h': return 3;
+    }
+    return -1;
+}
+
+// Choose tile shape and split-K factor, then launch.  `ws` (bytes) holds the
+// partial tiles of split-K; when it is too small the split factor is reduced.
+template <class T, class G>
+static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws_bytes,
+                        double flops) {
+    typedef typename T::E E;
+    if (a.m <= 0 || a.n <= 0) return;
+    GemmDev<T> g;
+    g.m = a.m; g.n = a.n; g.k = a.k;
+    g.A = a.A; g.lda = a.lda; g.opa = op_code(a.opa);
+    g.B = a.B; g.ldb = a.ldb; g.opb = op_code(a.opb);
+    g.A2 = a.A2; g.lda2 = a.lda2; g.opa2 = op_code(a.opa2);
+    g.B2 = a.B2; g.ldb2 = a.ldb2; g.opb2 = op_code(a.opb2);
+    g.nseg = (a.A2 && a.B2) ? 2 : 1;
+    g.alpha = a.alpha; g.beta = a.beta;
+    g.C = a.C; g.ldc = a.ldc;
+    g.lower = a.lower;
+    g.P = nullptr;
+    {
+        const char *pb = reinterpret_cast<const char *>(&a.beta);
+        bool z = true;
+        for (size_t i = 0; i < sizeof(a.beta); ++i) z = z && pb[i] == 0;
+        g.beta_zero = z ? 1 : 0;
+    }
+    if (a.k <= 0) {
+        // C = beta C only (alpha * empty sum); realised as a split-free launch
+        // with no chunks.
+    }
+    // tile shape: 64x64 (4 waves of 32x32) for the complex types; 128x64 for real
+    constexpr int BM = T::cplx ? 64 : 128;
+    constexpr int BN = 64;
+    g.tiles_m = cdiv(a.m, BM);
+    g.tiles_n = cdiv(a.n, BN);
+    int tiles = g.tiles_m * g.tiles_n;
+    if (a.lower) tiles = tiles;  // upper tiles exit at once
+    int chunks = cdiv(std::max(a.k, 0), BK) * g.nseg;
+    int splits = 1;
+    // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
+    while (splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 16) splits *= 2;
+    size_t need = (size_t)splits * a.m * a.n * sizeof(E);
+    while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
+        splits /= 2;
+        need = (size_t)splits * a.m * a.n * sizeof(E);
+    }
+    g.splits = splits;
+    g.P = splits > 1 ? ws : nullptr;
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->time_gemm) {
+        if (ctx->ev_free.size() < 2) {
+            hipEvent_t x, y;
+            HGV_HIP(hipEventCreate(&x));
+            HGV_HIP(hipEventCreate(&y));
+            ctx->ev_free.push_back(x);
+            ctx->ev_free.push_back(y);
+        }
+        e0 = ctx->ev_free.back(); ctx->ev_free.pop_back();
+        e1 = ctx->ev_free.back(); ctx->ev_free.pop_back();
+        HGV_HIP(hipEventRecord(e0, ctx->stream));
+    }
+    dim3 grid(g.tiles_m * g.tiles_n, splits);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+    HGV_LAUNCH_CHECK();
+    if (splits > 1) {
+        size_t total = (size_t)a.m * a.n;
+        int blocks = (int)std::min<size_t>(cdivz(total, 256), 4096);
+        hipLaunchKernelGGL((splitk_reduce<T>), dim3(blocks), dim3(256), 0, ctx->stream, g);
+        HGV_LAUNCH_CHECK();
+    }
+    if (ctx->time_gemm) {
+        HGV_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->ev_pending.push_back({e0, e1});
+        ctx->ev_flops.push_back(flops);
+    }
+}
+
+size_t zgemm_splitk_bytes(int n) {
+    // room for 16 partial tiles of a 256 x 256 output (or n x n when smaller)
+    size_t d = (size_t)std::min(std::max(n, 64), 256);
+    return 16 * d * d * sizeof(double2);
+}
+
+void zgemm(hgv_ctx_s *ctx, const ZGemm &g, double2 *ws, size_t ws_bytes) {
+    if (g.m <= 0 || g.n <= 0) return;
+    double f = 8.0 * g.m * (double)g.n * g.k * ((g.A2 && g.B2) ? 2 : 1);
+    if (g.lower) f *= 0.5;
+    gemm_launch<TZ>(ctx, g, ws, ws_bytes, f);
+}
+
+void cgemm(hgv_ctx_s *ctx, const CGemm &g, float2 *ws, size_t ws_bytes) {
+    if (g.m <= 0 || g.n <= 0) return;
+    double f = 8.0 * g.m * (double)g.n * g.k * ((g.A2 && g.B2) ? 2 : 1);
+    if (g.lower) f *= 0.5;
+    gemm_launch<TC>(ctx, g, ws, ws_bytes, f);
+}
+
+struct DGemmArgs {
+    int m, n, k;
+    char opa, opb;
+    const double *A; int lda;
+    const double *B; int ldb;
+    char opa2, opb2;
+    const double *A2; int lda2;
+    const double *B2; int ldb2;
+    double alpha, beta;
+    double *C; int ldc;
+    int lower;
+};
+
+void dgemm_nn(hgv_ctx_s *ctx, int m, int n, int k, double alpha, const double *A, int lda,
+              const double *B, int ldb, double beta, double *C, int ldc) {
+    if (m <= 0 || n <= 0) return;
+    DGemmArgs a{m, n, k, 'N', 'N', A, lda, B, ldb, 'N', 'N', nullptr, 1, nullptr, 1, alpha, beta, C, ldc, 0};
+    gemm_launch<TD>(ctx, a, nullptr, 0, 2.0 * m * (double)n * k);
+}
+
+}  // namespace hgv

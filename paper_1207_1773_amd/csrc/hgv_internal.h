@@ -1,0 +1,173 @@
+// hgv_internal.h -- shared declarations of the gfx950 solver library (not part
+// of the public ABI).  Device complex numbers are double2 (x = re, y = im) or
+// float2 for the complex64 path; matrices are column-major.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "hgv.h"
+
+struct hgv_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int last_hip_error = 0;
+    // Optional per-call accounting of the MFMA GEMM launches (events around
+    // every launch; enabled only while a call fills hgv_stats).
+    bool time_gemm = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    std::vector<double> ev_flops;
+    double gemm_ms = 0.0, gemm_flops = 0.0;
+    int gemm_launches = 0;
+    int magic = 0x68677631;
+};
+
+namespace hgv {
+
+// ---- errors -------------------------------------------------------------
+struct HipFail {
+    hipError_t err;
+};
+
+#define HGV_HIP(call)                                             \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) throw ::hgv::HipFail{e_};           \
+    } while (0)
+
+#define HGV_LAUNCH_CHECK() HGV_HIP(hipGetLastError())
+
+struct WorkspaceShort {
+    size_t need;
+};
+
+// ---- scratch arena ---------------------------------------------------------
+// Carves 256-byte aligned pieces out of the caller's workspace.  With a null
+// base it only measures (the *_bufsize queries run the same planning code).
+// Stages run one after another on one stream, so a stage's private scratch
+// is released (reset to a mark) when it returns; `peak` is the size needed.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+    size_t peak = 0;
+    Arena() = default;
+    Arena(void *b, size_t c) : base(static_cast<char *>(b)), cap(c) {}
+    template <class T>
+    T *take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        size_t at = off;
+        off += bytes;
+        if (off > peak) peak = off;
+        if (!base) return nullptr;
+        if (off > cap) throw WorkspaceShort{off};
+        return reinterpret_cast<T *>(base + at);
+    }
+    bool measuring() const { return base == nullptr; }
+    size_t mark() const { return off; }
+    void release(size_t m) { off = m; }
+};
+
+// ---- device complex helpers ---------------------------------------------------
+__host__ __device__ inline double2 zmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline double2 zcmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 zscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__host__ __device__ inline double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// a += b * c
+__host__ __device__ inline void zfma(double2 &a, double2 b, double2 c) {
+    a.x = fma(b.x, c.x, fma(-b.y, c.y, a.x));
+    a.y = fma(b.x, c.y, fma(b.y, c.x, a.y));
+}
+__host__ __device__ inline double2 zdiv(double2 a, double2 b) {
+    double s = 1.0 / (b.x * b.x + b.y * b.y);
+    return make_double2((a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s);
+}
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+inline size_t cdivz(size_t a, size_t b) { return (a + b - 1) / b; }
+
+// ---- GEMM (gemm.hip) -------------------------------------------------------
+// C <- alpha * (opA(A) opB(B) [+ opA2(A2) opB2(B2)]) + beta * C, complex double.
+// op: 'N', 'T', 'C'; for A also 'H': A is Hermitian (m == k) with only its
+// lower triangle stored (diagonal taken real).  lower != 0 restricts the
+// output to the elements i >= j (tiles entirely above the diagonal are
+// skipped, elements above it are not written).
+struct ZGemm {
+    int m = 0, n = 0, k = 0;
+    char opa = 'N', opb = 'N';
+    const double2 *A = nullptr; int lda = 1;
+    const double2 *B = nullptr; int ldb = 1;
+    char opa2 = 'N', opb2 = 'N';
+    const double2 *A2 = nullptr; int lda2 = 1;
+    const double2 *B2 = nullptr; int ldb2 = 1;
+    double2 alpha = {1.0, 0.0}, beta = {0.0, 0.0};
+    double2 *C = nullptr; int ldc = 1;
+    int lower = 0;
+};
+// Workspace for split-K partial sums reserved by every stage that calls zgemm.
+size_t zgemm_splitk_bytes(int n);
+void zgemm(hgv_ctx_s *ctx, const ZGemm &g, double2 *splitk_ws, size_t splitk_bytes);
+
+// Real double GEMM (divide-and-conquer merges): C <- A B (+ beta C), 'N' ops only.
+void dgemm_nn(hgv_ctx_s *ctx, int m, int n, int k, double alpha, const double *A, int lda,
+              const double *B, int ldb, double beta, double *C, int ldc);
+
+// Complex float GEMM for the mixed-precision path (same conventions as ZGemm).
+struct CGemm {
+    int m = 0, n = 0, k = 0;
+    char opa = 'N', opb = 'N';
+    const float2 *A = nullptr; int lda = 1;
+    const float2 *B = nullptr; int ldb = 1;
+    char opa2 = 'N', opb2 = 'N';
+    const float2 *A2 = nullptr; int lda2 = 1;
+    const float2 *B2 = nullptr; int ldb2 = 1;
+    float2 alpha = {1.0f, 0.0f}, beta = {0.0f, 0.0f};
+    float2 *C = nullptr; int ldc = 1;
+    int lower = 0;
+};
+void cgemm(hgv_ctx_s *ctx, const CGemm &g, float2 *splitk_ws, size_t splitk_bytes);
+
+// ---- small helpers (misc.hip) ---------------------------------------------------
+void fill_upper_from_lower(hgv_ctx_s *ctx, int n, double2 *A, int lda);
+void zero_strict_upper(hgv_ctx_s *ctx, int n, double2 *A, int lda);
+void copy_matrix(hgv_ctx_s *ctx, int m, int n, const double2 *A, int lda, double2 *B, int ldb);
+void set_info(hgv_ctx_s *ctx, int *d_info, int value);
+
+// ---- stages ----------------------------------------------------------------------
+// Every stage has a plan (arena-driven size) and a run with the same arena.
+void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_info, int info_offset);
+void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, Arena &ar);
+void trsm_lh_run(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
+// Triangular solves used by the recursive stages (L lower n x n):
+//   right_lc:  X <- X L^-H      (X m x n)
+//   left_ln:   X <- L^-1 X      (X n x m)
+//   left_lc:   X <- L^-H X      (X n x m)
+void trsm_right_lc(hgv_ctx_s *ctx, int m, int n, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
+void trsm_left_ln(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
+void trsm_left_lc(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
+
+void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar);
+void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e,
+               double2 *V2, double2 *tau2, Arena &ar);
+size_t v2_elems(int n, int nb);
+size_t v2_taus(int n, int nb);
+void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu,
+               double *lambda, double *Z, int ldz, Arena &ar, int *d_info);
+void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2,
+                  double2 *Y, int ldy, Arena &ar);
+void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A, int lda,
+                  const double2 *T1, double2 *Y, int ldy, Arena &ar);
+
+}  // namespace hgv

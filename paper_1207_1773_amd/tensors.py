@@ -1,0 +1,209 @@
+"""torch marshalling for libhgv: column-major device buffers, workspace, stream.
+
+Matrices are handed to the library as column-major buffers.  A torch matrix M
+(rows x cols) is stored column-major by the contiguous tensor ``M.mT.contiguous()``
+(shape cols x rows); the library's column-major output of shape rows x cols comes
+back as ``buf.mT``.  All arithmetic happens in the library; these helpers only copy,
+allocate and pass pointers.
+"""
+import ctypes
+
+import torch
+
+from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HGV_ST_POTRF, HGV_ST_Q1,
+               HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
+               hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
+               hgv_zhegst, hgv_zhegvx, hgv_zhegvx_bufsize, hgv_zpotrf, hgv_ztrsm_lh, hgv_zunmtr_q1,
+               hgv_zunmtr_q2, load)
+
+
+def colmajor(M, dtype=torch.complex128):
+    """Column-major copy of a matrix: a contiguous (cols x rows) tensor holding M^T."""
+    return M.to(dtype).mT.contiguous()
+
+
+def from_colmajor(buf):
+    """The (rows x cols) matrix whose column-major storage is buf (a view)."""
+    return buf.mT
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """One library context per device; calls run on torch's current stream."""
+
+    _cache = {}
+
+    def __init__(self, device=None):
+        load()
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("libhgv runs on a GPU device, got %s" % dev)
+        self.device = dev
+        self.handle = hgv_create(dev.index if dev.index is not None else 0)
+
+    @classmethod
+    def get(cls, device=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        key = dev.index or 0
+        if key not in cls._cache:
+            cls._cache[key] = Context(dev)
+        return cls._cache[key]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                hgv_destroy(h)
+            except Exception:
+                pass
+
+    def _sync_stream(self):
+        hgv_set_stream(self.handle, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def _work(self, nbytes):
+        n = max(int(nbytes), 256)
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def _info(self):
+        return torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    # ---- stages (inputs/outputs as ordinary torch matrices) -----------------------------
+    def potrf(self, B):
+        """Alg. 1 step 1: returns (L lower, info) for Hermitian PD B (lower triangle read)."""
+        self._sync_stream()
+        n = B.shape[0]
+        Bc = colmajor(B)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_POTRF, n))
+        info = self._info()
+        hgv_zpotrf(self.handle, n, _ptr(Bc), max(n, 1), _ptr(w), w.numel(), _ptr(info))
+        return torch.tril(from_colmajor(Bc)), int(info.item())
+
+    def hegst(self, A, L):
+        """Alg. 1 step 2: returns the lower triangle of L^-1 A L^-H."""
+        self._sync_stream()
+        n = A.shape[0]
+        Ac, Lc = colmajor(A), colmajor(L)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_HEGST, n))
+        hgv_zhegst(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Lc), max(n, 1), _ptr(w), w.numel())
+        return torch.tril(from_colmajor(Ac))
+
+    def he2hb(self, A, nb):
+        """Alg. 2 step 1, first stage: returns (A_out column-major buffer view, T1)."""
+        self._sync_stream()
+        n = A.shape[0]
+        Ac = colmajor(A)
+        np_ = (n + nb - 1) // nb
+        T1 = torch.zeros((max(np_, 1), nb, nb), dtype=torch.complex128, device=self.device)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_HE2HB, n, nb))
+        hgv_zhe2hb(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(w), w.numel())
+        return from_colmajor(Ac), T1
+
+    def hb2st(self, Aband, nb):
+        """Alg. 2 step 1, second stage: (d, e, V2, tau2) from the lower band of Aband."""
+        self._sync_stream()
+        n = Aband.shape[0]
+        Ac = colmajor(Aband)
+        d = torch.zeros(max(n, 1), dtype=torch.float64, device=self.device)
+        e = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        V2 = torch.zeros(max(hgv_v2_elems(n, nb), 1), dtype=torch.complex128, device=self.device)
+        tau2 = torch.zeros(max(hgv_v2_taus(n, nb), 1), dtype=torch.complex128, device=self.device)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_HB2ST, n, nb))
+        hgv_zhb2st(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(d), _ptr(e), _ptr(V2), _ptr(tau2), _ptr(w),
+                   w.numel())
+        return d[:n], e[:max(n - 1, 0)], V2, tau2
+
+    def stedc(self, d, e, il=1, iu=None):
+        """Alg. 2 step 2: (all eigenvalues, eigenvectors il..iu as n x m real, info)."""
+        self._sync_stream()
+        n = d.shape[0]
+        iu = n if iu is None else iu
+        m = iu - il + 1
+        dd = d.to(self.device, torch.float64).contiguous()
+        ee = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        if n > 1:
+            ee[:n - 1] = e[:n - 1]
+        lam = torch.zeros(max(n, 1), dtype=torch.float64, device=self.device)
+        Zc = torch.zeros((max(m, 1), max(n, 1)), dtype=torch.float64, device=self.device)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_STEDC, n, 0, m))
+        info = self._info()
+        hgv_dstedc(self.handle, n, _ptr(dd), _ptr(ee), il, iu, _ptr(lam), _ptr(Zc), max(n, 1), _ptr(w), w.numel(),
+                   _ptr(info))
+        return lam[:n], from_colmajor(Zc)[:n, :m], int(info.item())
+
+    def q2(self, V2, tau2, Y, nb):
+        """Alg. 2 step 3 (first part): Q2 Y."""
+        self._sync_stream()
+        n, m = Y.shape
+        Yc = colmajor(Y)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_Q2, n, nb, m))
+        hgv_zunmtr_q2(self.handle, n, nb, m, _ptr(V2), _ptr(tau2), _ptr(Yc), max(n, 1), _ptr(w), w.numel())
+        return from_colmajor(Yc)
+
+    def q1(self, Ab, T1, Y, nb):
+        """Alg. 2 step 3 (second part): Q1 Y with reflectors from he2hb (Ab as returned by he2hb)."""
+        self._sync_stream()
+        n, m = Y.shape
+        Ac = colmajor(Ab)
+        Yc = colmajor(Y)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_Q1, n, nb, m))
+        hgv_zunmtr_q1(self.handle, n, nb, m, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(Yc), max(n, 1), _ptr(w),
+                      w.numel())
+        return from_colmajor(Yc)
+
+    def trsm_lh(self, L, X):
+        """Alg. 1 step 4: L^-H X."""
+        self._sync_stream()
+        n, m = X.shape
+        Lc, Xc = colmajor(L), colmajor(X)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_TRSM, n, 0, m))
+        hgv_ztrsm_lh(self.handle, n, m, _ptr(Lc), max(n, 1), _ptr(Xc), max(n, 1), _ptr(w), w.numel())
+        return from_colmajor(Xc)
+
+    def gemm(self, opa, opb, A, B, alpha=1.0, beta=0.0, C=None):
+        """C <- alpha op(A) op(B) + beta C on the library's MFMA tiles."""
+        self._sync_stream()
+        Ac, Bc = colmajor(A), colmajor(B)
+        ra, ca = A.shape
+        rb, cb = B.shape
+        m = ra if opa == "N" else ca
+        k = ca if opa == "N" else ra
+        n = cb if opb == "N" else rb
+        Cc = colmajor(C) if C is not None else torch.zeros((n, m), dtype=torch.complex128, device=self.device)
+        hgv_zgemm(self.handle, opa, opb, m, n, k, complex(alpha), _ptr(Ac), max(ra, 1), _ptr(Bc), max(rb, 1),
+                  complex(beta), _ptr(Cc), max(m, 1))
+        return from_colmajor(Cc)
+
+    # ---- full solve ------------------------------------------------------------------------------
+    def zhegvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, inplace=False):
+        """Eigenpairs il..iu of (A, B).  Returns (W, X, info, stats_dict_or_None).
+
+        With inplace=True, A and B must already be column-major buffers (as made by
+        ``colmajor``); they are then destroyed / overwritten by L."""
+        self._sync_stream()
+        n = A.shape[0]
+        iu = n if iu is None else iu
+        m = iu - il + 1
+        Ac = A if inplace else colmajor(A)
+        Bc = B if inplace else colmajor(B)
+        opts = Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), 0, 0.0)
+        W = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
+        Xc = torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex128, device=self.device)
+        w = self._work(hgv_zhegvx_bufsize(self.handle, n, il, iu, opts))
+        info = self._info()
+        st = Stats() if stats else None
+        hgv_zhegvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
+                   _ptr(w), w.numel(), opts, _ptr(info), st)
+        return W[:m], from_colmajor(Xc)[:n, :m], int(info.item()), (st.as_dict() if st is not None else None)
+
+
+def eigh(A, B, il=1, iu=None, precision="fp64", nb=0):
+    """Eigenpairs il..iu (1-based, inclusive) of A x = lambda B x for Hermitian A and
+    Hermitian positive definite B (torch complex tensors on a GPU).  Returns (W, X)."""
+    ctx = Context.get(A.device)
+    W, X, info, _ = ctx.zhegvx(A, B, il, iu, precision, nb)
+    if info != 0:
+        raise RuntimeError("hgv_zhegvx failed: info = %d" % info)
+    return W, X
