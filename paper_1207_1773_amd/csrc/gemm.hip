@@ -418,9 +418,10 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
 }
 
 size_t zgemm_splitk_bytes(int n) {
-    // room for 16 partial tiles of a 256 x 256 output (or n x n when smaller)
+    // room for 16 partial tiles of a 256 x 256 output (or n x n when smaller),
+    // and for 8 partial copies of an n x 64 panel product
     size_t d = (size_t)std::min(std::max(n, 64), 256);
-    return 16 * d * d * sizeof(double2);
+    return std::max(16 * d * d, (size_t)8 * std::max(n, 1) * 64) * sizeof(double2);
 }
 
 void zgemm(hgv_ctx_s *ctx, const ZGemm &g, double2 *ws, size_t ws_bytes) {

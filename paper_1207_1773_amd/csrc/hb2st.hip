@@ -1,0 +1,431 @@
+// hb2st.hip -- second stage of the two-stage tridiagonalisation (Alg. 2
+// step 1, Sec. 4.2): column-wise bulge chasing of the Hermitian band of width
+// b to a real symmetric tridiagonal, and the matching back-transformation
+// Y <- Q2 Y of Alg. 2 step 3 (the first of the two back-transformation steps
+// the two-stage approach needs).
+//
+// Sweep s annihilates column s below its first subdiagonal.  Its task j acts
+// on the rows I_j = [s+1+j*b, s+(j+1)*b] (clipped to n):
+//   j = 0: reflector H_{s,0} from column s (rows I_0), applied on both sides
+//          of the diagonal block A[I_0, I_0];
+//   j > 0: the previous reflector is applied from the right to the block
+//          E = A[I_j, I_{j-1}] (this creates the bulge), H_{s,j} is generated
+//          from E's first column and applied from the left to E, then on both
+//          sides of A[I_j, I_j].
+// Every reflector H = I - tau v v^H maps its vector onto beta e_1 with beta
+// real, so the resulting tridiagonal is real.  Band storage keeps the lower
+// triangle with offsets 0 .. 2b-1 (the bulge reaches offset 2b-1):
+// element (r, c), r >= c, at AB[(r - c) + c * 2b].
+//
+// Parallel schedule (one persistent workgroup per sweep at a time, sweeps
+// dealt round-robin): task (s, j) touches rows/columns that overlap those of
+// task (s-1, j+1) but of no later task of sweep s-1, so it starts once sweep
+// s-1 has completed min(j+2, all) tasks.  Tasks that may run concurrently
+// touch disjoint data, and every task's arithmetic is fixed, so the result
+// equals the sequential one bit for bit.  Progress counters are published
+// with release stores and read with acquire loads at device (agent) scope.
+//
+// Q2 back-transformation: the reflectors H_{s,j} of b consecutive sweeps
+// s0 .. s0+b-1 at the same step j occupy a (2b-1) x b parallelogram of rows;
+// their product D = H_{s0} ... H_{s0+b-1} = I - V T V^H (compact WY).
+// Applying Q2 = prod_s prod_j H_{s,j} to Y is the same as applying the
+// groups block by block from the last block of sweeps to the first and,
+// within a block, with j ascending: any two reflectors whose rows overlap
+// keep their relative order.  Each workgroup owns a panel of columns of Y and
+// walks the groups in that order (no synchronisation between workgroups).
+#include <algorithm>
+
+#include "hgv_internal.h"
+
+namespace hgv {
+
+struct HbArgs {
+    int n, b, ldb;
+    double2 *AB;          // band storage, ldb = 2b
+    double2 *V2;          // group-major reflectors
+    double2 *tau2;
+    int *prog;            // tasks completed per sweep
+    int *err;             // set when a wait gives up
+    int J;                // tasks of sweep 0 (max over sweeps)
+};
+
+__host__ __device__ inline int hb_tasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
+
+__device__ inline double2 band_get(const double2 *AB, int ldb, int r, int c) {
+    // element (r, c) of the Hermitian band (r, c in range, |r - c| < ldb)
+    if (r >= c) return AB[(r - c) + (size_t)c * ldb];
+    double2 v = AB[(c - r) + (size_t)r * ldb];
+    return make_double2(v.x, -v.y);
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+template <int BM>
+__global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
+    __shared__ double2 Es[BM][BM + 1];
+    __shared__ double2 Ds[BM][BM + 1];
+    __shared__ double2 v[BM], vp[BM], pv[BM], wv[BM];
+    __shared__ double2 part[4][64];
+    __shared__ double2 sh_tau, sh_taup, sh_scale;
+    __shared__ double sh_beta, sh_tail;
+    const int tid = threadIdx.x;
+    const int n = a.n, b = a.b, ldb = a.ldb;
+    double2 *AB = a.AB;
+
+    for (int s = blockIdx.x; s < n - 1; s += gridDim.x) {
+        const int nt = hb_tasks(n, b, s);
+        for (int j = 0; j < nt; ++j) {
+            // ---- wait for sweep s-1 ------------------------------------------------
+            if (s > 0 && tid == 0) {
+                const int need = min(j + 2, hb_tasks(n, b, s - 1));
+                long spins = 0;
+                while (__hip_atomic_load(&a.prog[s - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(2);
+                    if (++spins > (1L << 26)) {
+                        __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            const int r0 = s + 1 + j * b;
+            const int L = min(b, n - r0);          // rows of this task
+            const int p0 = r0 - b;                 // first column of E (j > 0)
+            // ---- load D (full Hermitian from the lower band) and E / column s --------
+            for (int t = tid; t < L * L; t += 256) {
+                int i = t % L, k = t / L;
+                Ds[i][k] = band_get(AB, ldb, r0 + i, r0 + k);
+            }
+            if (j == 0) {
+                if (tid < L) Es[tid][0] = AB[(r0 + tid - s) + (size_t)s * ldb];
+            } else {
+                for (int t = tid; t < L * b; t += 256) {
+                    int i = t % L, c = t / L;
+                    Es[i][c] = AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb];
+                }
+            }
+            __syncthreads();
+            if (j > 0) {
+                // E <- E - tau_p (E v_p) v_p^H     (previous reflector from the right)
+                {
+                    const int i = tid & 63, q = tid >> 6;
+                    double2 acc = make_double2(0.0, 0.0);
+                    if (i < L)
+                        for (int c = q; c < b; c += 4) acc = zadd(acc, zmul(Es[i][c], vp[c]));
+                    part[q][i] = (i < L) ? acc : make_double2(0.0, 0.0);
+                }
+                __syncthreads();
+                if (tid < L) pv[tid] = zmul(sh_taup, zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid])));
+                __syncthreads();
+                for (int t = tid; t < L * b; t += 256) {
+                    int i = t % L, c = t / L;
+                    Es[i][c] = zsub(Es[i][c], zmul(pv[i], zconj(vp[c])));
+                }
+                __syncthreads();
+            }
+            // ---- reflector from Es[:, 0] -------------------------------------------------
+            if (tid < 64) {
+                double t2 = 0.0;
+                if (tid >= 1 && tid < L) t2 = zabs2(Es[tid][0]);
+                t2 = wave_sum(t2);
+                if (tid == 0) {
+                    double2 alpha = Es[0][0];
+                    double beta;
+                    double2 tau, scale;
+                    if (t2 == 0.0 && alpha.y == 0.0) {
+                        beta = alpha.x;
+                        tau = make_double2(0.0, 0.0);
+                        scale = make_double2(0.0, 0.0);
+                    } else {
+                        double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + t2);
+                        beta = -copysign(nrm, alpha.x);
+                        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                        scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+                    }
+                    sh_beta = beta;
+                    sh_tau = tau;
+                    sh_scale = scale;
+                }
+            }
+            __syncthreads();
+            if (tid < L) v[tid] = (tid == 0) ? make_double2(1.0, 0.0) : zmul(sh_scale, Es[tid][0]);
+            __syncthreads();
+            const double2 tau = sh_tau;
+            if (j == 0) {
+                if (tid < L) {
+                    double2 val = (tid == 0) ? make_double2(sh_beta, 0.0) : make_double2(0.0, 0.0);
+                    AB[(r0 + tid - s) + (size_t)s * ldb] = val;
+                }
+            } else {
+                // E[:, 1:] <- H^H E[:, 1:] = E - conj(tau) v (v^H E);  E[:, 0] = beta e_1
+                {
+                    const int c = tid & 63, q = tid >> 6;
+                    double2 acc = make_double2(0.0, 0.0);
+                    if (c >= 1 && c < b)
+                        for (int i = q; i < L; i += 4) acc = zadd(acc, zcmul(v[i], Es[i][c]));
+                    part[q][c] = (c < b) ? acc : make_double2(0.0, 0.0);
+                }
+                __syncthreads();
+                if (tid < b) {
+                    double2 s4 = zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid]));
+                    wv[tid] = zcmul(tau, s4);   // conj(tau) * (v^H E)_c
+                }
+                __syncthreads();
+                for (int t = tid; t < L * b; t += 256) {
+                    int i = t % L, c = t / L;
+                    double2 val;
+                    if (c == 0) val = (i == 0) ? make_double2(sh_beta, 0.0) : make_double2(0.0, 0.0);
+                    else val = zsub(Es[i][c], zmul(v[i], wv[c]));
+                    AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] = val;
+                }
+            }
+            // ---- two-sided update of D:  D <- H^H D H ------------------------------------
+            {
+                const int i = tid & 63, q = tid >> 6;
+                double2 acc = make_double2(0.0, 0.0);
+                if (i < L)
+                    for (int k = q; k < L; k += 4) acc = zadd(acc, zmul(Ds[i][k], v[k]));
+                part[q][i] = (i < L) ? acc : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            if (tid < L) pv[tid] = zmul(tau, zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid])));
+            __syncthreads();
+            if (tid < 64) {
+                // v^H p (real part suffices: tau-bar v^H p = |tau|^2 v^H D v is real)
+                double2 c = (tid < L) ? zcmul(v[tid], pv[tid]) : make_double2(0.0, 0.0);
+                double cr = wave_sum(c.x), ci = wave_sum(c.y);
+                if (tid == 0) {
+                    double2 vhp = make_double2(cr, ci);
+                    double2 half = zcmul(tau, vhp);          // conj(tau) v^H p
+                    sh_tail = 0.5 * half.x;
+                }
+            }
+            __syncthreads();
+            if (tid < L) wv[tid] = zsub(pv[tid], zscale(sh_tail, v[tid]));
+            __syncthreads();
+            for (int t = tid; t < L * L; t += 256) {
+                int i = t % L, k = t / L;
+                if (i < k) continue;
+                double2 val = zsub(zsub(Ds[i][k], zmul(v[i], zconj(wv[k]))), zmul(wv[i], zconj(v[k])));
+                if (i == k) val.y = 0.0;
+                AB[(i - k) + (size_t)(r0 + k) * ldb] = val;
+            }
+            // ---- store the reflector (group-major layout) and keep it for task j+1 -----
+            {
+                const int B = s / b, t = s % b;
+                size_t base = ((size_t)B * a.J + j) * b + t;
+                if (tid < b) a.V2[base * b + tid] = (tid < L) ? v[tid] : make_double2(0.0, 0.0);
+                if (tid == 0) a.tau2[base] = tau;
+            }
+            if (tid < L) vp[tid] = v[tid];
+            if (tid == 0) sh_taup = tau;
+            __threadfence();
+            __syncthreads();
+            if (tid == 0) __hip_atomic_store(&a.prog[s], j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Copy the lower band (offsets 0..b) of A into band storage; offsets b+1..2b-1 zero.
+__global__ void band_copy_kernel(int n, int b, const double2 *A, int lda, double2 *AB, int ldb) {
+    int off = threadIdx.x % ldb;
+    int c = blockIdx.x * (256 / ldb) + threadIdx.x / ldb;
+    if (threadIdx.x >= (256 / ldb) * ldb || c >= n) return;
+    int r = c + off;
+    double2 v = make_double2(0.0, 0.0);
+    if (off <= b && r < n) v = A[r + (size_t)c * lda];
+    if (off == 0) v.y = 0.0;
+    AB[off + (size_t)c * ldb] = v;
+}
+
+__global__ void tridiag_out_kernel(int n, const double2 *AB, int ldb, double *d, double *e) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) d[i] = AB[(size_t)i * ldb].x;
+    if (i < n - 1) e[i] = AB[1 + (size_t)i * ldb].x;
+}
+
+__global__ void zero2_kernel(double2 *p, size_t cnt) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    for (; i < cnt; i += (size_t)gridDim.x * blockDim.x) p[i] = make_double2(0.0, 0.0);
+}
+__global__ void zero_int_kernel(int *p, int cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < cnt; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+static int hb_J(int n, int b) { return n >= 2 ? hb_tasks(n, b, 0) : 0; }
+static int hb_nblk(int n, int b) { return n >= 2 ? cdiv(n - 1, b) : 0; }
+
+size_t v2_elems(int n, int nb) { return std::max<size_t>((size_t)hb_nblk(n, nb) * hb_J(n, nb) * nb * nb, 1); }
+size_t v2_taus(int n, int nb) { return std::max<size_t>((size_t)hb_nblk(n, nb) * hb_J(n, nb) * nb, 1); }
+
+static void zero2(hgv_ctx_s *ctx, double2 *p, size_t cnt) {
+    if (!cnt) return;
+    hipLaunchKernelGGL(zero2_kernel, dim3((unsigned)std::min<size_t>(cdivz(cnt, 256), 16384)), dim3(256), 0,
+                       ctx->stream, p, cnt);
+    HGV_LAUNCH_CHECK();
+}
+
+template <int BM>
+static void launch_hb2st(hgv_ctx_s *ctx, HbArgs &a) {
+    int dev = ctx->device, cus = 0, per = 0;
+    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM>, 256, 0));
+    int G = std::max(1, std::min(cus * std::max(per, 1), a.n - 1));
+    void *args[] = {&a};
+    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM>), dim3(G), dim3(256), args, 0,
+                                       ctx->stream));
+}
+
+void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e, double2 *V2,
+               double2 *tau2, Arena &ar) {
+    if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    const int b = nb, ldb = 2 * nb;
+    double2 *AB = ar.take<double2>((size_t)ldb * std::max(n, 1));
+    int *prog = ar.take<int>(std::max(n, 1));
+    int *err = ar.take<int>(1);
+    if (ar.measuring() || n == 0) return;
+    hipLaunchKernelGGL(band_copy_kernel, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB, ldb);
+    HGV_LAUNCH_CHECK();
+    zero2(ctx, V2, v2_elems(n, nb));
+    zero2(ctx, tau2, v2_taus(n, nb));
+    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, ctx->stream, prog, n);
+    HGV_LAUNCH_CHECK();
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, ctx->stream, err, 1);
+    HGV_LAUNCH_CHECK();
+    if (n >= 2) {
+        HbArgs a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
+        if (b <= 32) launch_hb2st<32>(ctx, a);
+        else launch_hb2st<64>(ctx, a);
+    }
+    hipLaunchKernelGGL(tridiag_out_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
+    HGV_LAUNCH_CHECK();
+}
+
+// ---- Q2 back-transformation ------------------------------------------------------------------
+// T of every diamond group (B, j): reflector t (sweep s0 + t) occupies local
+// rows t .. t+b-1 of the group; G[t1][t2] = sum_rows conj(V[row][t1]) V[row][t2],
+// T_tt = tau_t, T[0:t, t] = -tau_t T[0:t, 0:t] G[0:t, t].
+template <int BM>
+__global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int J, const double2 *V2, const double2 *tau2,
+                                                         double2 *T2) {
+    __shared__ double2 Vs[BM][BM + 1];
+    __shared__ double2 Gs[BM][BM + 1];
+    __shared__ double2 Ts[BM][BM + 1];
+    const int grp = blockIdx.x;                 // B * J + j
+    const int tid = threadIdx.x;
+    const double2 *vg = V2 + (size_t)grp * b * b;
+    const double2 *tg = tau2 + (size_t)grp * b;
+    for (int t = tid; t < b * b; t += 256) Vs[t / b][t % b] = vg[t];   // Vs[reflector][entry]
+    for (int t = tid; t < BM * BM; t += 256) Ts[t / BM][t % BM] = make_double2(0.0, 0.0);
+    __syncthreads();
+    // Gram entries for t1 < t2: rows rho in [t2, t1+b-1]
+    for (int t = tid; t < b * b; t += 256) {
+        int t1 = t % b, t2 = t / b;
+        if (t1 >= t2) continue;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int rho = t2; rho <= t1 + b - 1; ++rho) acc = zadd(acc, zcmul(Vs[t1][rho - t1], Vs[t2][rho - t2]));
+        Gs[t1][t2] = acc;
+    }
+    __syncthreads();
+    for (int c = 0; c < b; ++c) {
+        double2 tc = tg[c];
+        if (tid < c) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int l = tid; l < c; ++l) acc = zadd(acc, zmul(Ts[tid][l], Gs[l][c]));
+            Ts[tid][c] = zmul(make_double2(-tc.x, -tc.y), acc);
+        }
+        if (tid == 0) Ts[c][c] = tc;
+        __syncthreads();
+    }
+    double2 *tout = T2 + (size_t)grp * b * b;
+    for (int t = tid; t < b * b; t += 256) tout[t] = Ts[t % b][t / b];   // column-major b x b
+}
+
+// Y (n x m) <- Q2 Y; workgroup = NC columns; groups walked from the last block
+// of sweeps to the first, j ascending inside a block.
+template <int BM, int NC>
+__global__ __launch_bounds__(256) void q2_apply_kernel(int n, int m, int b, int J, int nblk, const double2 *V2,
+                                                        const double2 *T2, double2 *Y, int ldy) {
+    __shared__ double2 Vs[BM][BM + 1];          // Vs[t][i] = entry i of reflector t
+    __shared__ double2 Ts[BM][BM + 1];
+    __shared__ double2 Ys[2 * BM][NC + 1];
+    __shared__ double2 Ws[BM][NC + 1];
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * NC;
+    const int nc = min(NC, m - c0);
+    for (int B = nblk - 1; B >= 0; --B) {
+        for (int j = 0; j < J; ++j) {
+            const int R0 = B * b + 1 + j * b;
+            if (R0 > n - 1) break;
+            const int nrows = min(2 * b - 1, n - R0);
+            const int grp = B * J + j;
+            const double2 *vg = V2 + (size_t)grp * b * b;
+            const double2 *tg = T2 + (size_t)grp * b * b;
+            __syncthreads();
+            for (int t = tid; t < b * b; t += 256) {
+                Vs[t / b][t % b] = vg[t];
+                Ts[t % b][t / b] = tg[t];
+            }
+            for (int t = tid; t < nrows * NC; t += 256) {
+                int r = t % nrows, c = t / nrows;
+                Ys[r][c] = (c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            // W = V^H Y_rows
+            for (int t = tid; t < b * NC; t += 256) {
+                int c = t % NC, tt = t / NC;
+                double2 acc = make_double2(0.0, 0.0);
+                for (int i = 0; i < b && tt + i < nrows; ++i) acc = zadd(acc, zcmul(Vs[tt][i], Ys[tt + i][c]));
+                Ws[tt][c] = acc;
+            }
+            __syncthreads();
+            // W <- T W   (T upper triangular); computed into registers, then stored
+            double2 tw[(BM * NC + 255) / 256];
+            {
+                int q = 0;
+                for (int t = tid; t < b * NC; t += 256, ++q) {
+                    int c = t % NC, tt = t / NC;
+                    double2 acc = make_double2(0.0, 0.0);
+                    for (int l = tt; l < b; ++l) acc = zadd(acc, zmul(Ts[tt][l], Ws[l][c]));
+                    tw[q] = acc;
+                }
+            }
+            __syncthreads();
+            {
+                int q = 0;
+                for (int t = tid; t < b * NC; t += 256, ++q) Ws[t / NC][t % NC] = tw[q];
+            }
+            __syncthreads();
+            // Y_rows -= V W
+            for (int t = tid; t < nrows * NC; t += 256) {
+                int c = t % NC, r = t / NC;
+                double2 acc = Ys[r][c];
+                int tlo = max(0, r - b + 1), thi = min(r, b - 1);
+                for (int tt = tlo; tt <= thi; ++tt) acc = zsub(acc, zmul(Vs[tt][r - tt], Ws[tt][c]));
+                if (c < nc) Y[R0 + r + (size_t)(c0 + c) * ldy] = acc;
+            }
+        }
+    }
+}
+
+void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2, double2 *Y,
+                  int ldy, Arena &ar) {
+    if (nb > 32) throw HipFail{hipErrorInvalidValue};
+    const int b = nb;
+    const int J = hb_J(n, b), nblk = hb_nblk(n, b);
+    double2 *T2 = ar.take<double2>(std::max<size_t>((size_t)nblk * J * b * b, 1));
+    if (ar.measuring() || n < 2 || m == 0) return;
+    hipLaunchKernelGGL((q2_tbuild_kernel<32>), dim3(nblk * J), dim3(256), 0, ctx->stream, n, b, J, V2, tau2, T2);
+    HGV_LAUNCH_CHECK();
+    constexpr int NC = 64;
+    hipLaunchKernelGGL((q2_apply_kernel<32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, J, nblk, V2,
+                       T2, Y, ldy);
+    HGV_LAUNCH_CHECK();
+}
+
+}  // namespace hgv

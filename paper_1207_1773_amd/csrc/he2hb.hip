@@ -1,0 +1,342 @@
+// he2hb.hip -- first stage of the two-stage tridiagonalisation (Alg. 2 step 1,
+// Sec. 4.2, Fig. 1): reduction of the Hermitian A' to a band of width nb by
+// block Householder transformations, and the matching back-transformation
+// Y <- Q1 Y of Alg. 2 step 3.
+//
+// Panel p (columns k = p*nb .. k+jb-1) is factored below the band:
+//   (a) panel QR of P = A[k+nb:n, k:k+jb]:  P = (H_0 ... H_{r-1}) [R; 0],
+//       H_j = I - tau_j v_j v_j^H with H_j^H x = beta_j e_1, beta_j real;
+//   (b) T (compact WY, forward) from tau and V^H V:  H_0...H_{r-1} = I - V T V^H;
+//   (c) two-sided update of the trailing block A22 = A[k+nb:, k+nb:]:
+//       X = A22 V T (hemm), W = X - 1/2 V (T^H (V^H X)),
+//       A22 <- A22 - V W^H - W V^H (her2k, lower triangle only).
+// (b) and (c) are MFMA GEMMs (gemm.hip).  The panel QR is a sequence of
+// column steps; each step is one launch over row chunks of the panel held in
+// LDS: it finishes the reduction of the previous step's partial inner
+// products (fixed order, so results are reproducible), forms the reflector,
+// applies it to its rows, and computes the partial inner products the next
+// column needs.  Each launch boundary is the grid-wide synchronisation.
+#include <algorithm>
+
+#include "hgv_internal.h"
+
+namespace hgv {
+
+constexpr int PNB = 64;    // largest panel width supported by the column kernel
+constexpr int PCH = 128;   // panel rows per workgroup
+
+struct PanelArgs {
+    double2 *P; int ldp;   // panel, N x jb
+    int N, jb;
+    int j;                 // column being reduced (-1: only prepare column 0)
+    const double2 *part_in; double2 *part_out;   // [G][PNB] partial sums
+    const double2 *row_in; double2 *row_out;     // row j (resp. j+1) of the panel, [PNB]
+    double2 *tau;          // [jb]
+    int G;
+};
+
+// Reflector of x = (alpha, x_1..) with tail = ||x_1..||^2:  H^H x = beta e_1,
+// H = I - tau v v^H, v_0 = 1, v_i = scale x_i.
+__device__ inline void make_reflector(double2 alpha, double tail, double &beta, double2 &tau, double2 &scale) {
+    if (tail == 0.0 && alpha.y == 0.0) {
+        beta = alpha.x;
+        tau = make_double2(0.0, 0.0);
+        scale = make_double2(0.0, 0.0);
+        return;
+    }
+    double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + tail);
+    beta = -copysign(nrm, alpha.x);
+    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+}
+
+__global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
+    __shared__ double2 Ps[PCH][PNB + 1];
+    __shared__ double2 s[PNB], r0v[PNB], w[PNB];
+    __shared__ double2 vrow[PCH];
+    __shared__ double2 red[4][PNB];
+    const int tid = threadIdx.x;
+    const int g = blockIdx.x;
+    const int row0 = g * PCH;
+    const int rows = min(PCH, a.N - row0);
+    const int j = a.j;
+    const int c0 = max(j, 0);
+    const int ncol = a.jb - c0;
+
+    // load the chunk's columns c0..jb-1
+    for (int t = tid; t < PCH * ncol; t += 256) {
+        int r = t % PCH, c = c0 + t / PCH;
+        if (r < rows) Ps[r][c] = a.P[row0 + r + (size_t)c * a.ldp];
+    }
+    if (j >= 0) {
+        // finish the reduction of the partial sums for column j (same order in every block)
+        if (tid < ncol) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int q = 0; q < a.G; ++q) acc = zadd(acc, a.part_in[(size_t)q * PNB + j + tid]);
+            s[tid] = acc;
+            r0v[tid] = a.row_in[j + tid];
+        }
+    }
+    __syncthreads();
+    if (j >= 0) {
+        const double2 alpha = r0v[0];
+        const double tail = s[0].x;
+        double beta;
+        double2 tau, scale;
+        make_reflector(alpha, tail, beta, tau, scale);
+        // w_c = conj(tau) * v^H p_c,  v^H p_c = p0_c + conj(scale) (s_c - conj(alpha) p0_c)
+        if (tid < ncol && tid > 0) {
+            double2 p0 = r0v[tid];
+            double2 t1 = zsub(s[tid], zcmul(alpha, p0));
+            double2 vhp = zadd(p0, zcmul(scale, t1));
+            w[tid] = zcmul(tau, vhp);
+        }
+        if (tid < rows) {
+            int gr = row0 + tid;
+            double2 v = make_double2(0.0, 0.0);
+            if (gr == j) v = make_double2(1.0, 0.0);
+            else if (gr > j) v = zmul(scale, Ps[tid][j]);
+            vrow[tid] = v;
+        }
+        __syncthreads();
+        // apply H^H to columns j+1.., store v below the diagonal and beta on it
+        for (int t = tid; t < PCH * ncol; t += 256) {
+            int r = t % PCH, cc = t / PCH, c = j + cc;
+            int gr = row0 + r;
+            if (r >= rows || gr < j) continue;
+            if (cc == 0) {
+                Ps[r][c] = (gr == j) ? make_double2(beta, 0.0) : vrow[r];
+            } else {
+                Ps[r][c] = zsub(Ps[r][c], zmul(vrow[r], w[cc]));
+            }
+        }
+        if (g == 0 && tid == 0) a.tau[j] = tau;
+        __syncthreads();
+    }
+    // partial inner products for column jn = j+1:
+    //   part[c] = sum_{rows i >= jn} conj(P[i, jn]) P[i, c]   (c > jn)
+    //   part[jn] = sum_{rows i > jn} |P[i, jn]|^2
+    const int jn = j + 1;
+    if (jn < a.jb && jn < a.N) {
+        const int c = tid & (PNB - 1), grp = tid >> 6;
+        double2 acc = make_double2(0.0, 0.0);
+        if (c >= jn && c < a.jb) {
+            for (int r = grp * 32; r < grp * 32 + 32 && r < rows; ++r) {
+                int gr = row0 + r;
+                if (gr < jn) continue;
+                if (c == jn) {
+                    if (gr > jn) acc.x += zabs2(Ps[r][jn]);
+                } else {
+                    acc = zadd(acc, zcmul(Ps[r][jn], Ps[r][c]));
+                }
+            }
+        }
+        red[grp][c] = acc;
+        __syncthreads();
+        if (tid < PNB) {
+            double2 t = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
+            a.part_out[(size_t)g * PNB + tid] = t;
+            int lr = jn - row0;
+            if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) a.row_out[tid] = Ps[lr][tid];
+        }
+    }
+    // write back the updated columns
+    for (int t = tid; t < PCH * ncol; t += 256) {
+        int r = t % PCH, c = c0 + t / PCH;
+        if (r < rows) a.P[row0 + r + (size_t)c * a.ldp] = Ps[r][c];
+    }
+}
+
+// Explicit V (N x r): unit diagonal, zeros above, reflector entries below.
+__global__ void extract_v_kernel(int N, int r, const double2 *P, int ldp, double2 *V, int ldv) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= N || c >= r) return;
+    double2 v = (i > c) ? P[i + (size_t)c * ldp] : (i == c ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0));
+    V[i + (size_t)c * ldv] = v;
+}
+
+// T (r x r upper, ldt) from tau and G = V^H V:  T_jj = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One workgroup, column by column.
+__global__ void build_t_kernel(int r, const double2 *tau, const double2 *G, int ldg, double2 *T, int ldt) {
+    __shared__ double2 Ts[PNB][PNB + 1];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < PNB * PNB; t += blockDim.x) Ts[t % PNB][t / PNB] = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < r; ++j) {
+        double2 tj = tau[j];
+        if (tid < j) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int l = tid; l < j; ++l) acc = zadd(acc, zmul(Ts[tid][l], G[l + (size_t)j * ldg]));
+            Ts[tid][j] = zmul(make_double2(-tj.x, -tj.y), acc);
+        }
+        if (tid == 0) Ts[j][j] = tj;
+        __syncthreads();
+    }
+    for (int t = tid; t < r * r; t += blockDim.x) T[t % r + (size_t)(t / r) * ldt] = Ts[t % r][t / r];
+}
+
+__global__ void zero_kernel(double2 *p, size_t n) {
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+}
+
+static void zero_async(hgv_ctx_s *ctx, double2 *p, size_t n) {
+    if (n == 0) return;
+    int blocks = (int)std::min<size_t>(cdivz(n, 256), 8192);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, ctx->stream, p, n);
+    HGV_LAUNCH_CHECK();
+}
+
+static int num_panels(int n, int nb) { return (n - nb - 1 >= 0) ? (n - nb - 1) / nb + 1 : 0; }
+
+// Panel QR + T for panel P (N x jb, r = min(N, jb) reflectors).  Leaves V in
+// P (below the diagonal), beta on the diagonal, R above; T (r x r) in T, ldt.
+static void panel_qr(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int jb, double2 *tau, double2 *part,
+                     double2 *rowb, double2 *Vw, double2 *Gm, double2 *T, int ldt, double2 *ws, size_t wsb) {
+    const int r = std::min(N, jb);
+    const int G = cdiv(N, PCH);
+    PanelArgs a;
+    a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
+    for (int j = -1; j < r; ++j) {
+        int ib = (j + 1) & 1, ob = (j + 2) & 1;
+        a.j = j;
+        a.part_in = part + (size_t)ib * G * PNB;
+        a.part_out = part + (size_t)ob * G * PNB;
+        a.row_in = rowb + ib * PNB;
+        a.row_out = rowb + ob * PNB;
+        hipLaunchKernelGGL(panel_step_kernel, dim3(G), dim3(256), 0, ctx->stream, a);
+        HGV_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(extract_v_kernel, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
+                       Vw, N);
+    HGV_LAUNCH_CHECK();
+    ZGemm gg;  // G = V^H V
+    gg.m = r; gg.n = r; gg.k = N;
+    gg.opa = 'C'; gg.A = Vw; gg.lda = N;
+    gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
+    gg.C = Gm; gg.ldc = r;
+    zgemm(ctx, gg, ws, wsb);
+    hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    HGV_LAUNCH_CHECK();
+}
+
+void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar) {
+    if (nb > PNB) throw HipFail{hipErrorInvalidValue};
+    const int np = num_panels(n, nb);
+    const int Gmax = cdiv(std::max(n, 1), PCH);
+    size_t wsb = zgemm_splitk_bytes(n);
+    double2 *ws = ar.take<double2>(wsb / sizeof(double2));
+    double2 *part = ar.take<double2>((size_t)2 * Gmax * PNB);
+    double2 *rowb = ar.take<double2>(2 * PNB);
+    double2 *tau = ar.take<double2>(PNB);
+    double2 *Vw = ar.take<double2>((size_t)n * nb);
+    double2 *Y = ar.take<double2>((size_t)n * nb);
+    double2 *X = ar.take<double2>((size_t)n * nb);
+    double2 *Gm = ar.take<double2>((size_t)nb * nb);
+    double2 *M = ar.take<double2>((size_t)nb * nb);
+    double2 *M2 = ar.take<double2>((size_t)nb * nb);
+    if (ar.measuring() || n == 0) return;
+    zero_async(ctx, T1, (size_t)std::max(np, 1) * nb * nb);
+    for (int p = 0; p < np; ++p) {
+        const int k = p * nb;
+        const int jb = std::min(nb, n - k);
+        const int N = n - k - nb;
+        const int r = std::min(N, jb);
+        double2 *P = A + (k + nb) + (size_t)k * lda;
+        double2 *T = T1 + (size_t)p * nb * nb;
+        panel_qr(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb);
+        double2 *A22 = A + (k + nb) + (size_t)(k + nb) * lda;
+        ZGemm g;
+        // Y = V T
+        g = ZGemm();
+        g.m = N; g.n = r; g.k = r;
+        g.A = Vw; g.lda = N; g.B = T; g.ldb = nb;
+        g.C = Y; g.ldc = N;
+        zgemm(ctx, g, ws, wsb);
+        // X = A22 Y  (A22 Hermitian, lower triangle stored)
+        g = ZGemm();
+        g.m = N; g.n = r; g.k = N;
+        g.opa = 'H'; g.A = A22; g.lda = lda;
+        g.B = Y; g.ldb = N;
+        g.C = X; g.ldc = N;
+        zgemm(ctx, g, ws, wsb);
+        // M = V^H X
+        g = ZGemm();
+        g.m = r; g.n = r; g.k = N;
+        g.opa = 'C'; g.A = Vw; g.lda = N;
+        g.B = X; g.ldb = N;
+        g.C = M; g.ldc = r;
+        zgemm(ctx, g, ws, wsb);
+        // M2 = T^H M
+        g = ZGemm();
+        g.m = r; g.n = r; g.k = r;
+        g.opa = 'C'; g.A = T; g.lda = nb;
+        g.B = M; g.ldb = r;
+        g.C = M2; g.ldc = r;
+        zgemm(ctx, g, ws, wsb);
+        // W = X - 1/2 V M2  (into X)
+        g = ZGemm();
+        g.m = N; g.n = r; g.k = r;
+        g.A = Vw; g.lda = N; g.B = M2; g.ldb = r;
+        g.alpha = make_double2(-0.5, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.C = X; g.ldc = N;
+        zgemm(ctx, g, ws, wsb);
+        // A22 <- A22 - V W^H - W V^H (lower)
+        g = ZGemm();
+        g.m = N; g.n = N; g.k = r;
+        g.opa = 'N'; g.A = Vw; g.lda = N;
+        g.opb = 'C'; g.B = X; g.ldb = N;
+        g.opa2 = 'N'; g.A2 = X; g.lda2 = N;
+        g.opb2 = 'C'; g.B2 = Vw; g.ldb2 = N;
+        g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.C = A22; g.ldc = lda;
+        g.lower = 1;
+        zgemm(ctx, g, ws, wsb);
+    }
+}
+
+// Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y, last panel first.
+void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A, int lda, const double2 *T1, double2 *Y,
+                  int ldy, Arena &ar) {
+    if (nb > PNB) throw HipFail{hipErrorInvalidValue};
+    const int np = num_panels(n, nb);
+    size_t wsb = zgemm_splitk_bytes(n);
+    double2 *ws = ar.take<double2>(wsb / sizeof(double2));
+    double2 *Vw = ar.take<double2>((size_t)n * nb);
+    double2 *W1 = ar.take<double2>((size_t)nb * std::max(m, 1));
+    double2 *W2 = ar.take<double2>((size_t)nb * std::max(m, 1));
+    if (ar.measuring() || n == 0 || m == 0) return;
+    for (int p = np - 1; p >= 0; --p) {
+        const int k = p * nb;
+        const int jb = std::min(nb, n - k);
+        const int N = n - k - nb;
+        const int r = std::min(N, jb);
+        const double2 *P = A + (k + nb) + (size_t)k * lda;
+        const double2 *T = T1 + (size_t)p * nb * nb;
+        double2 *Ys = Y + (k + nb);
+        hipLaunchKernelGGL(extract_v_kernel, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P,
+                           lda, Vw, N);
+        HGV_LAUNCH_CHECK();
+        ZGemm g;  // W1 = V^H Ys
+        g.m = r; g.n = m; g.k = N;
+        g.opa = 'C'; g.A = Vw; g.lda = N;
+        g.B = Ys; g.ldb = ldy;
+        g.C = W1; g.ldc = r;
+        zgemm(ctx, g, ws, wsb);
+        g = ZGemm();  // W2 = T W1
+        g.m = r; g.n = m; g.k = r;
+        g.A = T; g.lda = nb; g.B = W1; g.ldb = r;
+        g.C = W2; g.ldc = r;
+        zgemm(ctx, g, ws, wsb);
+        g = ZGemm();  // Ys -= V W2
+        g.m = N; g.n = m; g.k = r;
+        g.A = Vw; g.lda = N; g.B = W2; g.ldb = r;
+        g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.C = Ys; g.ldc = ldy;
+        zgemm(ctx, g, ws, wsb);
+    }
+}
+
+}  // namespace hgv

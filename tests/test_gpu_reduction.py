@@ -1,0 +1,115 @@
+"""GPU checks of the two-stage tridiagonalisation (Alg. 2 step 1, Sec. 4.2) and of the
+two back-transformation steps (Alg. 2 step 3).
+
+The band matrix, the tridiagonal and the reflectors are not unique (they depend on the
+reflector convention and blocking), so these stages are checked through properties that
+hold for any correct implementation:
+  * he2hb: exact zeros outside the band, A' = Q1 Band Q1^H, Q1 unitary;
+  * hb2st: eig(T) = eig(Band), Band = Q2 T Q2^H, Q2 unitary, T real;
+  * the bulge-chasing schedule is pipelined across workgroups, yet every task's
+    arithmetic is fixed, so repeated runs are bitwise identical.
+Tolerance: a product of O(n) reflectors perturbs by O(n eps) relative; the tests use
+1e-13 * max(1, n/100) relative Frobenius error.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import rand_herm, rand_hpd, rel_fro, require_gpu, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    hgv = require_gpu()
+    return hgv.Context.get("cuda:0")
+
+
+def _tol(n):
+    return 1e-13 * max(1.0, n / 100.0)
+
+
+def band_part(M, b):
+    n = M.shape[0]
+    i, j = np.indices((n, n))
+    L = np.where((i - j >= 0) & (i - j <= b), M, 0)
+    return L + np.tril(L, -1).conj().T
+
+
+def random_band(n, b, seed):
+    A = rand_herm(n, seed)
+    B = band_part(np.tril(A), b)
+    return B
+
+
+@pytest.mark.parametrize("n,nb", [(1, 4), (2, 1), (5, 3), (40, 8), (100, 32), (129, 16), (300, 32), (513, 32),
+                                  (200, 64), (97, 1)])
+def test_he2hb_reconstruction(ctx, n, nb):
+    A = rand_herm(n, 100 + n)
+    Ab, T1 = ctx.he2hb(to_dev(np.tril(A)), nb)
+    Abn = to_np(Ab)
+    i, j = np.indices((n, n))
+    band = band_part(Abn, nb)
+    Q1 = to_np(ctx.q1(Ab, T1, to_dev(np.eye(n, dtype=complex)), nb))
+    assert rel_fro(Q1 @ band @ Q1.conj().T, A) < _tol(n)
+    assert np.linalg.norm(Q1.conj().T @ Q1 - np.eye(n)) < _tol(n) * np.sqrt(n)
+    np.testing.assert_allclose(np.linalg.eigvalsh(band), np.linalg.eigvalsh(A), atol=_tol(n) * np.abs(A).max() * n)
+
+
+@pytest.mark.parametrize("n,b", [(1, 3), (2, 1), (3, 2), (10, 3), (64, 8), (100, 32), (101, 7), (257, 16),
+                                 (300, 32), (150, 64)])
+def test_hb2st_properties(ctx, n, b):
+    band = random_band(n, b, 200 + n)
+    d, e, V2, tau2 = ctx.hb2st(to_dev(band), b)
+    d, e = to_np(d), to_np(e)
+    T = np.diag(d) + np.diag(e, -1) + np.diag(e, 1)
+    np.testing.assert_allclose(np.linalg.eigvalsh(T), np.linalg.eigvalsh(band),
+                               atol=_tol(n) * np.abs(band).max() * max(n, 1))
+    if b <= 32:
+        Q2 = to_np(ctx.q2(V2, tau2, to_dev(np.eye(n, dtype=complex)), b))
+        assert rel_fro(Q2 @ T @ Q2.conj().T, band) < _tol(n)
+        assert np.linalg.norm(Q2.conj().T @ Q2 - np.eye(n)) < _tol(n) * np.sqrt(n)
+
+
+def test_hb2st_bitwise_repeatable(ctx):
+    n, b = 700, 32
+    band = random_band(n, b, 7)
+    runs = [ctx.hb2st(to_dev(band), b) for _ in range(3)]
+    for r in runs[1:]:
+        for x, y in zip(runs[0], r):
+            assert torch_equal(x, y)
+
+
+def torch_equal(x, y):
+    import torch
+    return bool(torch.equal(x.view(torch.float64) if x.is_complex() else x,
+                            y.view(torch.float64) if y.is_complex() else y))
+
+
+@pytest.mark.parametrize("n,nb,m", [(300, 32, 7), (257, 16, 257), (64, 8, 1)])
+def test_q2_q1_on_rectangular_blocks(ctx, n, nb, m):
+    """Back-transformations applied to an n x m block equal the same columns of Q applied to I."""
+    band = random_band(n, nb, 300 + n)
+    d, e, V2, tau2 = ctx.hb2st(to_dev(band), nb)
+    rng = np.random.default_rng(n)
+    Y = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    Q2 = to_np(ctx.q2(V2, tau2, to_dev(np.eye(n, dtype=complex)), nb))
+    QY = to_np(ctx.q2(V2, tau2, to_dev(Y), nb))
+    assert rel_fro(QY, Q2 @ Y) < _tol(n)
+
+
+def test_two_stage_eigenvalues_match_oracle(ctx):
+    """he2hb + hb2st on A' = L^-1 A L^-H keeps the oracle's eigenvalues of the pencil."""
+    n, nb = 400, 32
+    A = rand_herm(n, 1)
+    B = rand_hpd(n, 2)
+    W, X, info = oracle.zhegv(A, B)
+    assert info == 0
+    L, _ = ctx.potrf(to_dev(np.tril(B)))
+    Ap = ctx.hegst(to_dev(np.tril(A)), L)
+    Ab, T1 = ctx.he2hb(Ap, nb)
+    d, e, V2, tau2 = ctx.hb2st(Ab, nb)
+    d, e = to_np(d), to_np(e)
+    T = np.diag(d) + np.diag(e, -1) + np.diag(e, 1)
+    np.testing.assert_allclose(np.linalg.eigvalsh(T), W, atol=1e-12 * np.abs(W).max())
