@@ -1,0 +1,198 @@
+"""Benchmark: generalized Hermitian-definite eigensolve on one MI355X.
+
+Workload (default): n = 10000 complex128 pencil with a constructed spectrum
+(A = L Q diag(D) Q^H L^H, B = L L^H, |D| log-uniform over [1e-3, 1e1] with random
+sign), all eigenpairs, FP64.  One step = one call of hgv_zhegvx (Cholesky, reduction to
+standard form, dense->band, bulge chasing, divide and conquer, the two back-transforms
+and the back-substitution).  Inputs are resident in HBM; each step starts from a
+device copy of the pencil (the solve destroys A and overwrites B).
+
+Prints ONE JSON line (rank 0).  Extra fields: per-stage milliseconds, the accuracy of
+the last step (residual, B-orthogonality, eigenvalue error against the constructed
+spectrum), the lower-fraction solves (10 % / 25 % of the eigenpairs), the GEMM
+roofline from HIP events recorded around every MFMA GEMM launch, and the CPU oracle
+timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix (and vector) peak
+PEAK_HBM_GBS = 8000.0
+
+
+def solve_flops(n, m):
+    """Algorithmic flops (LAPACK complex leading terms): potrf 4/3 n^3, hegst 4 n^3,
+    he2hb 16/3 n^3, Q2 8 n^2 m, Q1 8 n^2 m, back-substitution 4 n^2 m."""
+    return (4.0 / 3.0 + 4.0 + 16.0 / 3.0) * n ** 3 + 20.0 * n * n * m
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--frac", type=float, default=1.0, help="fraction of eigenpairs (lowest) in the timed step")
+    ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--fractions", type=str, default="0.1,0.25", help="extra untimed-by-contract fractions")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=2048)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported (the solver runs on one device)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1207_1773_amd as hgv
+    from inputs import constructed
+
+    dev = torch.device("cuda:0")
+    ctx = hgv.Context.get(dev)
+    n = args.n
+    m = max(1, int(math.ceil(args.frac * n)))
+
+    t0 = time.time()
+    A, B, parts = constructed(n, 2, "loguniform", device=dev, return_parts=True)
+    D_sorted = np.sort(parts["D"])
+    del parts
+    Ac0 = hgv.colmajor(A)
+    Bc0 = hgv.colmajor(B)
+    torch.cuda.synchronize()
+    t_gen = time.time() - t0
+    print("[bench] pencil n=%d generated in %.1f s" % (n, t_gen), file=sys.stderr, flush=True)
+
+    Ac = torch.empty_like(Ac0)
+    Bc = torch.empty_like(Bc0)
+
+    def step(mm, stats):
+        Ac.copy_(Ac0)
+        Bc.copy_(Bc0)
+        return ctx.zhegvx(Ac, Bc, 1, mm, "fp64", args.nb, stats=stats, inplace=True)
+
+    for i in range(args.warmup):
+        step(m, False)
+        torch.cuda.synchronize()
+        print("[bench] warmup %d done" % i, file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    stage_ms = {}
+    gemm_ms = gemm_flops = 0.0
+    gemm_launches = 0
+    t_start = time.time()
+    ev0.record()
+    last = None
+    for i in range(args.steps):
+        last = step(m, True)
+        st = last[3]
+        for k, v in st["ms"].items():
+            stage_ms[k] = stage_ms.get(k, 0.0) + v
+        gemm_ms += st["gemm_ms"]
+        gemm_flops += st["gemm_flops"]
+        gemm_launches += st["gemm_launches"]
+        print("[bench] step %d: %.1f ms" % (i, sum(st["ms"].values())), file=sys.stderr, flush=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.time() - t_start
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    W, X, info, st = last
+    flops = solve_flops(n, m)
+    tflops = flops / (ms_per_step * 1e-3) / 1e12
+
+    # accuracy of the last timed step (verification on the device with torch products)
+    Wn = W.cpu().numpy()
+    lam_err = float(np.abs(Wn - D_sorted[:m]).max() / np.abs(D_sorted).max())
+    Xs = X[:, : min(m, 2000)]
+    Ws = W[: min(m, 2000)].to(torch.complex128)
+    AX = A @ Xs
+    BX = B @ Xs
+    R = AX - BX * Ws[None, :]
+    n1 = lambda M: float(M.abs().sum(0).max())
+    res = n1(R) / (n * n1(A) * n1(Xs))
+    G = Xs.conj().T @ BX
+    orth = n1(G - torch.eye(G.shape[0], dtype=G.dtype, device=dev))
+
+    extra = {}
+    for f in [float(x) for x in args.fractions.split(",") if x]:
+        mf = max(1, int(math.ceil(f * n)))
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = step(mf, True)
+        e1.record()
+        torch.cuda.synchronize()
+        msf = e0.elapsed_time(e1)
+        extra["%d%%" % round(100 * f)] = {"m": mf, "s": msf / 1e3,
+                                          "tflops": solve_flops(n, mf) / (msf * 1e-3) / 1e12,
+                                          "stage_ms": r[3]["ms"], "info": r[2]}
+        print("[bench] fraction %.2f: %.1f ms" % (f, msf), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        An, Bn = constructed(args.cpu_n, 2, "loguniform")
+        An, Bn = An.numpy(), Bn.numpy()
+        tc = time.time()
+        _, _, cinfo = oracle.zhegv(An, Bn)
+        tcpu = time.time() - tc
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cores = min(cores, os.cpu_count() or cores)
+        cpu = {"value": solve_flops(args.cpu_n, args.cpu_n) / tcpu / 1e12, "unit": "TFLOP/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "oracle full solve (all pairs) of the same pencil recipe at n=%d: %.2f s (info %d); "
+                         "n^3-scaled estimate for n=%d: %.0f s" % (args.cpu_n, tcpu, cinfo, n,
+                                                                    tcpu * (n / args.cpu_n) ** 3)}
+
+    stage_avg = {k: v / args.steps for k, v in stage_ms.items() if v > 0}
+    gemm_avg_ms = gemm_ms / max(gemm_launches, 1)
+    achieved = (gemm_flops / (gemm_ms * 1e-3) / 1e12) if gemm_ms > 0 else None
+    out = {
+        "metric": "generalized eigensolve s & TFLOP/s, n=10k c128; FP64 vs mixed at equal residual",
+        "value": tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "constructed-spectrum pencil, |D| log-uniform [1e-3,1e1], n=%d, lowest %d "
+                               "eigenpairs (%.0f%%), FP64, nb=%s" % (n, m, 100.0 * m / n,
+                                                                   st["nb"] if st else args.nb),
+                   "n": n, "m": m, "precision": "fp64"},
+        "seconds_per_solve": ms_per_step / 1e3,
+        "stage_ms": stage_avg,
+        "accuracy": {"residual": res, "orthogonality": orth, "orth_over_n": orth / n,
+                     "max_rel_eig_err_vs_constructed": lam_err, "info": info,
+                     "checked_columns": int(Xs.shape[1])},
+        "fractions": extra,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
+                     "kernel": "gemm_kernel<complex double, 64x64> (all MFMA GEMM launches of a step)",
+                     "launches_per_step": gemm_launches / args.steps,
+                     "avg_launch_ms": gemm_avg_ms,
+                     "gemm_share_of_step": (gemm_ms / args.steps) / ms_per_step},
+        "cpu_baseline": cpu,
+        "wall_s_timed": wall,
+        "input_generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -307,33 +307,48 @@ void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double 
 }
 
 // ---- Q2 back-transformation ------------------------------------------------------------------
-// T of every diamond group (B, j): reflector t (sweep s0 + t) occupies local
-// rows t .. t+b-1 of the group; G[t1][t2] = sum_rows conj(V[row][t1]) V[row][t2],
-// T_tt = tau_t, T[0:t, t] = -tau_t T[0:t, 0:t] G[0:t, t].
-template <int BM>
-__global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int J, const double2 *V2, const double2 *tau2,
-                                                         double2 *T2) {
-    __shared__ double2 Vs[BM][BM + 1];
-    __shared__ double2 Gs[BM][BM + 1];
-    __shared__ double2 Ts[BM][BM + 1];
+// Groups hold g <= b consecutive sweeps at one step j (any g <= b keeps every
+// pair of overlapping reflectors in order).  Reflector t of group (B, j) is
+// H_{B*g + t, j}; it occupies local rows t .. t+b-1 of the group, whose first
+// row is B*g + 1 + j*b.
+__device__ inline const double2 *v2_ptr(const double2 *V2, int b, int J, int s, int j) {
+    return V2 + (((size_t)(s / b) * J + j) * b + (s % b)) * b;
+}
+__device__ inline size_t tau2_idx(int b, int J, int s, int j) { return ((size_t)(s / b) * J + j) * b + (s % b); }
+
+// T of every group: G[t1][t2] = sum_rows conj(V[row][t1]) V[row][t2] over the
+// overlap rows [t2, t1+b-1]; T_tt = tau_t, T[0:t, t] = -tau_t T[0:t, 0:t] G[0:t, t].
+template <int BMAX, int GMAX>
+__global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int J, const double2 *V2,
+                                                         const double2 *tau2, double2 *T2) {
+    __shared__ double2 Vs[GMAX][BMAX + 1];
+    __shared__ double2 Gs[GMAX][GMAX + 1];
+    __shared__ double2 Ts[GMAX][GMAX + 1];
+    __shared__ double2 taus[GMAX];
     const int grp = blockIdx.x;                 // B * J + j
+    const int B = grp / J, j = grp % J;
     const int tid = threadIdx.x;
-    const double2 *vg = V2 + (size_t)grp * b * b;
-    const double2 *tg = tau2 + (size_t)grp * b;
-    for (int t = tid; t < b * b; t += 256) Vs[t / b][t % b] = vg[t];   // Vs[reflector][entry]
-    for (int t = tid; t < BM * BM; t += 256) Ts[t / BM][t % BM] = make_double2(0.0, 0.0);
+    for (int t = tid; t < g * b; t += 256) {
+        int tt = t / b, i = t % b;
+        int s = B * g + tt;
+        Vs[tt][i] = (s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : make_double2(0.0, 0.0);
+    }
+    if (tid < g) {
+        int s = B * g + tid;
+        taus[tid] = (s <= n - 2) ? tau2[tau2_idx(b, J, s, j)] : make_double2(0.0, 0.0);
+    }
+    for (int t = tid; t < GMAX * GMAX; t += 256) Ts[t / GMAX][t % GMAX] = make_double2(0.0, 0.0);
     __syncthreads();
-    // Gram entries for t1 < t2: rows rho in [t2, t1+b-1]
-    for (int t = tid; t < b * b; t += 256) {
-        int t1 = t % b, t2 = t / b;
+    for (int t = tid; t < g * g; t += 256) {
+        int t1 = t % g, t2 = t / g;
         if (t1 >= t2) continue;
         double2 acc = make_double2(0.0, 0.0);
         for (int rho = t2; rho <= t1 + b - 1; ++rho) acc = zadd(acc, zcmul(Vs[t1][rho - t1], Vs[t2][rho - t2]));
         Gs[t1][t2] = acc;
     }
     __syncthreads();
-    for (int c = 0; c < b; ++c) {
-        double2 tc = tg[c];
+    for (int c = 0; c < g; ++c) {
+        double2 tc = taus[c];
         if (tid < c) {
             double2 acc = make_double2(0.0, 0.0);
             for (int l = tid; l < c; ++l) acc = zadd(acc, zmul(Ts[tid][l], Gs[l][c]));
@@ -342,70 +357,70 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int J, con
         if (tid == 0) Ts[c][c] = tc;
         __syncthreads();
     }
-    double2 *tout = T2 + (size_t)grp * b * b;
-    for (int t = tid; t < b * b; t += 256) tout[t] = Ts[t % b][t / b];   // column-major b x b
+    double2 *tout = T2 + (size_t)grp * g * g;
+    for (int t = tid; t < g * g; t += 256) tout[t] = Ts[t % g][t / g];   // column-major g x g
 }
 
-// Y (n x m) <- Q2 Y; workgroup = NC columns; groups walked from the last block
-// of sweeps to the first, j ascending inside a block.
-template <int BM, int NC>
-__global__ __launch_bounds__(256) void q2_apply_kernel(int n, int m, int b, int J, int nblk, const double2 *V2,
-                                                        const double2 *T2, double2 *Y, int ldy) {
-    __shared__ double2 Vs[BM][BM + 1];          // Vs[t][i] = entry i of reflector t
-    __shared__ double2 Ts[BM][BM + 1];
-    __shared__ double2 Ys[2 * BM][NC + 1];
-    __shared__ double2 Ws[BM][NC + 1];
+// Y (n x m) <- Q2 Y; workgroup = NC columns; groups walked from the last group
+// of sweeps to the first, j ascending inside a group of sweeps.
+template <int BMAX, int GMAX, int NC>
+__global__ __launch_bounds__(256) void q2_apply_kernel(int n, int m, int b, int g, int J, int ngrp,
+                                                        const double2 *V2, const double2 *T2, double2 *Y, int ldy) {
+    __shared__ double2 Vs[GMAX][BMAX + 1];     // Vs[t][i] = entry i of reflector t
+    __shared__ double2 Ts[GMAX][GMAX + 1];
+    __shared__ double2 Ys[GMAX + BMAX][NC + 1];
+    __shared__ double2 Ws[GMAX][NC + 1];
     const int tid = threadIdx.x;
     const int c0 = blockIdx.x * NC;
     const int nc = min(NC, m - c0);
-    for (int B = nblk - 1; B >= 0; --B) {
+    for (int B = ngrp - 1; B >= 0; --B) {
         for (int j = 0; j < J; ++j) {
-            const int R0 = B * b + 1 + j * b;
+            const int R0 = B * g + 1 + j * b;
             if (R0 > n - 1) break;
-            const int nrows = min(2 * b - 1, n - R0);
-            const int grp = B * J + j;
-            const double2 *vg = V2 + (size_t)grp * b * b;
-            const double2 *tg = T2 + (size_t)grp * b * b;
+            const int nrows = min(g + b - 1, n - R0);
+            const double2 *tg = T2 + ((size_t)B * J + j) * g * g;
             __syncthreads();
-            for (int t = tid; t < b * b; t += 256) {
-                Vs[t / b][t % b] = vg[t];
-                Ts[t % b][t / b] = tg[t];
+            for (int t = tid; t < g * b; t += 256) {
+                int tt = t / b, i = t % b;
+                int s = B * g + tt;
+                Vs[tt][i] = (s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : make_double2(0.0, 0.0);
             }
+            for (int t = tid; t < g * g; t += 256) Ts[t % g][t / g] = tg[t];
             for (int t = tid; t < nrows * NC; t += 256) {
                 int r = t % nrows, c = t / nrows;
                 Ys[r][c] = (c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : make_double2(0.0, 0.0);
             }
             __syncthreads();
             // W = V^H Y_rows
-            for (int t = tid; t < b * NC; t += 256) {
+            for (int t = tid; t < g * NC; t += 256) {
                 int c = t % NC, tt = t / NC;
                 double2 acc = make_double2(0.0, 0.0);
                 for (int i = 0; i < b && tt + i < nrows; ++i) acc = zadd(acc, zcmul(Vs[tt][i], Ys[tt + i][c]));
                 Ws[tt][c] = acc;
             }
             __syncthreads();
-            // W <- T W   (T upper triangular); computed into registers, then stored
-            double2 tw[(BM * NC + 255) / 256];
+            // W <- T W   (T upper triangular)
+            double2 tw[(GMAX * NC + 255) / 256];
             {
                 int q = 0;
-                for (int t = tid; t < b * NC; t += 256, ++q) {
+                for (int t = tid; t < g * NC; t += 256, ++q) {
                     int c = t % NC, tt = t / NC;
                     double2 acc = make_double2(0.0, 0.0);
-                    for (int l = tt; l < b; ++l) acc = zadd(acc, zmul(Ts[tt][l], Ws[l][c]));
+                    for (int l = tt; l < g; ++l) acc = zadd(acc, zmul(Ts[tt][l], Ws[l][c]));
                     tw[q] = acc;
                 }
             }
             __syncthreads();
             {
                 int q = 0;
-                for (int t = tid; t < b * NC; t += 256, ++q) Ws[t / NC][t % NC] = tw[q];
+                for (int t = tid; t < g * NC; t += 256, ++q) Ws[t / NC][t % NC] = tw[q];
             }
             __syncthreads();
             // Y_rows -= V W
             for (int t = tid; t < nrows * NC; t += 256) {
                 int c = t % NC, r = t / NC;
                 double2 acc = Ys[r][c];
-                int tlo = max(0, r - b + 1), thi = min(r, b - 1);
+                int tlo = max(0, r - b + 1), thi = min(r, g - 1);
                 for (int tt = tlo; tt <= thi; ++tt) acc = zsub(acc, zmul(Vs[tt][r - tt], Ws[tt][c]));
                 if (c < nc) Y[R0 + r + (size_t)(c0 + c) * ldy] = acc;
             }
@@ -413,18 +428,30 @@ __global__ __launch_bounds__(256) void q2_apply_kernel(int n, int m, int b, int 
     }
 }
 
+static int q2_group(int b) { return std::min(b, 32); }
+
 void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2, double2 *Y,
                   int ldy, Arena &ar) {
-    if (nb > 32) throw HipFail{hipErrorInvalidValue};
-    const int b = nb;
-    const int J = hb_J(n, b), nblk = hb_nblk(n, b);
-    double2 *T2 = ar.take<double2>(std::max<size_t>((size_t)nblk * J * b * b, 1));
+    if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    const int b = nb, g = q2_group(b);
+    const int J = hb_J(n, b), ngrp = n >= 2 ? cdiv(n - 1, g) : 0;
+    double2 *T2 = ar.take<double2>(std::max<size_t>((size_t)ngrp * J * g * g, 1));
     if (ar.measuring() || n < 2 || m == 0) return;
-    hipLaunchKernelGGL((q2_tbuild_kernel<32>), dim3(nblk * J), dim3(256), 0, ctx->stream, n, b, J, V2, tau2, T2);
-    HGV_LAUNCH_CHECK();
-    constexpr int NC = 64;
-    hipLaunchKernelGGL((q2_apply_kernel<32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, J, nblk, V2,
-                       T2, Y, ldy);
+    if (b <= 32) {
+        hipLaunchKernelGGL((q2_tbuild_kernel<32, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
+                           tau2, T2);
+        HGV_LAUNCH_CHECK();
+        constexpr int NC = 64;
+        hipLaunchKernelGGL((q2_apply_kernel<32, 32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, g,
+                           J, ngrp, V2, T2, Y, ldy);
+    } else {
+        hipLaunchKernelGGL((q2_tbuild_kernel<64, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
+                           tau2, T2);
+        HGV_LAUNCH_CHECK();
+        constexpr int NC = 32;
+        hipLaunchKernelGGL((q2_apply_kernel<64, 32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, g,
+                           J, ngrp, V2, T2, Y, ldy);
+    }
     HGV_LAUNCH_CHECK();
 }
 

@@ -1,0 +1,560 @@
+// stedc.hip -- divide-and-conquer eigensolver for the real symmetric
+// tridiagonal T (Alg. 2 step 2, Sec. 4.3), entirely on the device.
+//
+// Split: T is torn into leaves of S rows; at a boundary with coupling e
+// (rows q-1, q) T = diag(T1, T2) + rho v v^T with rho = |e| and
+// v = e_{q-1} + sign(e) e_q, so |e| is subtracted from d_{q-1} and d_q.
+// Leaves: implicit QL with shifts, one workgroup per leaf (lane r keeps row r
+// of the leaf's eigenvector matrix; lane 0 runs the scalar chase and
+// publishes the rotations).
+// Merge (the displayed identity of Sec. 4.3): with Z1, Z2 the children's
+// eigenvectors, T = diag(Z1, Z2) (diag(L1, L2) + rho u u^T) diag(Z1, Z2)^T,
+// u = [last row of Z1, sign(e) * first row of Z2]; the rank-one problem
+// D + rho u u^T = Q L Q^T is solved here and Z = diag(Z1, Z2) Q is one GEMM
+// per child (gemm.hip).  For the rank-one problem:
+//   * the two sorted child spectra are merged (ranks by binary search);
+//   * deflation: an entry with rho |u_i| <= tol is already an eigenpair;
+//     two close entries are rotated so that one component of u vanishes and
+//     that entry deflates (the rotation is kept and later applied to Q);
+//   * each remaining root lies in (d_j, d_{j+1}) (the last in
+//     (d_k, d_k + rho |u|^2)); it is found by bisection on
+//     f(t) = 1 + rho sum u_i^2 / (delta_i - t) with t measured from the
+//     nearer pole (delta_i = d_i - d_origin exact), so t keeps full relative
+//     accuracy;
+//   * the vector u is recomputed from the computed roots (Gu & Eisenstat,
+//     SIAM J. Matrix Anal. Appl. 16 (1995)):
+//       u_i^2 = prod_j (l_j - d_i) / (rho prod_{j != i} (d_j - d_i)),
+//     which makes the eigenvectors q_j = (u_i / (d_i - l_j))_i / norm
+//     numerically orthogonal;
+//   * the eigenvalues (roots and deflated entries) are sorted and the columns
+//     of Q built in that order; only the wanted columns are built and
+//     multiplied in the last merge.
+#include <algorithm>
+#include <cfloat>
+
+#include "hgv_internal.h"
+
+namespace hgv {
+
+constexpr int DC_LEAF = 32;
+
+struct MergeGeom {
+    int a, n1, n2, k;
+};
+
+__host__ __device__ inline MergeGeom merge_geom(int n, int L, int p) {
+    MergeGeom g;
+    g.a = p * 2 * L;
+    g.n1 = min(L, n - g.a);
+    g.n2 = max(0, min(L, n - g.a - g.n1));
+    g.k = g.n1 + g.n2;
+    return g;
+}
+
+struct DcArgs {
+    int n, L, P;
+    const double *e;
+    double *D;
+    const double *Zc;
+    int ldz;
+    double *ds, *zs;
+    int *perm;
+    double *dK, *zK;
+    int *Kpos, *Dpos;
+    int *kcnt, *nrot;
+    double *rhop;
+    int *rot_p, *rot_i;
+    double *rot_c, *rot_s;
+    int *org;
+    double *tau, *zh, *ival;
+    int *colitem;
+    double *Q;
+    int c_lo, c_hi;   // columns built at this level (last level: wanted range)
+};
+
+__host__ __device__ inline size_t qoff(int L, int p) { return (size_t)p * 4 * (size_t)L * L; }
+
+// ---- leaves -------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void dc_leaf_kernel(int n, int S, const double *d, const double *e, double *D,
+                                                     double *Z, int ldz, int *info) {
+    __shared__ double dl[64], el[64];
+    __shared__ double zr[64][65];
+    __shared__ double rc[64], rs[64];
+    __shared__ int rj[64];
+    __shared__ int ctl_nrot, ctl_done;
+    const int lane = threadIdx.x;
+    const int a = blockIdx.x * S;
+    const int sz = min(S, n - a);
+    if (lane < sz) {
+        double dv = d[a + lane];
+        if (lane == 0 && a > 0) dv -= fabs(e[a - 1]);
+        if (lane == sz - 1 && a + sz < n) dv -= fabs(e[a + sz - 1]);
+        dl[lane] = dv;
+        el[lane] = (lane < sz - 1) ? e[a + lane] : 0.0;
+    }
+    for (int c = 0; c < sz; ++c) zr[lane][c] = (lane == c) ? 1.0 : 0.0;
+    int l = 0, steps = 0;   // lane 0's QL state
+    __syncthreads();
+    for (;;) {
+        if (lane == 0) {
+            int done = 0, nr = 0;
+            for (;;) {
+                if (l >= sz) { done = 1; break; }
+                int m = l;
+                while (m < sz - 1 && fabs(el[m]) > DBL_EPSILON * (fabs(dl[m]) + fabs(dl[m + 1]))) ++m;
+                if (m == l) { ++l; steps = 0; continue; }
+                if (steps++ >= 30) {
+                    if (info && *info == 0) *info = a + l + 1;
+                    done = 1;
+                    break;
+                }
+                // shift: eigenvalue of [d_l e_l; e_l d_{l+1}] nearest d_l
+                double del = 0.5 * (dl[l + 1] - dl[l]);
+                double rt = hypot(del, el[l]);
+                double sigma = dl[l] - el[l] * el[l] / (del + (del >= 0.0 ? rt : -rt));
+                double bulge = 0.0;
+                for (int jj = m - 1; jj >= l; --jj) {
+                    double x, y;
+                    if (jj == m - 1) { x = dl[m] - sigma; y = el[m - 1]; }
+                    else { x = el[jj + 1]; y = bulge; }
+                    double r = hypot(x, y);
+                    double c = (r == 0.0) ? 1.0 : x / r, s = (r == 0.0) ? 0.0 : y / r;
+                    if (jj != m - 1) el[jj + 1] = r;
+                    double a0 = dl[jj], b0 = el[jj], d0 = dl[jj + 1];
+                    dl[jj] = c * c * a0 - 2.0 * c * s * b0 + s * s * d0;
+                    dl[jj + 1] = s * s * a0 + 2.0 * c * s * b0 + c * c * d0;
+                    el[jj] = c * s * (a0 - d0) + (c * c - s * s) * b0;
+                    if (jj > l) {
+                        bulge = s * el[jj - 1];
+                        el[jj - 1] = c * el[jj - 1];
+                    }
+                    rj[nr] = jj; rc[nr] = c; rs[nr] = s;
+                    ++nr;
+                }
+                break;
+            }
+            ctl_nrot = nr;
+            ctl_done = done;
+        }
+        __syncthreads();
+        const int nr = ctl_nrot;
+        // apply this step's rotations to my row:  Z <- Z G^T
+        if (lane < sz) {
+            for (int t = 0; t < nr; ++t) {
+                int jj = rj[t];
+                double c = rc[t], s = rs[t];
+                double zj = zr[lane][jj], zj1 = zr[lane][jj + 1];
+                zr[lane][jj] = c * zj - s * zj1;
+                zr[lane][jj + 1] = s * zj + c * zj1;
+            }
+        }
+        bool stop = ctl_done != 0;
+        __syncthreads();
+        if (stop) break;
+    }
+    // sort ascending (rank by counting, ties by index) and write D, Z
+    __shared__ int rank[64];
+    if (lane < sz) {
+        double v = dl[lane];
+        int r = 0;
+        for (int j = 0; j < sz; ++j) r += (dl[j] < v || (dl[j] == v && j < lane)) ? 1 : 0;
+        rank[lane] = r;
+        D[a + r] = v;
+    }
+    __syncthreads();
+    if (lane < sz)
+        for (int c = 0; c < sz; ++c) Z[(a + lane) + (size_t)(a + rank[c]) * ldz] = zr[lane][c];
+}
+
+// ---- merge steps ------------------------------------------------------------------------------
+// M1: u (normalised later) and the merged order of the two sorted child spectra.
+__global__ void dc_m1_kernel(DcArgs A) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= A.n) return;
+    int p = g / (2 * A.L);
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    int x = g - m.a;
+    double lam = A.D[g];
+    double sig = (A.e[m.a + m.n1 - 1] >= 0.0) ? 1.0 : -1.0;
+    double z = (x < m.n1) ? A.Zc[(m.a + m.n1 - 1) + (size_t)g * A.ldz] : sig * A.Zc[(m.a + m.n1) + (size_t)g * A.ldz];
+    int rank;
+    if (x < m.n1) {   // count right entries strictly below lam
+        const double *R = A.D + m.a + m.n1;
+        int lo = 0, hi = m.n2;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (R[mid] < lam) lo = mid + 1; else hi = mid; }
+        rank = x + lo;
+    } else {          // count left entries <= lam
+        const double *Lf = A.D + m.a;
+        int lo = 0, hi = m.n1;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (Lf[mid] <= lam) lo = mid + 1; else hi = mid; }
+        rank = (x - m.n1) + lo;
+    }
+    A.ds[m.a + rank] = lam;
+    A.zs[m.a + rank] = z;
+    A.perm[m.a + rank] = x;
+}
+
+// M2: normalise u, deflation scan (serial per merge, in sorted order).
+__global__ void dc_m2_kernel(DcArgs A) {
+    int p = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    double *ds = A.ds + m.a, *zs = A.zs + m.a;
+    double nz2 = 0.0, dmax = 0.0;
+    for (int i = 0; i < m.k; ++i) {
+        nz2 += zs[i] * zs[i];
+        dmax = fmax(dmax, fabs(ds[i]));
+    }
+    double rho = fabs(A.e[m.a + m.n1 - 1]);
+    double rhop = rho * nz2;
+    double inv = nz2 > 0.0 ? 1.0 / sqrt(nz2) : 0.0;
+    for (int i = 0; i < m.k; ++i) zs[i] *= inv;
+    double tol = 8.0 * DBL_EPSILON * fmax(dmax, rhop);
+    int kk = 0, nd = 0, nr = 0, prev = -1;
+    for (int i = 0; i < m.k; ++i) {
+        if (rhop * fabs(zs[i]) <= tol) {
+            A.Dpos[m.a + nd++] = i;
+            continue;
+        }
+        if (prev < 0) { prev = i; continue; }
+        double s = zs[prev], c = zs[i];
+        double r = hypot(c, s);
+        c /= r;
+        s /= r;
+        double t = ds[i] - ds[prev];
+        if (fabs(t * c * s) <= tol) {
+            zs[i] = r;
+            zs[prev] = 0.0;
+            double dp = ds[prev] * c * c + ds[i] * s * s;
+            ds[i] = ds[prev] * s * s + ds[i] * c * c;
+            ds[prev] = dp;
+            A.rot_p[m.a + nr] = prev;
+            A.rot_i[m.a + nr] = i;
+            A.rot_c[m.a + nr] = c;
+            A.rot_s[m.a + nr] = s;
+            ++nr;
+            A.Dpos[m.a + nd++] = prev;
+            prev = i;
+        } else {
+            A.Kpos[m.a + kk] = prev;
+            A.dK[m.a + kk] = ds[prev];
+            A.zK[m.a + kk] = zs[prev];
+            ++kk;
+            prev = i;
+        }
+    }
+    if (prev >= 0) {
+        A.Kpos[m.a + kk] = prev;
+        A.dK[m.a + kk] = ds[prev];
+        A.zK[m.a + kk] = zs[prev];
+        ++kk;
+    }
+    A.kcnt[p] = kk;
+    A.nrot[p] = nr;
+    A.rhop[p] = rhop;
+}
+
+// M3: secular roots by bisection in the shifted variable.
+__global__ void dc_m3_kernel(DcArgs A) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= A.n) return;
+    int p = g / (2 * A.L);
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    int j = g - m.a;
+    int kp = A.kcnt[p];
+    if (j >= kp) return;
+    const double *dK = A.dK + m.a, *zK = A.zK + m.a;
+    double rho = A.rhop[p];
+    int org;
+    double lo, hi;
+    if (j < kp - 1) {
+        double mid = 0.5 * (dK[j + 1] - dK[j]);
+        double f = 1.0;
+        for (int i = 0; i < kp; ++i) f += rho * zK[i] * zK[i] / ((dK[i] - dK[j]) - mid);
+        if (f >= 0.0) { org = j; lo = 0.0; hi = mid; }
+        else { org = j + 1; lo = -mid; hi = 0.0; }
+    } else {
+        double s2 = 0.0;
+        for (int i = 0; i < kp; ++i) s2 += zK[i] * zK[i];
+        org = j; lo = 0.0; hi = rho * s2;
+    }
+    const double dorg = dK[org];
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double f = 1.0;
+        for (int i = 0; i < kp; ++i) f += rho * zK[i] * zK[i] / ((dK[i] - dorg) - mid);
+        if (f < 0.0) lo = mid;
+        else hi = mid;
+    }
+    A.org[m.a + j] = org;
+    A.tau[m.a + j] = 0.5 * (lo + hi);
+}
+
+// M4: Gu-Eisenstat recomputation of u from the computed roots.
+__global__ void dc_m4_kernel(DcArgs A) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= A.n) return;
+    int p = g / (2 * A.L);
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    int i = g - m.a;
+    int kp = A.kcnt[p];
+    if (i >= kp) return;
+    const double *dK = A.dK + m.a;
+    const int *org = A.org + m.a;
+    const double *tau = A.tau + m.a;
+    double di = dK[i];
+    double prod = ((dK[org[i]] - di) + tau[i]) / A.rhop[p];
+    for (int j = 0; j < kp; ++j) {
+        if (j == i) continue;
+        prod *= ((dK[org[j]] - di) + tau[j]) / (dK[j] - di);
+    }
+    A.zh[m.a + i] = copysign(sqrt(fabs(prod)), A.zK[m.a + i]);
+}
+
+// M5: eigenvalue of every item (roots first, then deflated entries).
+__global__ void dc_m5_kernel(DcArgs A) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= A.n) return;
+    int p = g / (2 * A.L);
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    int x = g - m.a;
+    int kp = A.kcnt[p];
+    double v = (x < kp) ? A.dK[m.a + A.org[m.a + x]] + A.tau[m.a + x] : A.ds[m.a + A.Dpos[m.a + x - kp]];
+    A.ival[m.a + x] = v;
+}
+
+// M6: sort the items (rank by counting, ties by item index); new spectrum into D.
+__global__ void dc_m6_kernel(DcArgs A) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= A.n) return;
+    int p = g / (2 * A.L);
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0) return;
+    int x = g - m.a;
+    const double *iv = A.ival + m.a;
+    double v = iv[x];
+    int r = 0;
+    for (int y = 0; y < m.k; ++y) r += (iv[y] < v || (iv[y] == v && y < x)) ? 1 : 0;
+    A.D[m.a + r] = v;
+    A.colitem[m.a + r] = x;
+}
+
+// M7: column `col` of Q (rows in the children's order).  The column is built
+// in the sorted basis (in LDS when it fits), the deflation rotations are
+// applied in reverse order, then rows are scattered through perm.
+template <int KCAP>
+__global__ __launch_bounds__(256) void dc_m7_kernel(DcArgs A, int p_fixed) {
+    __shared__ double col_s[KCAP > 0 ? KCAP : 1];
+    __shared__ double red[256];
+    int p, col;
+    if (p_fixed >= 0) {
+        p = p_fixed;
+        col = A.c_lo + blockIdx.x;
+    } else {
+        int g = blockIdx.x;
+        p = g / (2 * A.L);
+        col = g - p * 2 * A.L;
+    }
+    MergeGeom m = merge_geom(A.n, A.L, p);
+    if (m.n2 <= 0 || col >= m.k) return;
+    const int tid = threadIdx.x;
+    const int kp = A.kcnt[p];
+    const int x = A.colitem[m.a + col];
+    double *Qc = A.Q + qoff(A.L, p) + (size_t)(col - (p_fixed >= 0 ? A.c_lo : 0)) * m.k;
+    const int *perm = A.perm + m.a;
+    // sorted-basis column: KCAP > 0 -> LDS; else written straight to permuted rows
+    double inv = 1.0;
+    double dorg = 0.0, tx = 0.0;
+    if (x < kp) {
+        dorg = A.dK[m.a + A.org[m.a + x]];
+        tx = A.tau[m.a + x];
+        double ss = 0.0;
+        for (int i = tid; i < kp; i += 256) {
+            double v = A.zh[m.a + i] / ((A.dK[m.a + i] - dorg) - tx);
+            ss += v * v;
+        }
+        red[tid] = ss;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        inv = 1.0 / sqrt(red[0]);
+    }
+    if (KCAP > 0) {
+        for (int i = tid; i < m.k; i += 256) col_s[i] = 0.0;
+        __syncthreads();
+        if (x < kp) {
+            for (int i = tid; i < kp; i += 256)
+                col_s[A.Kpos[m.a + i]] = inv * A.zh[m.a + i] / ((A.dK[m.a + i] - dorg) - tx);
+        } else if (tid == 0) {
+            col_s[A.Dpos[m.a + x - kp]] = 1.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int t = A.nrot[p] - 1; t >= 0; --t) {
+                int pr = A.rot_p[m.a + t], ir = A.rot_i[m.a + t];
+                double c = A.rot_c[m.a + t], s = A.rot_s[m.a + t];
+                double qp = col_s[pr], qi = col_s[ir];
+                col_s[pr] = c * qp + s * qi;
+                col_s[ir] = -s * qp + c * qi;
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < m.k; i += 256) Qc[perm[i]] = col_s[i];
+    } else {
+        for (int i = tid; i < m.k; i += 256) Qc[i] = 0.0;
+        __syncthreads();
+        if (x < kp) {
+            for (int i = tid; i < kp; i += 256)
+                Qc[perm[A.Kpos[m.a + i]]] = inv * A.zh[m.a + i] / ((A.dK[m.a + i] - dorg) - tx);
+        } else if (tid == 0) {
+            Qc[perm[A.Dpos[m.a + x - kp]]] = 1.0;
+        }
+        __threadfence_block();
+        __syncthreads();
+        if (tid == 0) {
+            for (int t = A.nrot[p] - 1; t >= 0; --t) {
+                int pr = perm[A.rot_p[m.a + t]], ir = perm[A.rot_i[m.a + t]];
+                double c = A.rot_c[m.a + t], s = A.rot_s[m.a + t];
+                double qp = Qc[pr], qi = Qc[ir];
+                Qc[pr] = c * qp + s * qi;
+                Qc[ir] = -s * qp + c * qi;
+            }
+        }
+    }
+}
+
+__global__ void dcopy2d_kernel(int m, int n, const double *A, int lda, double *B, int ldb) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < m && j < n) B[i + (size_t)j * ldb] = A[i + (size_t)j * lda];
+}
+
+__global__ void dcopy_kernel(int n, const double *a, double *b) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+static void dcopy2d(hgv_ctx_s *ctx, int m, int n, const double *A, int lda, double *B, int ldb) {
+    if (m <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(dcopy2d_kernel, dim3(cdiv(m, 64), cdiv(n, 4)), dim3(256), 0, ctx->stream, m, n, A, lda, B, ldb);
+    HGV_LAUNCH_CHECK();
+}
+
+void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu, double *lambda, double *Z,
+               int ldz, Arena &ar, int *d_info) {
+    const int S = DC_LEAF;
+    const int m = iu - il + 1;
+    // Q buffer: the largest level's sum of k^2 with offsets p * 4 L^2
+    size_t qmax = 1;
+    for (int L = S; L < n; L *= 2) {
+        int P = cdiv(n, 2 * L);
+        MergeGeom last = merge_geom(n, L, P - 1);
+        size_t need = (P - 1 > 0 ? qoff(L, P - 1) : 0) + (size_t)last.k * last.k;
+        qmax = std::max(qmax, need);
+    }
+    double *Za = ar.take<double>((size_t)n * n);
+    double *Zb = ar.take<double>((size_t)n * n);
+    double *Qb = ar.take<double>(qmax);
+    double *D = ar.take<double>(n);
+    double *ds = ar.take<double>(n), *zs = ar.take<double>(n);
+    int *perm = ar.take<int>(n);
+    double *dK = ar.take<double>(n), *zK = ar.take<double>(n);
+    int *Kpos = ar.take<int>(n), *Dpos = ar.take<int>(n);
+    int np = cdiv(std::max(n, 1), 2 * S) + 1;
+    int *kcnt = ar.take<int>(np), *nrot = ar.take<int>(np);
+    double *rhop = ar.take<double>(np);
+    int *rot_p = ar.take<int>(n), *rot_i = ar.take<int>(n);
+    double *rot_c = ar.take<double>(n), *rot_s = ar.take<double>(n);
+    int *org = ar.take<int>(n);
+    double *tau = ar.take<double>(n), *zh = ar.take<double>(n), *ival = ar.take<double>(n);
+    int *colitem = ar.take<int>(n);
+    if (ar.measuring() || n == 0) return;
+
+    const int nleaf = cdiv(n, S);
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nleaf), dim3(64), 0, ctx->stream, n, S, d, e, D, Za, n, d_info);
+    HGV_LAUNCH_CHECK();
+    double *Zc = Za, *Zn = Zb;
+    if (n <= S) {
+        dcopy2d(ctx, n, m, Zc + (size_t)(il - 1) * n, n, Z, ldz);
+        hipLaunchKernelGGL(dcopy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, D, lambda);
+        HGV_LAUNCH_CHECK();
+        return;
+    }
+    for (int L = S; L < n; L *= 2) {
+        const int P = cdiv(n, 2 * L);
+        const bool last = (2 * L >= n);
+        DcArgs A;
+        A.n = n; A.L = L; A.P = P; A.e = e; A.D = D; A.Zc = Zc; A.ldz = n;
+        A.ds = ds; A.zs = zs; A.perm = perm; A.dK = dK; A.zK = zK; A.Kpos = Kpos; A.Dpos = Dpos;
+        A.kcnt = kcnt; A.nrot = nrot; A.rhop = rhop;
+        A.rot_p = rot_p; A.rot_i = rot_i; A.rot_c = rot_c; A.rot_s = rot_s;
+        A.org = org; A.tau = tau; A.zh = zh; A.ival = ival; A.colitem = colitem; A.Q = Qb;
+        A.c_lo = last ? il - 1 : 0;
+        A.c_hi = last ? iu : 2 * L;
+        dim3 gN(cdiv(n, 256));
+        hipLaunchKernelGGL(dc_m1_kernel, gN, dim3(256), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dc_m2_kernel, dim3(P), dim3(64), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dc_m3_kernel, gN, dim3(256), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dc_m4_kernel, gN, dim3(256), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dc_m5_kernel, gN, dim3(256), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(dc_m6_kernel, gN, dim3(256), 0, ctx->stream, A);
+        HGV_LAUNCH_CHECK();
+        const int kmax = std::min(2 * L, n);
+        if (last) {
+            int ncols = m;
+            if (kmax <= 1024)
+                hipLaunchKernelGGL((dc_m7_kernel<1024>), dim3(ncols), dim3(256), 0, ctx->stream, A, 0);
+            else if (kmax <= 16384)
+                hipLaunchKernelGGL((dc_m7_kernel<16384>), dim3(ncols), dim3(256), 0, ctx->stream, A, 0);
+            else
+                hipLaunchKernelGGL((dc_m7_kernel<0>), dim3(ncols), dim3(256), 0, ctx->stream, A, 0);
+        } else {
+            int ncols = P * 2 * L;
+            if (kmax <= 1024)
+                hipLaunchKernelGGL((dc_m7_kernel<1024>), dim3(ncols), dim3(256), 0, ctx->stream, A, -1);
+            else if (kmax <= 16384)
+                hipLaunchKernelGGL((dc_m7_kernel<16384>), dim3(ncols), dim3(256), 0, ctx->stream, A, -1);
+            else
+                hipLaunchKernelGGL((dc_m7_kernel<0>), dim3(ncols), dim3(256), 0, ctx->stream, A, -1);
+        }
+        HGV_LAUNCH_CHECK();
+        for (int p = 0; p < P; ++p) {
+            MergeGeom g = merge_geom(n, L, p);
+            if (g.n2 <= 0) {   // unpaired block: carried over unchanged
+                if (!last) dcopy2d(ctx, g.n1, g.n1, Zc + g.a + (size_t)g.a * n, n, Zn + g.a + (size_t)g.a * n, n);
+                continue;
+            }
+            const double *Qp = Qb + qoff(L, p);
+            if (last) {
+                // wanted columns only, straight into the output
+                dgemm_nn(ctx, g.n1, m, g.n1, 1.0, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, 0.0, Z + g.a, ldz);
+                dgemm_nn(ctx, g.n2, m, g.n2, 1.0, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1, g.k,
+                         0.0, Z + g.a + g.n1, ldz);
+            } else {
+                dgemm_nn(ctx, g.n1, g.k, g.n1, 1.0, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, 0.0,
+                         Zn + g.a + (size_t)g.a * n, n);
+                dgemm_nn(ctx, g.n2, g.k, g.n2, 1.0, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1,
+                         g.k, 0.0, Zn + (g.a + g.n1) + (size_t)g.a * n, n);
+            }
+        }
+        std::swap(Zc, Zn);
+        if (last) break;
+    }
+    hipLaunchKernelGGL(dcopy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, D, lambda);
+    HGV_LAUNCH_CHECK();
+}
+
+}  // namespace hgv
