@@ -6,8 +6,11 @@
 // All three are recursive: an order-n problem splits at n1 (a multiple of 64
 // near n/2) into two halves joined by large MFMA GEMMs (herk / her2k / hemm /
 // gemm updates with K up to n/2), so nearly all flops run in gemm.hip.  The
-// leaves (order <= 64) are single-workgroup kernels working out of LDS and
-// registers.
+// leaves are 64 x 64 diagonal blocks: Cholesky and the reduction to standard
+// form of a block run in one workgroup out of LDS; the triangular-solve leaves
+// multiply by the inverse of the 64 x 64 diagonal block of L (an MFMA GEMM in
+// place, since one tile spans the 64-wide dimension).  The block inverses come
+// from the Cholesky leaves, or from a batched inversion kernel when L is given.
 #include "hgv_internal.h"
 
 namespace hgv {
@@ -21,17 +24,37 @@ static int split_point(int n) {
     return n1;
 }
 
+// Inverse of the lower-triangular sz x sz block held in S (LDS) into Inv (LDS):
+// column c solves L x = e_c by forward substitution (one thread per column).
+__device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LEAF + 1], int sz, int tid,
+                                       int nthreads) {
+    for (int c = tid; c < LEAF; c += nthreads) {
+        for (int i = 0; i < LEAF; ++i) {
+            if (i < c || i >= sz || c >= sz) {
+                Inv[i][c] = make_double2(0.0, 0.0);
+                continue;
+            }
+            double2 s = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+            for (int k = c; k < i; ++k) s = zsub(s, zmul(S[i][k], Inv[k][c]));
+            Inv[i][c] = zdiv(s, S[i][i]);
+        }
+    }
+}
+
 // ---- leaf Cholesky (n <= 64), one workgroup -----------------------------------
 // Right-looking unblocked Cholesky of the lower triangle held in LDS.  A
 // non-positive (or NaN) pivot at local column j records info = base + j + 1
-// (first failure wins) and stops the factorisation of this block.
-__global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, int *info, int base) {
+// (first failure wins) and stops the factorisation of this block.  The
+// inverse of the factor is written to Linv (64 x 64, column-major).
+__global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, int *info, int base,
+                                                    double2 *Linv) {
     __shared__ double2 S[LEAF][LEAF + 1];
+    __shared__ double2 Iv[LEAF][LEAF + 1];
     __shared__ int fail;
     const int tid = threadIdx.x;
-    for (int t = tid; t < n * n; t += 256) {
-        int i = t % n, j = t / n;
-        if (i >= j) S[i][j] = A[i + (size_t)j * lda];
+    for (int t = tid; t < LEAF * LEAF; t += 256) {
+        int i = t % LEAF, j = t / LEAF;
+        S[i][j] = (i < n && j < n && i >= j) ? A[i + (size_t)j * lda] : make_double2(0.0, 0.0);
     }
     if (tid == 0) fail = 0;
     __syncthreads();
@@ -50,7 +73,6 @@ __global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, 
         double inv = 1.0 / S[j][j].x;
         for (int i = j + 1 + tid; i < n; i += 256) S[i][j] = zscale(inv, S[i][j]);
         __syncthreads();
-        // trailing update of the lower triangle: S[i][k] -= S[i][j] conj(S[k][j]), j < k <= i
         int m = n - j - 1;
         for (int t = tid; t < m * m; t += 256) {
             int i = j + 1 + t % m, k = j + 1 + t / m;
@@ -66,85 +88,35 @@ __global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, 
         int i = t % n, j = t / n;
         if (i >= j) A[i + (size_t)j * lda] = S[i][j];
     }
+    if (Linv) {
+        if (fail) {   // keep the solves finite; the result is flagged through info
+            for (int t = tid; t < LEAF * LEAF; t += 256) {
+                int i = t % LEAF, j = t / LEAF;
+                S[i][j] = (i == j) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+        }
+        tri_inverse_lds(S, Iv, n, tid, 256);
+        __syncthreads();
+        for (int t = tid; t < LEAF * LEAF; t += 256) Linv[t] = Iv[t % LEAF][t / LEAF];
+    }
 }
 
-// ---- leaf triangular solves (order n <= 64), one wave per 64 right-hand sides --
-// mode 0 (right, L^H):  X (rows) <- X L^-H : x_j = (b_j - sum_{k<j} x_k conj(L_jk)) / L_jj
-// mode 1 (left,  L):    X (cols) <- L^-1 X : x_i = (b_i - sum_{k<i} L_ik x_k) / L_ii
-// mode 2 (left,  L^H):  X (cols) <- L^-H X : x_i = (b_i - sum_{k>i} conj(L_ki) x_k) / L_ii
-// Each lane keeps its right-hand side in registers; L is broadcast from LDS.
-// Columns (modes 1, 2) are staged through LDS so global accesses coalesce.
-template <int MODE>
-__global__ __launch_bounds__(64) void trsm_leaf_kernel(int n, int nrhs, const double2 *L, int ldl,
-                                                       double2 *X, int ldx) {
-    __shared__ double2 Ls[LEAF][LEAF + 1];
-    __shared__ double2 Xs[LEAF][LEAF + 1];
-    const int lane = threadIdx.x;
-    const int r0 = blockIdx.x * 64;
-    for (int t = lane; t < n * n; t += 64) {
-        int i = t % n, j = t / n;
-        Ls[i][j] = (i >= j) ? L[i + (size_t)j * ldl] : make_double2(0.0, 0.0);
-    }
-    double2 x[LEAF];
-    const int my = r0 + lane;
-    if (MODE == 0) {
-#pragma unroll
-        for (int k = 0; k < LEAF; ++k)
-            x[k] = (k < n && my < nrhs) ? X[my + (size_t)k * ldx] : make_double2(0.0, 0.0);
-    } else {
-        // stage columns r0..r0+63 (n rows each) through LDS: Xs[i][c]
-        for (int t = lane; t < n * 64; t += 64) {
-            int i = t % n, c = t / n;
-            Xs[i][c] = (r0 + c < nrhs) ? X[i + (size_t)(r0 + c) * ldx] : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < LEAF; ++k) x[k] = (k < n) ? Xs[k][lane] : make_double2(0.0, 0.0);
+// Inverse of every 64 x 64 diagonal block of the lower-triangular L.
+__global__ __launch_bounds__(64) void trtri_diag_kernel(int n, const double2 *L, int ldl, double2 *Linv) {
+    __shared__ double2 S[LEAF][LEAF + 1];
+    __shared__ double2 Iv[LEAF][LEAF + 1];
+    const int blk = blockIdx.x, tid = threadIdx.x;
+    const int o = blk * LEAF, sz = min(LEAF, n - o);
+    for (int t = tid; t < LEAF * LEAF; t += 64) {
+        int i = t % LEAF, j = t / LEAF;
+        S[i][j] = (i < sz && j < sz && i >= j) ? L[(o + i) + (size_t)(o + j) * ldl] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    if (MODE == 0 || MODE == 1) {
-#pragma unroll
-        for (int j = 0; j < LEAF; ++j) {
-            if (j < n) {
-                double2 s = x[j];
-#pragma unroll
-                for (int k = 0; k < j; ++k) {
-                    double2 l = Ls[j][k];
-                    if (MODE == 0) s = zsub(s, zmul(x[k], zconj(l)));
-                    else s = zsub(s, zmul(l, x[k]));
-                }
-                double2 d = Ls[j][j];
-                x[j] = (MODE == 0) ? zdiv(s, zconj(d)) : zdiv(s, d);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int jj = LEAF - 1; jj >= 0; --jj) {
-            if (jj < n) {
-                double2 s = x[jj];
-#pragma unroll
-                for (int k = jj + 1; k < LEAF; ++k)
-                    if (k < n) s = zsub(s, zmul(zconj(Ls[k][jj]), x[k]));
-                x[jj] = zdiv(s, zconj(Ls[jj][jj]));
-            }
-        }
-    }
-    if (MODE == 0) {
-        if (my < nrhs) {
-#pragma unroll
-            for (int k = 0; k < LEAF; ++k)
-                if (k < n) X[my + (size_t)k * ldx] = x[k];
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < LEAF; ++k)
-            if (k < n) Xs[k][lane] = x[k];
-        __syncthreads();
-        for (int t = lane; t < n * 64; t += 64) {
-            int i = t % n, c = t / n;
-            if (r0 + c < nrhs) X[i + (size_t)(r0 + c) * ldx] = Xs[i][c];
-        }
-    }
+    tri_inverse_lds(S, Iv, sz, tid, 64);
+    __syncthreads();
+    double2 *out = Linv + (size_t)blk * LEAF * LEAF;
+    for (int t = tid; t < LEAF * LEAF; t += 64) out[t] = Iv[t % LEAF][t / LEAF];
 }
 
 // ---- leaf reduction to standard form (n <= 64), one workgroup ---------------------
@@ -164,40 +136,35 @@ __global__ __launch_bounds__(64) void hegs2_kernel(int n, double2 *A, int lda, c
         Ws[i][j] = a;
     }
     __syncthreads();
-    double2 x[LEAF];
-    // pass 1: column `lane` of W = L^-1 A
-#pragma unroll
-    for (int k = 0; k < LEAF; ++k) x[k] = (k < n && lane < n) ? Ws[k][lane] : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int j = 0; j < LEAF; ++j) {
-        if (j < n) {
-            double2 s = x[j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], x[k]));
-            x[j] = zdiv(s, Ls[j][j]);
+    // pass 1: column `lane` of W = L^-1 A (in place in Ws, column by column)
+    if (lane < n) {
+        for (int j = 0; j < n; ++j) {
+            double2 s = Ws[j][lane];
+            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], Ws[k][lane]));
+            Ws[j][lane] = zdiv(s, Ls[j][j]);
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < LEAF; ++k)
-        if (k < n && lane < n) Ws[k][lane] = x[k];
-    __syncthreads();
-    // pass 2: column `lane` of C = L^-1 W^H, i.e. right-hand side conj(W[lane, :])
-#pragma unroll
-    for (int k = 0; k < LEAF; ++k) x[k] = (k < n && lane < n) ? zconj(Ws[lane][k]) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int j = 0; j < LEAF; ++j) {
-        if (j < n) {
-            double2 s = x[j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], x[k]));
-            x[j] = zdiv(s, Ls[j][j]);
+    // transpose-conjugate W in place: Ws <- W^H
+    for (int t = lane; t < n * n; t += 64) {
+        int i = t % n, j = t / n;
+        if (i < j) {
+            double2 x = Ws[i][j], y = Ws[j][i];
+            Ws[i][j] = zconj(y);
+            Ws[j][i] = zconj(x);
+        } else if (i == j) {
+            Ws[i][i] = zconj(Ws[i][i]);
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < LEAF; ++k)
-        if (k < n && lane < n) Ws[k][lane] = x[k];
+    // pass 2: C = L^-1 W^H
+    if (lane < n) {
+        for (int j = 0; j < n; ++j) {
+            double2 s = Ws[j][lane];
+            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], Ws[k][lane]));
+            Ws[j][lane] = zdiv(s, Ls[j][j]);
+        }
+    }
     __syncthreads();
     for (int t = lane; t < n * n; t += 64) {
         int i = t % n, j = t / n;
@@ -207,109 +174,155 @@ __global__ __launch_bounds__(64) void hegs2_kernel(int n, double2 *A, int lda, c
 }
 
 // ---- recursive drivers -----------------------------------------------------------------
-static double2 *gemm_ws(Arena &ar, int n, size_t &bytes) {
-    bytes = zgemm_splitk_bytes(n);
-    return ar.take<double2>(bytes / sizeof(double2));
+// Linv: inverses of the 64 x 64 diagonal blocks of the current L (block k at
+// Linv + k * 64 * 64); the recursion keeps every split at a multiple of 64.
+struct TriCtx {
+    hgv_ctx_s *ctx;
+    double2 *ws;
+    size_t wsb;
+};
+
+static const double2 *linv_at(const double2 *Linv, int off) { return Linv + (size_t)(off / LEAF) * LEAF * LEAF; }
+
+// X (m x n, n <= 64) <- X L^-H = X (L^-1)^H   (in place: one column tile)
+static void leaf_right_lc(const TriCtx &t, int m, int n, const double2 *Li, double2 *X, int ldx) {
+    ZGemm g;
+    g.m = m; g.n = n; g.k = n;
+    g.opa = 'N'; g.A = X; g.lda = ldx;
+    g.opb = 'C'; g.B = Li; g.ldb = LEAF;
+    g.C = X; g.ldc = ldx;
+    g.allow_split = 0;
+    zgemm(t.ctx, g, t.ws, t.wsb);
+}
+// X (n x m, n <= 64) <- L^-1 X   (in place: one row tile)
+static void leaf_left_ln(const TriCtx &t, int n, int m, const double2 *Li, double2 *X, int ldx) {
+    ZGemm g;
+    g.m = n; g.n = m; g.k = n;
+    g.opa = 'N'; g.A = Li; g.lda = LEAF;
+    g.opb = 'N'; g.B = X; g.ldb = ldx;
+    g.C = X; g.ldc = ldx;
+    g.allow_split = 0;
+    zgemm(t.ctx, g, t.ws, t.wsb);
+}
+// X (n x m, n <= 64) <- L^-H X = (L^-1)^H X
+static void leaf_left_lc(const TriCtx &t, int n, int m, const double2 *Li, double2 *X, int ldx) {
+    ZGemm g;
+    g.m = n; g.n = m; g.k = n;
+    g.opa = 'C'; g.A = Li; g.lda = LEAF;
+    g.opb = 'N'; g.B = X; g.ldb = ldx;
+    g.C = X; g.ldc = ldx;
+    g.allow_split = 0;
+    zgemm(t.ctx, g, t.ws, t.wsb);
 }
 
-template <int MODE>
-static void trsm_leaf(hgv_ctx_s *ctx, int n, int nrhs, const double2 *L, int ldl, double2 *X, int ldx) {
-    if (n <= 0 || nrhs <= 0) return;
-    hipLaunchKernelGGL((trsm_leaf_kernel<MODE>), dim3(cdiv(nrhs, 64)), dim3(64), 0, ctx->stream, n, nrhs, L,
-                       ldl, X, ldx);
-    HGV_LAUNCH_CHECK();
-}
-
-static void trsm_right_lc_rec(hgv_ctx_s *ctx, int m, int n, const double2 *L, int ldl, double2 *X, int ldx,
-                              double2 *ws, size_t wsb) {
+static void trsm_right_lc_rec(const TriCtx &t, int m, int n, const double2 *L, int ldl, const double2 *Linv,
+                              double2 *X, int ldx) {
     if (m <= 0 || n <= 0) return;
     if (n <= LEAF) {
-        trsm_leaf<0>(ctx, n, m, L, ldl, X, ldx);
+        leaf_right_lc(t, m, n, Linv, X, ldx);
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
-    trsm_right_lc_rec(ctx, m, n1, L, ldl, X, ldx, ws, wsb);
+    trsm_right_lc_rec(t, m, n1, L, ldl, Linv, X, ldx);
     ZGemm g;  // X2 -= X1 L21^H
     g.m = m; g.n = n2; g.k = n1;
     g.opa = 'N'; g.A = X; g.lda = ldx;
     g.opb = 'C'; g.B = L + n1; g.ldb = ldl;
     g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
     g.C = X + (size_t)n1 * ldx; g.ldc = ldx;
-    zgemm(ctx, g, ws, wsb);
-    trsm_right_lc_rec(ctx, m, n2, L + n1 + (size_t)n1 * ldl, ldl, X + (size_t)n1 * ldx, ldx, ws, wsb);
+    zgemm(t.ctx, g, t.ws, t.wsb);
+    trsm_right_lc_rec(t, m, n2, L + n1 + (size_t)n1 * ldl, ldl, linv_at(Linv, n1), X + (size_t)n1 * ldx, ldx);
 }
 
-static void trsm_left_ln_rec(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx,
-                             double2 *ws, size_t wsb) {
+static void trsm_left_ln_rec(const TriCtx &t, int n, int m, const double2 *L, int ldl, const double2 *Linv,
+                             double2 *X, int ldx) {
     if (m <= 0 || n <= 0) return;
     if (n <= LEAF) {
-        trsm_leaf<1>(ctx, n, m, L, ldl, X, ldx);
+        leaf_left_ln(t, n, m, Linv, X, ldx);
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
-    trsm_left_ln_rec(ctx, n1, m, L, ldl, X, ldx, ws, wsb);
+    trsm_left_ln_rec(t, n1, m, L, ldl, Linv, X, ldx);
     ZGemm g;  // X2 -= L21 X1
     g.m = n2; g.n = m; g.k = n1;
     g.opa = 'N'; g.A = L + n1; g.lda = ldl;
     g.opb = 'N'; g.B = X; g.ldb = ldx;
     g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
     g.C = X + n1; g.ldc = ldx;
-    zgemm(ctx, g, ws, wsb);
-    trsm_left_ln_rec(ctx, n2, m, L + n1 + (size_t)n1 * ldl, ldl, X + n1, ldx, ws, wsb);
+    zgemm(t.ctx, g, t.ws, t.wsb);
+    trsm_left_ln_rec(t, n2, m, L + n1 + (size_t)n1 * ldl, ldl, linv_at(Linv, n1), X + n1, ldx);
 }
 
-static void trsm_left_lc_rec(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx,
-                             double2 *ws, size_t wsb) {
+static void trsm_left_lc_rec(const TriCtx &t, int n, int m, const double2 *L, int ldl, const double2 *Linv,
+                             double2 *X, int ldx) {
     if (m <= 0 || n <= 0) return;
     if (n <= LEAF) {
-        trsm_leaf<2>(ctx, n, m, L, ldl, X, ldx);
+        leaf_left_lc(t, n, m, Linv, X, ldx);
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
-    trsm_left_lc_rec(ctx, n2, m, L + n1 + (size_t)n1 * ldl, ldl, X + n1, ldx, ws, wsb);
+    trsm_left_lc_rec(t, n2, m, L + n1 + (size_t)n1 * ldl, ldl, linv_at(Linv, n1), X + n1, ldx);
     ZGemm g;  // X1 -= L21^H X2
     g.m = n1; g.n = m; g.k = n2;
     g.opa = 'C'; g.A = L + n1; g.lda = ldl;
     g.opb = 'N'; g.B = X + n1; g.ldb = ldx;
     g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
     g.C = X; g.ldc = ldx;
-    zgemm(ctx, g, ws, wsb);
-    trsm_left_lc_rec(ctx, n1, m, L, ldl, X, ldx, ws, wsb);
+    zgemm(t.ctx, g, t.ws, t.wsb);
+    trsm_left_lc_rec(t, n1, m, L, ldl, Linv, X, ldx);
+}
+
+// Scratch shared by the recursive stages: split-K partials and block inverses.
+static TriCtx tri_scratch(hgv_ctx_s *ctx, Arena &ar, int n, double2 **Linv) {
+    TriCtx t;
+    t.ctx = ctx;
+    t.wsb = zgemm_splitk_bytes(n);
+    t.ws = ar.take<double2>(t.wsb / sizeof(double2));
+    *Linv = ar.take<double2>((size_t)cdiv(std::max(n, 1), LEAF) * LEAF * LEAF);
+    return t;
+}
+
+static void invert_diag_blocks(hgv_ctx_s *ctx, int n, const double2 *L, int ldl, double2 *Linv) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(trtri_diag_kernel, dim3(cdiv(n, LEAF)), dim3(64), 0, ctx->stream, n, L, ldl, Linv);
+    HGV_LAUNCH_CHECK();
 }
 
 void trsm_right_lc(hgv_ctx_s *ctx, int m, int n, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar) {
-    size_t b;
-    double2 *ws = gemm_ws(ar, n, b);
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
     if (ar.measuring()) return;
-    trsm_right_lc_rec(ctx, m, n, L, ldl, X, ldx, ws, b);
+    invert_diag_blocks(ctx, n, L, ldl, Linv);
+    trsm_right_lc_rec(t, m, n, L, ldl, Linv, X, ldx);
 }
 void trsm_left_ln(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar) {
-    size_t b;
-    double2 *ws = gemm_ws(ar, n, b);
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
     if (ar.measuring()) return;
-    trsm_left_ln_rec(ctx, n, m, L, ldl, X, ldx, ws, b);
+    invert_diag_blocks(ctx, n, L, ldl, Linv);
+    trsm_left_ln_rec(t, n, m, L, ldl, Linv, X, ldx);
 }
 void trsm_left_lc(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar) {
-    size_t b;
-    double2 *ws = gemm_ws(ar, n, b);
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
     if (ar.measuring()) return;
-    trsm_left_lc_rec(ctx, n, m, L, ldl, X, ldx, ws, b);
+    invert_diag_blocks(ctx, n, L, ldl, Linv);
+    trsm_left_lc_rec(t, n, m, L, ldl, Linv, X, ldx);
 }
 void trsm_lh_run(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar) {
     trsm_left_lc(ctx, n, m, L, ldl, X, ldx, ar);
 }
 
-static void potrf_rec(hgv_ctx_s *ctx, int n, double2 *A, int lda, int *info, int base, double2 *ws,
-                      size_t wsb) {
+static void potrf_rec(const TriCtx &t, int n, double2 *A, int lda, int *info, int base, double2 *Linv) {
     if (n <= 0) return;
     if (n <= LEAF) {
-        hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, ctx->stream, n, A, lda, info, base);
+        hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, t.ctx->stream, n, A, lda, info, base, Linv);
         HGV_LAUNCH_CHECK();
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
-    potrf_rec(ctx, n1, A, lda, info, base, ws, wsb);
-    trsm_right_lc_rec(ctx, n2, n1, A, lda, A + n1, lda, ws, wsb);  // L21 = A21 L11^-H
+    potrf_rec(t, n1, A, lda, info, base, Linv);
+    trsm_right_lc_rec(t, n2, n1, A, lda, Linv, A + n1, lda);  // L21 = A21 L11^-H
     ZGemm g;  // A22 -= L21 L21^H (lower)
     g.m = n2; g.n = n2; g.k = n1;
     g.opa = 'N'; g.A = A + n1; g.lda = lda;
@@ -317,38 +330,37 @@ static void potrf_rec(hgv_ctx_s *ctx, int n, double2 *A, int lda, int *info, int
     g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
     g.C = A + n1 + (size_t)n1 * lda; g.ldc = lda;
     g.lower = 1;
-    zgemm(ctx, g, ws, wsb);
-    potrf_rec(ctx, n2, A + n1 + (size_t)n1 * lda, lda, info, base + n1, ws, wsb);
+    zgemm(t.ctx, g, t.ws, t.wsb);
+    potrf_rec(t, n2, A + n1 + (size_t)n1 * lda, lda, info, base + n1, const_cast<double2 *>(linv_at(Linv, n1)));
 }
 
 void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_info, int info_offset) {
-    size_t b;
-    double2 *ws = gemm_ws(ar, n, b);
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
     if (ar.measuring()) return;
-    potrf_rec(ctx, n, B, ldb, d_info, info_offset, ws, b);
+    potrf_rec(t, n, B, ldb, d_info, info_offset, Linv);
 }
 
-static void hegst_rec(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, double2 *ws,
-                      size_t wsb) {
+static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2 *L, int ldl, const double2 *Linv) {
     if (n <= 0) return;
     if (n <= LEAF) {
-        hipLaunchKernelGGL(hegs2_kernel, dim3(1), dim3(64), 0, ctx->stream, n, A, lda, L, ldl);
+        hipLaunchKernelGGL(hegs2_kernel, dim3(1), dim3(64), 0, t.ctx->stream, n, A, lda, L, ldl);
         HGV_LAUNCH_CHECK();
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
     double2 *A11 = A, *A21 = A + n1, *A22 = A + n1 + (size_t)n1 * lda;
     const double2 *L11 = L, *L21 = L + n1, *L22 = L + n1 + (size_t)n1 * ldl;
-    hegst_rec(ctx, n1, A11, lda, L11, ldl, ws, wsb);
-    trsm_right_lc_rec(ctx, n2, n1, L11, ldl, A21, lda, ws, wsb);  // A21 <- A21 L11^-H
-    fill_upper_from_lower(ctx, n1, A11, lda);                      // A'11 as a full matrix
+    hegst_rec(t, n1, A11, lda, L11, ldl, Linv);
+    trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);      // A21 <- A21 L11^-H
+    fill_upper_from_lower(t.ctx, n1, A11, lda);                   // A'11 as a full matrix
     ZGemm h;  // A21 -= 1/2 L21 A'11
     h.m = n2; h.n = n1; h.k = n1;
     h.opa = 'N'; h.A = L21; h.lda = ldl;
     h.opb = 'N'; h.B = A11; h.ldb = lda;
     h.alpha = make_double2(-0.5, 0.0); h.beta = make_double2(1.0, 0.0);
     h.C = A21; h.ldc = lda;
-    zgemm(ctx, h, ws, wsb);
+    zgemm(t.ctx, h, t.ws, t.wsb);
     ZGemm r;  // A22 -= A21 L21^H + L21 A21^H (lower)
     r.m = n2; r.n = n2; r.k = n1;
     r.opa = 'N'; r.A = A21; r.lda = lda;
@@ -358,17 +370,18 @@ static void hegst_rec(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 
     r.alpha = make_double2(-1.0, 0.0); r.beta = make_double2(1.0, 0.0);
     r.C = A22; r.ldc = lda;
     r.lower = 1;
-    zgemm(ctx, r, ws, wsb);
-    zgemm(ctx, h, ws, wsb);                                        // A21 -= 1/2 L21 A'11
-    trsm_left_ln_rec(ctx, n2, n1, L22, ldl, A21, lda, ws, wsb);   // A21 <- L22^-1 A21
-    hegst_rec(ctx, n2, A22, lda, L22, ldl, ws, wsb);
+    zgemm(t.ctx, r, t.ws, t.wsb);
+    zgemm(t.ctx, h, t.ws, t.wsb);                                  // A21 -= 1/2 L21 A'11
+    trsm_left_ln_rec(t, n2, n1, L22, ldl, linv_at(Linv, n1), A21, lda);   // A21 <- L22^-1 A21
+    hegst_rec(t, n2, A22, lda, L22, ldl, linv_at(Linv, n1));
 }
 
 void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, Arena &ar) {
-    size_t b;
-    double2 *ws = gemm_ws(ar, n, b);
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
     if (ar.measuring()) return;
-    hegst_rec(ctx, n, A, lda, L, ldl, ws, b);
+    invert_diag_blocks(ctx, n, L, ldl, Linv);
+    hegst_rec(t, n, A, lda, L, ldl, Linv);
 }
 
 }  // namespace hgv

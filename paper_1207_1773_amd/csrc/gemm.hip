@@ -7,7 +7,8 @@
 //
 // Design (CDNA4):
 //  * workgroup = 4 wave64s arranged 2 x 2; each wave owns a (BM/2) x (BN/2)
-//    sub-tile made of 16x16 MFMA blocks;
+//    sub-tile made of 16x16 MFMA blocks; registers are capped so that two
+//    workgroups share a CU (two waves per SIMD hide LDS and MFMA latency);
 //  * complex double: four real v_mfma_f64_16x16x4f64 per 16x16x4 complex block
 //    (re*re, -im*im into the real accumulator, re*im, im*re into the
 //    imaginary one); real double: one; complex float: four
@@ -210,7 +211,7 @@ __device__ inline float2 e_add(float2 a, float2 b) { return make_float2(a.x + b.
 __device__ inline double e_add(double a, double b) { return a + b; }
 
 template <class T, int BM, int BN>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmDev<T> g) {
+__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
     typedef typename T::E E;
     typedef typename T::Acc Acc;
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -379,7 +380,7 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     int chunks = cdiv(std::max(a.k, 0), BK) * g.nseg;
     int splits = 1;
     // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
-    while (splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 16) splits *= 2;
+    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 16) splits *= 2;
     size_t need = (size_t)splits * a.m * a.n * sizeof(E);
     while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
         splits /= 2;
@@ -449,12 +450,13 @@ struct DGemmArgs {
     double alpha, beta;
     double *C; int ldc;
     int lower;
+    int allow_split;
 };
 
 void dgemm_nn(hgv_ctx_s *ctx, int m, int n, int k, double alpha, const double *A, int lda,
               const double *B, int ldb, double beta, double *C, int ldc) {
     if (m <= 0 || n <= 0) return;
-    DGemmArgs a{m, n, k, 'N', 'N', A, lda, B, ldb, 'N', 'N', nullptr, 1, nullptr, 1, alpha, beta, C, ldc, 0};
+    DGemmArgs a{m, n, k, 'N', 'N', A, lda, B, ldb, 'N', 'N', nullptr, 1, nullptr, 1, alpha, beta, C, ldc, 0, 1};
     gemm_launch<TD>(ctx, a, nullptr, 0, 2.0 * m * (double)n * k);
 }
 

@@ -64,164 +64,181 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
+// Lane groups of TPR consecutive lanes own one row (or column) of a task's
+// blocks; sums over a row reduce inside the group with shuffles.
+template <int TPR>
+__device__ inline double2 group_sum(double2 x) {
+#pragma unroll
+    for (int o = 1; o < TPR; o <<= 1) {
+        x.x += __shfl_xor(x.x, o, 64);
+        x.y += __shfl_xor(x.y, o, 64);
+    }
+    return x;
+}
+
+// One workgroup runs whole sweeps; per task (see the file comment):
+//   D (the diagonal block, rows/columns I_j) lives in registers: thread
+//   (row, q) owns D[row][q + TPR*u];
+//   E (rows I_j, columns I_{j-1}) lives in LDS because it is used by rows (the
+//   right application of the previous reflector) and then by columns (the
+//   left application of the new one).
 template <int BM>
 __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
+    constexpr int TPR = 256 / BM;   // lanes per row
+    constexpr int NU = BM / TPR;    // row elements per lane
     __shared__ double2 Es[BM][BM + 1];
-    __shared__ double2 Ds[BM][BM + 1];
-    __shared__ double2 v[BM], vp[BM], pv[BM], wv[BM];
-    __shared__ double2 part[4][64];
-    __shared__ double2 sh_tau, sh_taup, sh_scale;
-    __shared__ double sh_beta, sh_tail;
-    const int tid = threadIdx.x;
+    __shared__ double2 v[BM], vp[BM], pv[BM];
+    __shared__ double2 sh_tau, sh_taup;
+    __shared__ double sh_beta;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int row = tid / TPR, q = tid % TPR;
     const int n = a.n, b = a.b, ldb = a.ldb;
     double2 *AB = a.AB;
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 Dr[NU];
 
     for (int s = blockIdx.x; s < n - 1; s += gridDim.x) {
         const int nt = hb_tasks(n, b, s);
         for (int j = 0; j < nt; ++j) {
             // ---- wait for sweep s-1 ------------------------------------------------
             if (s > 0 && tid == 0) {
+                // poll with relaxed loads (an acquire per poll would invalidate the
+                // caches for every other workgroup), then one acquire fence
                 const int need = min(j + 2, hb_tasks(n, b, s - 1));
                 long spins = 0;
-                while (__hip_atomic_load(&a.prog[s - 1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1L << 26)) {
+                while (__hip_atomic_load(&a.prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1L << 27)) {
                         __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
             const int r0 = s + 1 + j * b;
             const int L = min(b, n - r0);          // rows of this task
             const int p0 = r0 - b;                 // first column of E (j > 0)
-            // ---- load D (full Hermitian from the lower band) and E / column s --------
-            for (int t = tid; t < L * L; t += 256) {
-                int i = t % L, k = t / L;
-                Ds[i][k] = band_get(AB, ldb, r0 + i, r0 + k);
+            // ---- D row into registers, E (or column s) into LDS --------------------
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                int k = q + TPR * u;
+                Dr[u] = (row < L && k < L) ? band_get(AB, ldb, r0 + row, r0 + k) : zero;
             }
             if (j == 0) {
-                if (tid < L) Es[tid][0] = AB[(r0 + tid - s) + (size_t)s * ldb];
+                if (tid < BM) Es[tid][0] = (tid < L) ? AB[(r0 + tid - s) + (size_t)s * ldb] : zero;
             } else {
-                for (int t = tid; t < L * b; t += 256) {
-                    int i = t % L, c = t / L;
-                    Es[i][c] = AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb];
+#pragma unroll
+                for (int t = tid; t < BM * BM; t += 256) {
+                    int i = t % BM, c = t / BM;
+                    Es[i][c] = (i < L && c < b) ? AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] : zero;
                 }
             }
             __syncthreads();
             if (j > 0) {
-                // E <- E - tau_p (E v_p) v_p^H     (previous reflector from the right)
-                {
-                    const int i = tid & 63, q = tid >> 6;
-                    double2 acc = make_double2(0.0, 0.0);
-                    if (i < L)
-                        for (int c = q; c < b; c += 4) acc = zadd(acc, zmul(Es[i][c], vp[c]));
-                    part[q][i] = (i < L) ? acc : make_double2(0.0, 0.0);
+                // E <- E - tau_p (E v_p) v_p^H   (previous reflector from the right)
+                double2 acc = zero;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    int c = q + TPR * u;
+                    acc = zadd(acc, zmul(Es[row][c], vp[c]));
                 }
-                __syncthreads();
-                if (tid < L) pv[tid] = zmul(sh_taup, zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid])));
-                __syncthreads();
-                for (int t = tid; t < L * b; t += 256) {
-                    int i = t % L, c = t / L;
-                    Es[i][c] = zsub(Es[i][c], zmul(pv[i], zconj(vp[c])));
+                double2 y = zmul(sh_taup, group_sum<TPR>(acc));
+                if (row < L) {
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        int c = q + TPR * u;
+                        Es[row][c] = zsub(Es[row][c], zmul(y, zconj(vp[c])));
+                    }
                 }
                 __syncthreads();
             }
-            // ---- reflector from Es[:, 0] -------------------------------------------------
+            // ---- reflector from Es[:, 0] (wave 0) -------------------------------------
             if (tid < 64) {
-                double t2 = 0.0;
-                if (tid >= 1 && tid < L) t2 = zabs2(Es[tid][0]);
-                t2 = wave_sum(t2);
-                if (tid == 0) {
-                    double2 alpha = Es[0][0];
-                    double beta;
-                    double2 tau, scale;
-                    if (t2 == 0.0 && alpha.y == 0.0) {
-                        beta = alpha.x;
-                        tau = make_double2(0.0, 0.0);
-                        scale = make_double2(0.0, 0.0);
-                    } else {
-                        double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + t2);
-                        beta = -copysign(nrm, alpha.x);
-                        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-                        scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
-                    }
+                double2 x = (lane < L) ? Es[lane][0] : zero;
+                double t2 = wave_sum((lane >= 1) ? zabs2(x) : 0.0);
+                double2 alpha = make_double2(__shfl(x.x, 0, 64), __shfl(x.y, 0, 64));
+                double beta;
+                double2 tau, scale;
+                if (t2 == 0.0 && alpha.y == 0.0) {
+                    beta = alpha.x;
+                    tau = zero;
+                    scale = zero;
+                } else {
+                    double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + t2);
+                    beta = -copysign(nrm, alpha.x);
+                    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                    scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+                }
+                if (lane < BM) v[lane] = (lane >= L) ? zero : (lane == 0 ? make_double2(1.0, 0.0) : zmul(scale, x));
+                if (lane == 0) {
                     sh_beta = beta;
                     sh_tau = tau;
-                    sh_scale = scale;
                 }
             }
-            __syncthreads();
-            if (tid < L) v[tid] = (tid == 0) ? make_double2(1.0, 0.0) : zmul(sh_scale, Es[tid][0]);
             __syncthreads();
             const double2 tau = sh_tau;
+            const double beta = sh_beta;
             if (j == 0) {
-                if (tid < L) {
-                    double2 val = (tid == 0) ? make_double2(sh_beta, 0.0) : make_double2(0.0, 0.0);
-                    AB[(r0 + tid - s) + (size_t)s * ldb] = val;
-                }
+                if (tid < L) AB[(r0 + tid - s) + (size_t)s * ldb] = (tid == 0) ? make_double2(beta, 0.0) : zero;
             } else {
-                // E[:, 1:] <- H^H E[:, 1:] = E - conj(tau) v (v^H E);  E[:, 0] = beta e_1
-                {
-                    const int c = tid & 63, q = tid >> 6;
-                    double2 acc = make_double2(0.0, 0.0);
-                    if (c >= 1 && c < b)
-                        for (int i = q; i < L; i += 4) acc = zadd(acc, zcmul(v[i], Es[i][c]));
-                    part[q][c] = (c < b) ? acc : make_double2(0.0, 0.0);
+                // E[:, 1:] <- E - conj(tau) v (v^H E);  E[:, 0] = beta e_1   (column owners)
+                const int c = row;   // lane group -> column
+                double2 acc = zero;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    int i = q + TPR * u;
+                    acc = zadd(acc, zcmul(v[i], Es[i][c]));
                 }
-                __syncthreads();
-                if (tid < b) {
-                    double2 s4 = zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid]));
-                    wv[tid] = zcmul(tau, s4);   // conj(tau) * (v^H E)_c
-                }
-                __syncthreads();
-                for (int t = tid; t < L * b; t += 256) {
-                    int i = t % L, c = t / L;
-                    double2 val;
-                    if (c == 0) val = (i == 0) ? make_double2(sh_beta, 0.0) : make_double2(0.0, 0.0);
-                    else val = zsub(Es[i][c], zmul(v[i], wv[c]));
-                    AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] = val;
+                double2 wc = zcmul(tau, group_sum<TPR>(acc));
+                if (c < b) {
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        int i = q + TPR * u;
+                        if (i < L) {
+                            double2 val = (c == 0) ? (i == 0 ? make_double2(beta, 0.0) : zero)
+                                                   : zsub(Es[i][c], zmul(v[i], wc));
+                            AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] = val;
+                        }
+                    }
                 }
             }
-            // ---- two-sided update of D:  D <- H^H D H ------------------------------------
+            // ---- two-sided update of D:  D <- H^H D H -----------------------------------
             {
-                const int i = tid & 63, q = tid >> 6;
-                double2 acc = make_double2(0.0, 0.0);
-                if (i < L)
-                    for (int k = q; k < L; k += 4) acc = zadd(acc, zmul(Ds[i][k], v[k]));
-                part[q][i] = (i < L) ? acc : make_double2(0.0, 0.0);
-            }
-            __syncthreads();
-            if (tid < L) pv[tid] = zmul(tau, zadd(zadd(part[0][tid], part[1][tid]), zadd(part[2][tid], part[3][tid])));
-            __syncthreads();
-            if (tid < 64) {
-                // v^H p (real part suffices: tau-bar v^H p = |tau|^2 v^H D v is real)
-                double2 c = (tid < L) ? zcmul(v[tid], pv[tid]) : make_double2(0.0, 0.0);
-                double cr = wave_sum(c.x), ci = wave_sum(c.y);
-                if (tid == 0) {
-                    double2 vhp = make_double2(cr, ci);
-                    double2 half = zcmul(tau, vhp);          // conj(tau) v^H p
-                    sh_tail = 0.5 * half.x;
+                double2 acc = zero;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) acc = zadd(acc, zmul(Dr[u], v[q + TPR * u]));
+                double2 prow = zmul(tau, group_sum<TPR>(acc));
+                if (q == 0) pv[row] = (row < L) ? prow : zero;
+                __syncthreads();
+                // w = p - 1/2 conj(tau) (v^H p) v   (the scalar is real; same order in every wave)
+                double2 c1 = (lane < BM) ? zcmul(v[lane], pv[lane]) : zero;
+                double vr = wave_sum(c1.x), vi = wave_sum(c1.y);
+                double half = 0.5 * zcmul(tau, make_double2(vr, vi)).x;
+                double2 wrow = zsub(prow, zscale(half, v[row]));
+                double2 vrow = v[row];
+                if (row < L) {
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        int k = q + TPR * u;
+                        if (k <= row) {
+                            double2 wk = zsub(pv[k], zscale(half, v[k]));
+                            double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(v[k])));
+                            if (k == row) val.y = 0.0;
+                            AB[(row - k) + (size_t)(r0 + k) * ldb] = val;
+                        }
+                    }
                 }
-            }
-            __syncthreads();
-            if (tid < L) wv[tid] = zsub(pv[tid], zscale(sh_tail, v[tid]));
-            __syncthreads();
-            for (int t = tid; t < L * L; t += 256) {
-                int i = t % L, k = t / L;
-                if (i < k) continue;
-                double2 val = zsub(zsub(Ds[i][k], zmul(v[i], zconj(wv[k]))), zmul(wv[i], zconj(v[k])));
-                if (i == k) val.y = 0.0;
-                AB[(i - k) + (size_t)(r0 + k) * ldb] = val;
             }
             // ---- store the reflector (group-major layout) and keep it for task j+1 -----
             {
                 const int B = s / b, t = s % b;
                 size_t base = ((size_t)B * a.J + j) * b + t;
-                if (tid < b) a.V2[base * b + tid] = (tid < L) ? v[tid] : make_double2(0.0, 0.0);
+                if (tid < b) a.V2[base * b + tid] = v[tid];
                 if (tid == 0) a.tau2[base] = tau;
             }
-            if (tid < L) vp[tid] = v[tid];
+            __syncthreads();
+            if (tid < BM) vp[tid] = v[tid];
             if (tid == 0) sh_taup = tau;
             __threadfence();
             __syncthreads();
@@ -275,7 +292,9 @@ static void launch_hb2st(hgv_ctx_s *ctx, HbArgs &a) {
     int dev = ctx->device, cus = 0, per = 0;
     HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM>, 256, 0));
-    int G = std::max(1, std::min(cus * std::max(per, 1), a.n - 1));
+    // a sweep starts two tasks behind its predecessor, so about J/2 sweeps are
+    // in flight at once; more workgroups would only poll
+    int G = std::max(1, std::min({cus * std::max(per, 1), a.n - 1, a.J / 2 + 4}));
     void *args[] = {&a};
     HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM>), dim3(G), dim3(256), args, 0,
                                        ctx->stream));
@@ -361,68 +380,122 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int
     for (int t = tid; t < g * g; t += 256) tout[t] = Ts[t % g][t / g];   // column-major g x g
 }
 
-// Y (n x m) <- Q2 Y; workgroup = NC columns; groups walked from the last group
-// of sweeps to the first, j ascending inside a group of sweeps.
-template <int BMAX, int GMAX, int NC>
-__global__ __launch_bounds__(256) void q2_apply_kernel(int n, int m, int b, int g, int J, int ngrp,
-                                                        const double2 *V2, const double2 *T2, double2 *Y, int ldy) {
-    __shared__ double2 Vs[GMAX][BMAX + 1];     // Vs[t][i] = entry i of reflector t
-    __shared__ double2 Ts[GMAX][GMAX + 1];
-    __shared__ double2 Ys[GMAX + BMAX][NC + 1];
-    __shared__ double2 Ws[GMAX][NC + 1];
-    const int tid = threadIdx.x;
+// Y (n x m) <- Q2 Y on MFMA tiles.  Workgroup = 16 columns of Y (so two or
+// three workgroups share a CU and hide each other's latencies); for every
+// group (walked from the last group of sweeps to the first, j ascending):
+//   W = V^H Y_rows  (two 16x16 tiles, the k range split over the 4 waves),
+//   W <- T W        (two tiles),
+//   Y_rows -= V W   (six row tiles).
+// v_mfma_f64_16x16x4f64 does the products (four real products per complex
+// block).  V (the (g+b-1) x g parallelogram, column t non-zero on rows
+// t .. t+b-1) and T are read from memory straight into operand registers
+// (they are shared by all workgroups and stay in L2); only the Y rows and W
+// live in LDS.  k-steps of tiles that are entirely zero are skipped.
+typedef double q2v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline void q2_cmfma(double2 a, double2 b, q2v4d &re, q2v4d &im) {
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+}
+
+template <int BMAX>
+__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp,
+                                                       const double2 *V2, const double2 *T2, double2 *Y, int ldy) {
+    constexpr int NC = 16, GM = 32, RM = 96;
+    constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
+    __shared__ double2 Ys[RM][NC + 1];
+    __shared__ double2 Wp[2][GM][NC + 1];     // partial W over the two k halves
+    __shared__ double2 W2[GM][NC + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
     const int c0 = blockIdx.x * NC;
     const int nc = min(NC, m - c0);
+    const double2 zero = make_double2(0.0, 0.0);
     for (int B = ngrp - 1; B >= 0; --B) {
+        const int s0 = B * g;
         for (int j = 0; j < J; ++j) {
-            const int R0 = B * g + 1 + j * b;
+            const int R0 = s0 + 1 + j * b;
             if (R0 > n - 1) break;
             const int nrows = min(g + b - 1, n - R0);
             const double2 *tg = T2 + ((size_t)B * J + j) * g * g;
+            // element (r, t) of the parallelogram V
+            auto vget = [&](int r, int t) -> double2 {
+                int i = r - t, s = s0 + t;
+                return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
+            };
             __syncthreads();
-            for (int t = tid; t < g * b; t += 256) {
-                int tt = t / b, i = t % b;
-                int s = B * g + tt;
-                Vs[tt][i] = (s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : make_double2(0.0, 0.0);
+            for (int t = tid; t < RM * NC; t += 256) {
+                int r = t % RM, c = t / RM;
+                Ys[r][c] = (r < nrows && c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : zero;
             }
-            for (int t = tid; t < g * g; t += 256) Ts[t % g][t / g] = tg[t];
-            for (int t = tid; t < nrows * NC; t += 256) {
-                int r = t % nrows, c = t / nrows;
-                Ys[r][c] = (c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : make_double2(0.0, 0.0);
-            }
-            __syncthreads();
-            // W = V^H Y_rows
-            for (int t = tid; t < g * NC; t += 256) {
-                int c = t % NC, tt = t / NC;
-                double2 acc = make_double2(0.0, 0.0);
-                for (int i = 0; i < b && tt + i < nrows; ++i) acc = zadd(acc, zcmul(Vs[tt][i], Ys[tt + i][c]));
-                Ws[tt][c] = acc;
+            // step-1 operands: wave -> (t tile, k half)
+            const int t0 = 16 * (wave & 1), kh = wave >> 1;
+            const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
+            const int ka = (nks + 1) / 2;
+            const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
+            double2 a1[K1];
+#pragma unroll
+            for (int q = 0; q < K1; ++q) {
+                int kq = kbeg + q;
+                double2 v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
+                a1[q] = make_double2(v.x, -v.y);   // conj(V)
             }
             __syncthreads();
-            // W <- T W   (T upper triangular)
-            double2 tw[(GMAX * NC + 255) / 256];
             {
-                int q = 0;
-                for (int t = tid; t < g * NC; t += 256, ++q) {
-                    int c = t % NC, tt = t / NC;
-                    double2 acc = make_double2(0.0, 0.0);
-                    for (int l = tt; l < g; ++l) acc = zadd(acc, zmul(Ts[tt][l], Ws[l][c]));
-                    tw[q] = acc;
+                q2v4d re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < K1; ++q) {
+                    int kq = kbeg + q;
+                    if (kq < kend) q2_cmfma(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
                 }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Wp[kh][t0 + lk + 4 * i][lr] = make_double2(re[i], im[i]);
             }
             __syncthreads();
-            {
-                int q = 0;
-                for (int t = tid; t < g * NC; t += 256, ++q) Ws[t / NC][t % NC] = tw[q];
+            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]); T upper triangular
+            if (wave < 2) {
+                q2v4d re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                for (int l4 = t0; l4 < GM; l4 += 4) {
+                    int row = t0 + lr, col = l4 + lk;
+                    double2 tv = (row < g && col < g) ? tg[row + col * g] : zero;
+                    double2 w = zadd(Wp[0][l4 + lk][lr], Wp[1][l4 + lk][lr]);
+                    q2_cmfma(tv, w, re, im);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) W2[t0 + lk + 4 * i][lr] = make_double2(re[i], im[i]);
             }
             __syncthreads();
-            // Y_rows -= V W
-            for (int t = tid; t < nrows * NC; t += 256) {
-                int c = t % NC, r = t / NC;
-                double2 acc = Ys[r][c];
-                int tlo = max(0, r - b + 1), thi = min(r, g - 1);
-                for (int tt = tlo; tt <= thi; ++tt) acc = zsub(acc, zmul(Vs[tt][r - tt], Ws[tt][c]));
-                if (c < nc) Y[R0 + r + (size_t)(c0 + c) * ldy] = acc;
+            // step 3: Y_rows -= V W2, row tiles wave and wave + 4
+            for (int q = wave; q < 6; q += 4) {
+                const int r0 = 16 * q;
+                if (r0 >= nrows) continue;
+                q2v4d re, im;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    double2 y = Ys[r0 + lk + 4 * i][lr];
+                    re[i] = y.x;
+                    im[i] = y.y;
+                }
+                const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+                double2 a3[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int t4 = tlo + 4 * u;
+                    double2 v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
+                    a3[u] = make_double2(-v.x, -v.y);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int t4 = tlo + 4 * u;
+                    if (t4 < thi) q2_cmfma(a3[u], W2[t4 + lk][lr], re, im);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int r = r0 + lk + 4 * i;
+                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = make_double2(re[i], im[i]);
+                }
             }
         }
     }
@@ -437,21 +510,19 @@ void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const
     const int J = hb_J(n, b), ngrp = n >= 2 ? cdiv(n - 1, g) : 0;
     double2 *T2 = ar.take<double2>(std::max<size_t>((size_t)ngrp * J * g * g, 1));
     if (ar.measuring() || n < 2 || m == 0) return;
-    if (b <= 32) {
+    if (b <= 32)
         hipLaunchKernelGGL((q2_tbuild_kernel<32, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
-        HGV_LAUNCH_CHECK();
-        constexpr int NC = 64;
-        hipLaunchKernelGGL((q2_apply_kernel<32, 32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, g,
-                           J, ngrp, V2, T2, Y, ldy);
-    } else {
+    else
         hipLaunchKernelGGL((q2_tbuild_kernel<64, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
-        HGV_LAUNCH_CHECK();
-        constexpr int NC = 32;
-        hipLaunchKernelGGL((q2_apply_kernel<64, 32, NC>), dim3(cdiv(m, NC)), dim3(256), 0, ctx->stream, n, m, b, g,
-                           J, ngrp, V2, T2, Y, ldy);
-    }
+    HGV_LAUNCH_CHECK();
+    if (b <= 32)
+        hipLaunchKernelGGL((q2_mfma_kernel<32>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
+                           V2, T2, Y, ldy);
+    else
+        hipLaunchKernelGGL((q2_mfma_kernel<64>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
+                           V2, T2, Y, ldy);
     HGV_LAUNCH_CHECK();
 }
 

@@ -69,13 +69,21 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
         if (r < rows) Ps[r][c] = a.P[row0 + r + (size_t)c * a.ldp];
     }
     if (j >= 0) {
-        // finish the reduction of the partial sums for column j (same order in every block)
-        if (tid < ncol) {
-            double2 acc = make_double2(0.0, 0.0);
-            for (int q = 0; q < a.G; ++q) acc = zadd(acc, a.part_in[(size_t)q * PNB + j + tid]);
-            s[tid] = acc;
-            r0v[tid] = a.row_in[j + tid];
+        // finish the reduction of the partial sums for column j: 4 threads per
+        // column sum interleaved quarters of the G partials (loads issued
+        // independently), then the quarters are added in a fixed order, so the
+        // result is the same in every block and from run to run
+        const int c = tid & 63, qq = tid >> 6;
+        double2 acc = make_double2(0.0, 0.0);
+        if (c < ncol) {
+            const double2 *src = a.part_in + j + c;
+#pragma unroll 8
+            for (int q = qq; q < a.G; q += 4) acc = zadd(acc, src[(size_t)q * PNB]);
         }
+        red[qq][c] = acc;
+        if (tid < ncol) r0v[tid] = a.row_in[j + tid];
+        __syncthreads();
+        if (tid < ncol) s[tid] = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
     }
     __syncthreads();
     if (j >= 0) {

@@ -115,6 +115,7 @@ struct ZGemm {
     double2 alpha = {1.0, 0.0}, beta = {0.0, 0.0};
     double2 *C = nullptr; int ldc = 1;
     int lower = 0;
+    int allow_split = 1;   // 0: never split K (lets C alias B when one tile spans n)
 };
 // Workspace for split-K partial sums reserved by every stage that calls zgemm.
 size_t zgemm_splitk_bytes(int n);
@@ -136,6 +137,7 @@ struct CGemm {
     float2 alpha = {1.0f, 0.0f}, beta = {0.0f, 0.0f};
     float2 *C = nullptr; int ldc = 1;
     int lower = 0;
+    int allow_split = 1;
 };
 void cgemm(hgv_ctx_s *ctx, const CGemm &g, float2 *splitk_ws, size_t splitk_bytes);
 

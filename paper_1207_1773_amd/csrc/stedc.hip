@@ -17,10 +17,10 @@
 //     two close entries are rotated so that one component of u vanishes and
 //     that entry deflates (the rotation is kept and later applied to Q);
 //   * each remaining root lies in (d_j, d_{j+1}) (the last in
-//     (d_k, d_k + rho |u|^2)); it is found by bisection on
+//     (d_k, d_k + rho |u|^2)); it is a zero of
 //     f(t) = 1 + rho sum u_i^2 / (delta_i - t) with t measured from the
-//     nearer pole (delta_i = d_i - d_origin exact), so t keeps full relative
-//     accuracy;
+//     nearer pole (delta_i = d_i - d_origin), so t keeps full relative
+//     accuracy; found by a bracketed two-pole rational model iteration;
 //   * the vector u is recomputed from the computed roots (Gu & Eisenstat,
 //     SIAM J. Matrix Anal. Appl. 16 (1995)):
 //       u_i^2 = prod_j (l_j - d_i) / (rho prod_{j != i} (d_j - d_i)),
@@ -256,7 +256,31 @@ __global__ void dc_m2_kernel(DcArgs A) {
     A.rhop[p] = rhop;
 }
 
-// M3: secular roots by bisection in the shifted variable.
+// M3: secular roots.  Root j lies in (d_j, d_{j+1}) (last root: right of d_k);
+// t is measured from the nearer pole (origin).  Each iteration fits the model
+//   f(x) ~ c + sL / (pL - x) + sR / (pR - x)
+// to the value and the two partial derivatives of f at the iterate (sL from
+// the terms at or left of the left pole, sR from the rest; pL, pR the poles of
+// the interval) and takes the model's root (a quadratic) as the next iterate;
+// a bracket [lo, hi] with f(lo) < 0 < f(hi) is kept, and the step falls back
+// to bisection when the model root leaves it or every fourth iteration.  The
+// iteration stops when |f| is below its rounding-error bound.
+__device__ inline void secular_eval(const double *dK, const double *zK, int kp, double dorg, double rho, double t,
+                                    int split, double &f, double &dl, double &dr, double &err) {
+    double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
+    for (int i = 0; i < kp; ++i) {
+        double del = (dK[i] - dorg) - t;
+        double q = zK[i] / del;
+        double term = zK[i] * q, dterm = q * q;
+        if (i <= split) { psi += term; dpsi += dterm; }
+        else { phi += term; dphi += dterm; }
+    }
+    f = 1.0 + rho * (psi + phi);
+    dl = rho * dpsi;
+    dr = rho * dphi;
+    err = 8.0 * DBL_EPSILON * (1.0 + rho * (fabs(psi) + fabs(phi)) + fabs(t) * (dl + dr)) * (double)(kp > 8 ? 8 : kp);
+}
+
 __global__ void dc_m3_kernel(DcArgs A) {
     int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= A.n) return;
@@ -282,16 +306,53 @@ __global__ void dc_m3_kernel(DcArgs A) {
         org = j; lo = 0.0; hi = rho * s2;
     }
     const double dorg = dK[org];
-    for (int it = 0; it < 400; ++it) {
-        double mid = 0.5 * (lo + hi);
-        if (mid <= lo || mid >= hi) break;
-        double f = 1.0;
-        for (int i = 0; i < kp; ++i) f += rho * zK[i] * zK[i] / ((dK[i] - dorg) - mid);
-        if (f < 0.0) lo = mid;
-        else hi = mid;
+    const bool last = (j == kp - 1);
+    const double pL = dK[j] - dorg;                          // left pole (relative)
+    const double pR = last ? 0.0 : dK[j + 1] - dorg;          // right pole (relative)
+    double t = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double f, sl, sr, err;
+        secular_eval(dK, zK, kp, dorg, rho, t, j, f, sl, sr, err);
+        if (fabs(f) <= err) break;
+        if (f < 0.0) lo = t;
+        else hi = t;
+        if (hi - lo <= 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+        double tn = 0.5 * (lo + hi);   // bisection fallback
+        if ((it & 3) != 3) {
+            // model weights from the derivatives at t
+            double aL = (pL - t), aR = (pR - t);
+            double wL = aL * aL * sl;                        // >= 0
+            if (last) {
+                double c = f - wL / aL;                      // model: c + wL / (pL - x) = 0
+                if (c > 0.0) tn = pL + wL / c;
+            } else {
+                double wR = aR * aR * sr;
+                double c = f - wL / aL - wR / aR;
+                double w = pR - pL;
+                // u = x - pL solves c u^2 - (c w + wL + wR) u + wL w = 0 on (0, w)
+                double qa = c, qb = -(c * w + wL + wR), qc = wL * w;
+                double disc = qb * qb - 4.0 * qa * qc;
+                if (disc >= 0.0) {
+                    double sq = sqrt(disc);
+                    double u;
+                    if (qa == 0.0) u = -qc / qb;
+                    else if (qb <= 0.0) {
+                        double u1 = (-qb + sq) / (2.0 * qa), u2 = (2.0 * qc) / (-qb + sq);
+                        u = (u2 > 0.0 && u2 < w) ? u2 : u1;
+                    } else {
+                        double u1 = (2.0 * qc) / (-qb - sq), u2 = (-qb - sq) / (2.0 * qa);
+                        u = (u1 > 0.0 && u1 < w) ? u1 : u2;
+                    }
+                    tn = pL + u;
+                }
+            }
+            if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        }
+        if (tn == t) break;
+        t = tn;
     }
     A.org[m.a + j] = org;
-    A.tau[m.a + j] = 0.5 * (lo + hi);
+    A.tau[m.a + j] = t;
 }
 
 // M4: Gu-Eisenstat recomputation of u from the computed roots.
