@@ -114,6 +114,22 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
                void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
                hgv_stats *stats);
 
+/* ---- batched solves ------------------------------------------------------- */
+/* Many independent pencils of uneven orders (the paper's target applications
+ * solve such problems many times).  Arrays of length `batch` live in HOST
+ * memory and hold per-problem sizes and DEVICE pointers with the meaning of
+ * hgv_zhegvx; nb may be NULL (default band width per order) or hold a band
+ * width per problem (e.g. from the autotuner of the Python package).  The
+ * problems run concurrently on streams owned by the context, forked from and
+ * joined back into the context's stream, so the whole call can be captured in
+ * one HIP graph.  d_info is a device array of `batch` ints. */
+int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu,
+                               const int *nb, size_t *bytes);
+int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *A, const int *lda,
+                       hgv_c128 *const *B, const int *ldb, const int *il, const int *iu, double *const *W,
+                       hgv_c128 *const *X, const int *ldx, const int *nb, void *work, size_t work_bytes,
+                       int *d_info);
+
 /* ---- stages (each one step of Algorithm 1 / Algorithm 2) ----------------- */
 /* Workspace bytes of one stage call below (stage = HGV_ST_*; m = number of
  * eigenvector columns where it matters, nb = band width where it matters). */
@@ -172,6 +188,27 @@ int hgv_zunmtr_q1(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *A, int ld
 /* Alg. 1 step 4: X <- L^-H X (X n x m, L lower from hgv_zpotrf). */
 int hgv_ztrsm_lh(hgv_ctx_t ctx, int n, int m, const hgv_c128 *L, int ldl, hgv_c128 *X,
                  int ldx, void *work, size_t work_bytes);
+
+/* ---- differentiable solve (reverse mode) ------------------------------------------ */
+/* Gauge fixing used by the differentiable solve: every column of X (n x m) is
+ * multiplied by a unit complex number so that its entry of largest modulus
+ * (the first one on ties) becomes real and positive. */
+int hgv_gauge_fix(hgv_ctx_t ctx, int n, int m, hgv_c128 *X, int ldx);
+
+int hgv_zhegvx_backward_bufsize(hgv_ctx_t ctx, int n, int il, int iu, size_t *bytes);
+
+/* Reverse mode of the selected pairs il..iu for the loss
+ *   L = sum_i Wbar_i lambda_i + Re sum_i Xbar_i^H x_i
+ * (first-order perturbation theory of A x = lambda B x with x^H B x = 1 and the
+ * gauge of hgv_gauge_fix).  Inputs: lambda (all n eigenvalues, ascending),
+ * Xall (n x n, all B-orthonormal eigenvectors; columns il..iu gauge fixed),
+ * Wbar (m doubles), Xbar (n x m).  Outputs: Abar, Bbar (n x n, Hermitian, full
+ * storage) such that dL = Re tr(Abar^H dA) + Re tr(Bbar^H dB) for Hermitian dA,
+ * dB.  Argument numbers for -i: ctx 1, n 2, il 3, iu 4, lambda 5, Xall 6,
+ * ldxa 7, Wbar 8, Xbar 9, ldxb 10, Abar 11, ldab 12, Bbar 13, ldbb 14, work 15. */
+int hgv_zhegvx_backward(hgv_ctx_t ctx, int n, int il, int iu, const double *lambda, const hgv_c128 *Xall,
+                        int ldxa, const double *Wbar, const hgv_c128 *Xbar, int ldxb, hgv_c128 *Abar, int ldab,
+                        hgv_c128 *Bbar, int ldbb, void *work, size_t work_bytes);
 
 /* ---- building block -------------------------------------------------------- */
 /* C <- alpha op(A) op(B) + beta C on the MFMA tiles the stages use.

@@ -28,7 +28,8 @@ EXPORTS = [
     "hgv_create", "hgv_destroy", "hgv_set_stream", "hgv_status_string", "hgv_last_hip_error",
     "hgv_default_nb", "hgv_zhegvx_bufsize", "hgv_zhegvx", "hgv_stage_bufsize", "hgv_zpotrf",
     "hgv_zhegst", "hgv_zhe2hb", "hgv_zhb2st", "hgv_v2_elems", "hgv_v2_taus", "hgv_dstedc",
-    "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm",
+    "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_gauge_fix",
+    "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
 ]
 
 
@@ -99,6 +100,11 @@ def load():
         "hgv_zunmtr_q1": (I, [P, I, I, I, P, I, P, P, I, P, SZ]),
         "hgv_ztrsm_lh": (I, [P, I, I, P, I, P, I, P, SZ]),
         "hgv_zgemm": (I, [P, ctypes.c_char, ctypes.c_char, I, I, I, c128, P, I, P, I, c128, P, I]),
+        "hgv_gauge_fix": (I, [P, I, I, P, I]),
+        "hgv_zhegvx_backward_bufsize": (I, [P, I, I, I, ctypes.POINTER(SZ)]),
+        "hgv_zhegvx_backward": (I, [P, I, I, I, P, P, I, P, P, I, P, I, P, I, P, SZ]),
+        "hgv_zhegvx_batched_bufsize": (I, [P, I, P, P, P, P, ctypes.POINTER(SZ)]),
+        "hgv_zhegvx_batched": (I, [P, I, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -126,6 +132,14 @@ def hgv_destroy(ctx):
 
 def hgv_set_stream(ctx, stream):
     _check(load().hgv_set_stream(ctx, stream), "hgv_set_stream")
+
+
+def hgv_status_string(status):
+    return load().hgv_status_string(status).decode()
+
+
+def hgv_last_hip_error(ctx):
+    return load().hgv_last_hip_error(ctx)
 
 
 def hgv_default_nb(n, precision=HGV_FP64):
@@ -198,6 +212,45 @@ def hgv_zgemm(ctx, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
     _check(load().hgv_zgemm(ctx, opa.encode(), opb.encode(), m, n, k, a, A, lda, B, ldb, b, C, ldc), "hgv_zgemm")
 
 
+def hgv_gauge_fix(ctx, n, m, X, ldx):
+    _check(load().hgv_gauge_fix(ctx, n, m, X, ldx), "hgv_gauge_fix")
+
+
+def hgv_zhegvx_backward_bufsize(ctx, n, il, iu):
+    out = SZ()
+    _check(load().hgv_zhegvx_backward_bufsize(ctx, n, il, iu, ctypes.byref(out)), "hgv_zhegvx_backward_bufsize")
+    return out.value
+
+
+def hgv_zhegvx_backward(ctx, n, il, iu, lam, Xall, ldxa, Wbar, Xbar, ldxb, Abar, ldab, Bbar, ldbb, work, work_bytes):
+    _check(load().hgv_zhegvx_backward(ctx, n, il, iu, lam, Xall, ldxa, Wbar, Xbar, ldxb, Abar, ldab, Bbar, ldbb,
+                                      work, work_bytes), "hgv_zhegvx_backward")
+
+
+def _iarr(vals):
+    return (ctypes.c_int * len(vals))(*vals)
+
+
+def _parr(vals):
+    return (ctypes.c_void_p * len(vals))(*vals)
+
+
+def hgv_zhegvx_batched_bufsize(ctx, n, il, iu, nb=None):
+    out = SZ()
+    _check(load().hgv_zhegvx_batched_bufsize(ctx, len(n), _iarr(n), _iarr(il), _iarr(iu),
+                                             _iarr(nb) if nb is not None else None, ctypes.byref(out)),
+           "hgv_zhegvx_batched_bufsize")
+    return out.value
+
+
+def hgv_zhegvx_batched(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, nb, work, work_bytes, d_info):
+    _check(load().hgv_zhegvx_batched(ctx, len(n), _iarr(n), _parr(A), _iarr(lda), _parr(B), _iarr(ldb), _iarr(il),
+                                     _iarr(iu), _parr(W), _parr(X), _iarr(ldx),
+                                     _iarr(nb) if nb is not None else None, work, work_bytes, d_info),
+           "hgv_zhegvx_batched")
+
+
 # ---- torch marshalling ---------------------------------------------------------------------
 from . import tensors  # noqa: E402  (torch-facing helpers)
 from .tensors import Context, eigh, colmajor, from_colmajor  # noqa: E402,F401
+from .autograd import EighGeneralized, eigh_differentiable  # noqa: E402,F401

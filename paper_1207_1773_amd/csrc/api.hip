@@ -200,6 +200,9 @@ int hgv_create(hgv_ctx_t *ctx, int device) {
 int hgv_destroy(hgv_ctx_t ctx) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
     (void)hipSetDevice(ctx->device);
+    for (hipStream_t st : ctx->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t e : ctx->side_ev) (void)hipEventDestroy(e);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->ev_pending) {
         (void)hipEventDestroy(p.first);
@@ -521,6 +524,177 @@ int hgv_zgemm(hgv_ctx_t ctx, char opa, char opb, int m, int n, int k, hgv_c128 a
         g.beta = make_double2(beta.re, beta.im);
         g.C = reinterpret_cast<double2 *>(C); g.ldc = ldc;
         zgemm(ctx, g, nullptr, 0);
+        return HGV_OK;
+    });
+}
+
+// ---- batched solves ----------------------------------------------------------------------
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static int batch_nb(const int *nb, int i, int n) {
+    return (nb && nb[i] > 0) ? nb[i] : hgv_default_nb(n, HGV_FP64);
+}
+
+int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu, const int *nb,
+                               size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (batch < 0) return -2;
+    if (batch > 0 && (!n || !il || !iu)) return -3;
+    if (!bytes) return -7;
+    *bytes = 0;
+    size_t total = 256;
+    for (int i = 0; i < batch; ++i) {
+        if (n[i] < 0) return -3;
+        if (n[i] == 0) continue;
+        if (il[i] < 1 || il[i] > n[i] || iu[i] < il[i] || iu[i] > n[i]) return -4;
+        int b = batch_nb(nb, i, n[i]);
+        if (b > 64) return -6;
+        hgv_opts o{HGV_FP64, b, 0, 0.0};
+        size_t need = 0;
+        int st = hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &need);
+        if (st != HGV_OK) return st;
+        total += align256(need);
+    }
+    *bytes = total;
+    return HGV_OK;
+}
+
+int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *A, const int *lda,
+                       hgv_c128 *const *B, const int *ldb, const int *il, const int *iu, double *const *W,
+                       hgv_c128 *const *X, const int *ldx, const int *nb, void *work, size_t work_bytes,
+                       int *d_info) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (batch < 0) return -2;
+    if (batch == 0) return HGV_OK;
+    if (!n || !A || !lda || !B || !ldb || !il || !iu || !W || !X || !ldx) return -3;
+    for (int i = 0; i < batch; ++i) {
+        const int nn = std::max(1, n[i]);
+        if (n[i] < 0) return -3;
+        if (lda[i] < nn || ldb[i] < nn || ldx[i] < nn) return -5;
+        if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || !X[i])) return -4;
+    }
+    size_t need = 0;
+    int st = hgv_zhegvx_batched_bufsize(ctx, batch, n, il, iu, nb, &need);
+    if (st != HGV_OK) return st;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -15;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        const int K = 8;
+        if (ctx->side.empty()) {
+            for (int k = 0; k < K; ++k) {
+                hipStream_t s;
+                hipEvent_t e;
+                HGV_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+                HGV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                ctx->side.push_back(s);
+                ctx->side_ev.push_back(e);
+            }
+            HGV_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+        }
+        // workspace slices in problem order; problems dealt longest first to the
+        // least loaded stream (estimated cost ~ n^3)
+        std::vector<size_t> off(batch, 0);
+        size_t at = 0;
+        for (int i = 0; i < batch; ++i) {
+            off[i] = at;
+            if (n[i] == 0) continue;
+            hgv_opts o{HGV_FP64, batch_nb(nb, i, n[i]), 0, 0.0};
+            size_t b = 0;
+            (void)hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &b);
+            at += align256(b);
+        }
+        std::vector<int> order(batch);
+        for (int i = 0; i < batch; ++i) order[i] = i;
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return n[x] > n[y]; });
+        std::vector<double> load(K, 0.0);
+        hipStream_t user = ctx->stream;
+        HGV_HIP(hipEventRecord(ctx->fork_ev, user));
+        for (int k = 0; k < K; ++k) HGV_HIP(hipStreamWaitEvent(ctx->side[k], ctx->fork_ev, 0));
+        try {
+            for (int idx : order) {
+                int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[k] += (double)n[idx] * n[idx] * n[idx];
+                ctx->stream = ctx->side[k];
+                int *inf = d_info ? d_info + idx : nullptr;
+                if (n[idx] == 0) {
+                    set_info(ctx, inf, 0);
+                    continue;
+                }
+                Arena ar(static_cast<char *>(work) + off[idx], work_bytes - off[idx]);
+                zhegvx_fp64(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx],
+                            reinterpret_cast<double2 *>(B[idx]), ldb[idx], il[idx], iu[idx], W[idx],
+                            reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, batch_nb(nb, idx, n[idx]), inf, nullptr);
+            }
+        } catch (...) {
+            ctx->stream = user;
+            throw;
+        }
+        ctx->stream = user;
+        for (int k = 0; k < K; ++k) {
+            HGV_HIP(hipEventRecord(ctx->side_ev[k], ctx->side[k]));
+            HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));
+        }
+        return HGV_OK;
+    });
+}
+
+int hgv_gauge_fix(hgv_ctx_t ctx, int n, int m, hgv_c128 *X, int ldx) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (m < 0) return -3;
+    if (n > 0 && m > 0 && !X) return -4;
+    if (ldx < std::max(1, n)) return -5;
+    return guarded(ctx, [&]() {
+        gauge_fix_run(ctx, n, m, reinterpret_cast<double2 *>(X), ldx);
+        return HGV_OK;
+    });
+}
+
+int hgv_zhegvx_backward_bufsize(hgv_ctx_t ctx, int n, int il, int iu, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && (il < 1 || il > n)) return -3;
+    if (n > 0 && (iu < il || iu > n)) return -4;
+    if (!bytes) return -5;
+    *bytes = 0;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        adjoint_run(ctx, n, il, iu, nullptr, nullptr, n, nullptr, nullptr, n, nullptr, n, nullptr, n, ar);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_zhegvx_backward(hgv_ctx_t ctx, int n, int il, int iu, const double *lambda, const hgv_c128 *Xall, int ldxa,
+                        const double *Wbar, const hgv_c128 *Xbar, int ldxb, hgv_c128 *Abar, int ldab, hgv_c128 *Bbar,
+                        int ldbb, void *work, size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    const int nn = std::max(1, n);
+    if (n > 0 && (il < 1 || il > n)) return -3;
+    if (n > 0 && (iu < il || iu > n)) return -4;
+    if (n > 0 && !lambda) return -5;
+    if (n > 0 && !Xall) return -6;
+    if (ldxa < nn) return -7;
+    if (n > 0 && !Wbar) return -8;
+    if (n > 0 && !Xbar) return -9;
+    if (ldxb < nn) return -10;
+    if (n > 0 && !Abar) return -11;
+    if (ldab < nn) return -12;
+    if (n > 0 && !Bbar) return -13;
+    if (ldbb < nn) return -14;
+    size_t need = 0;
+    int st = hgv_zhegvx_backward_bufsize(ctx, n, il, iu, &need);
+    if (st != HGV_OK) return st;
+    if (n == 0) return HGV_OK;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -15;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        adjoint_run(ctx, n, il, iu, lambda, reinterpret_cast<const double2 *>(Xall), ldxa, Wbar,
+                    reinterpret_cast<const double2 *>(Xbar), ldxb, reinterpret_cast<double2 *>(Abar), ldab,
+                    reinterpret_cast<double2 *>(Bbar), ldbb, ar);
         return HGV_OK;
     });
 }

@@ -17,8 +17,8 @@
 // triangle with offsets 0 .. 2b-1 (the bulge reaches offset 2b-1):
 // element (r, c), r >= c, at AB[(r - c) + c * 2b].
 //
-// Parallel schedule (one persistent workgroup per sweep at a time, sweeps
-// dealt round-robin): task (s, j) touches rows/columns that overlap those of
+// Parallel schedule (a workgroup runs one sweep at a time and takes the next
+// sweep from a ticket counter): task (s, j) touches rows/columns that overlap those of
 // task (s-1, j+1) but of no later task of sweep s-1, so it starts once sweep
 // s-1 has completed min(j+2, all) tasks.  Tasks that may run concurrently
 // touch disjoint data, and every task's arithmetic is fixed, so the result
@@ -39,22 +39,25 @@
 
 namespace hgv {
 
+template <class E>
 struct HbArgs {
     int n, b, ldb;
-    double2 *AB;          // band storage, ldb = 2b
-    double2 *V2;          // group-major reflectors
-    double2 *tau2;
+    E *AB;                // band storage, ldb = 2b
+    E *V2;                // group-major reflectors
+    E *tau2;
     int *prog;            // tasks completed per sweep
     int *err;             // set when a wait gives up
+    int *ticket;          // next sweep to take
     int J;                // tasks of sweep 0 (max over sweeps)
 };
 
 __host__ __device__ inline int hb_tasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
 
-__device__ inline double2 band_get(const double2 *AB, int ldb, int r, int c) {
+template <class E>
+__device__ inline double2 band_get(const E *AB, int ldb, int r, int c) {
     // element (r, c) of the Hermitian band (r, c in range, |r - c| < ldb)
-    if (r >= c) return AB[(r - c) + (size_t)c * ldb];
-    double2 v = AB[(c - r) + (size_t)r * ldb];
+    if (r >= c) return El<E>::to(AB[(r - c) + (size_t)c * ldb]);
+    double2 v = El<E>::to(AB[(c - r) + (size_t)r * ldb]);
     return make_double2(v.x, -v.y);
 }
 
@@ -82,8 +85,8 @@ __device__ inline double2 group_sum(double2 x) {
 //   E (rows I_j, columns I_{j-1}) lives in LDS because it is used by rows (the
 //   right application of the previous reflector) and then by columns (the
 //   left application of the new one).
-template <int BM>
-__global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
+template <int BM, class E>
+__global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
     constexpr int TPR = 256 / BM;   // lanes per row
     constexpr int NU = BM / TPR;    // row elements per lane
     __shared__ double2 Es[BM][BM + 1];
@@ -93,11 +96,22 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int row = tid / TPR, q = tid % TPR;
     const int n = a.n, b = a.b, ldb = a.ldb;
-    double2 *AB = a.AB;
+    E *AB = a.AB;
     const double2 zero = make_double2(0.0, 0.0);
+    auto bld = [&](size_t idx) -> double2 { return El<E>::to(AB[idx]); };
+    auto bst = [&](size_t idx, double2 v) { AB[idx] = El<E>::from(v); };
     double2 Dr[NU];
+    __shared__ int sh_sweep;
 
-    for (int s = blockIdx.x; s < n - 1; s += gridDim.x) {
+    for (;;) {
+        // take the next sweep; a sweep only waits for its predecessor, which was
+        // taken earlier by a workgroup that is already running, so the lowest
+        // unfinished sweep always progresses whatever the residency
+        if (tid == 0) sh_sweep = atomicAdd(a.ticket, 1);
+        __syncthreads();
+        const int s = sh_sweep;
+        __syncthreads();
+        if (s >= n - 1) break;
         const int nt = hb_tasks(n, b, s);
         for (int j = 0; j < nt; ++j) {
             // ---- wait for sweep s-1 ------------------------------------------------
@@ -126,12 +140,12 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
                 Dr[u] = (row < L && k < L) ? band_get(AB, ldb, r0 + row, r0 + k) : zero;
             }
             if (j == 0) {
-                if (tid < BM) Es[tid][0] = (tid < L) ? AB[(r0 + tid - s) + (size_t)s * ldb] : zero;
+                if (tid < BM) Es[tid][0] = (tid < L) ? bld((r0 + tid - s) + (size_t)s * ldb) : zero;
             } else {
 #pragma unroll
                 for (int t = tid; t < BM * BM; t += 256) {
                     int i = t % BM, c = t / BM;
-                    Es[i][c] = (i < L && c < b) ? AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] : zero;
+                    Es[i][c] = (i < L && c < b) ? bld((r0 + i - p0 - c) + (size_t)(p0 + c) * ldb) : zero;
                 }
             }
             __syncthreads();
@@ -180,7 +194,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
             const double2 tau = sh_tau;
             const double beta = sh_beta;
             if (j == 0) {
-                if (tid < L) AB[(r0 + tid - s) + (size_t)s * ldb] = (tid == 0) ? make_double2(beta, 0.0) : zero;
+                if (tid < L) bst((r0 + tid - s) + (size_t)s * ldb, (tid == 0) ? make_double2(beta, 0.0) : zero);
             } else {
                 // E[:, 1:] <- E - conj(tau) v (v^H E);  E[:, 0] = beta e_1   (column owners)
                 const int c = row;   // lane group -> column
@@ -198,7 +212,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
                         if (i < L) {
                             double2 val = (c == 0) ? (i == 0 ? make_double2(beta, 0.0) : zero)
                                                    : zsub(Es[i][c], zmul(v[i], wc));
-                            AB[(r0 + i - p0 - c) + (size_t)(p0 + c) * ldb] = val;
+                            bst((r0 + i - p0 - c) + (size_t)(p0 + c) * ldb, val);
                         }
                     }
                 }
@@ -225,7 +239,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
                             double2 wk = zsub(pv[k], zscale(half, v[k]));
                             double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(v[k])));
                             if (k == row) val.y = 0.0;
-                            AB[(row - k) + (size_t)(r0 + k) * ldb] = val;
+                            bst((row - k) + (size_t)(r0 + k) * ldb, val);
                         }
                     }
                 }
@@ -234,8 +248,8 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
             {
                 const int B = s / b, t = s % b;
                 size_t base = ((size_t)B * a.J + j) * b + t;
-                if (tid < b) a.V2[base * b + tid] = v[tid];
-                if (tid == 0) a.tau2[base] = tau;
+                if (tid < b) a.V2[base * b + tid] = El<E>::from(v[tid]);
+                if (tid == 0) a.tau2[base] = El<E>::from(tau);
             }
             __syncthreads();
             if (tid < BM) vp[tid] = v[tid];
@@ -248,26 +262,29 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs a) {
 }
 
 // Copy the lower band (offsets 0..b) of A into band storage; offsets b+1..2b-1 zero.
-__global__ void band_copy_kernel(int n, int b, const double2 *A, int lda, double2 *AB, int ldb) {
+template <class E>
+__global__ void band_copy_kernel(int n, int b, const E *A, int lda, E *AB, int ldb) {
     int off = threadIdx.x % ldb;
     int c = blockIdx.x * (256 / ldb) + threadIdx.x / ldb;
     if (threadIdx.x >= (256 / ldb) * ldb || c >= n) return;
     int r = c + off;
-    double2 v = make_double2(0.0, 0.0);
+    E v = El<E>::mk(0.0, 0.0);
     if (off <= b && r < n) v = A[r + (size_t)c * lda];
-    if (off == 0) v.y = 0.0;
+    if (off == 0) v.y = 0;
     AB[off + (size_t)c * ldb] = v;
 }
 
-__global__ void tridiag_out_kernel(int n, const double2 *AB, int ldb, double *d, double *e) {
+template <class E>
+__global__ void tridiag_out_kernel(int n, const E *AB, int ldb, double *d, double *e) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) d[i] = AB[(size_t)i * ldb].x;
     if (i < n - 1) e[i] = AB[1 + (size_t)i * ldb].x;
 }
 
-__global__ void zero2_kernel(double2 *p, size_t cnt) {
+template <class E>
+__global__ void zero2_kernel(E *p, size_t cnt) {
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    for (; i < cnt; i += (size_t)gridDim.x * blockDim.x) p[i] = make_double2(0.0, 0.0);
+    for (; i < cnt; i += (size_t)gridDim.x * blockDim.x) p[i] = El<E>::mk(0.0, 0.0);
 }
 __global__ void zero_int_kernel(int *p, int cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,66 +297,73 @@ static int hb_nblk(int n, int b) { return n >= 2 ? cdiv(n - 1, b) : 0; }
 size_t v2_elems(int n, int nb) { return std::max<size_t>((size_t)hb_nblk(n, nb) * hb_J(n, nb) * nb * nb, 1); }
 size_t v2_taus(int n, int nb) { return std::max<size_t>((size_t)hb_nblk(n, nb) * hb_J(n, nb) * nb, 1); }
 
-static void zero2(hgv_ctx_s *ctx, double2 *p, size_t cnt) {
+template <class E>
+static void zero2(hgv_ctx_s *ctx, E *p, size_t cnt) {
     if (!cnt) return;
-    hipLaunchKernelGGL(zero2_kernel, dim3((unsigned)std::min<size_t>(cdivz(cnt, 256), 16384)), dim3(256), 0,
+    hipLaunchKernelGGL(zero2_kernel<E>, dim3((unsigned)std::min<size_t>(cdivz(cnt, 256), 16384)), dim3(256), 0,
                        ctx->stream, p, cnt);
     HGV_LAUNCH_CHECK();
 }
 
-template <int BM>
-static void launch_hb2st(hgv_ctx_s *ctx, HbArgs &a) {
+template <int BM, class E>
+static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
     int dev = ctx->device, cus = 0, per = 0;
     HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM>, 256, 0));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM, E>, 256, 0));
     // a sweep starts two tasks behind its predecessor, so about J/2 sweeps are
     // in flight at once; more workgroups would only poll
     int G = std::max(1, std::min({cus * std::max(per, 1), a.n - 1, a.J / 2 + 4}));
-    void *args[] = {&a};
-    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM>), dim3(G), dim3(256), args, 0,
-                                       ctx->stream));
+    hipLaunchKernelGGL((hb2st_kernel<BM, E>), dim3(G), dim3(256), 0, ctx->stream, a);
+    HGV_LAUNCH_CHECK();
 }
 
-void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e, double2 *V2,
-               double2 *tau2, Arena &ar) {
+template <class E>
+void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar) {
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
     const int b = nb, ldb = 2 * nb;
-    double2 *AB = ar.take<double2>((size_t)ldb * std::max(n, 1));
-    int *prog = ar.take<int>(std::max(n, 1));
-    int *err = ar.take<int>(1);
+    E *AB = ar.take<E>((size_t)ldb * std::max(n, 1));
+    int *prog = ar.take<int>(std::max(n, 1) + 2);
+    int *err = prog + std::max(n, 1);
+    int *ticket = err + 1;
     if (ar.measuring() || n == 0) return;
-    hipLaunchKernelGGL(band_copy_kernel, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB, ldb);
+    hipLaunchKernelGGL(band_copy_kernel<E>, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB,
+                       ldb);
     HGV_LAUNCH_CHECK();
     zero2(ctx, V2, v2_elems(n, nb));
     zero2(ctx, tau2, v2_taus(n, nb));
-    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, ctx->stream, prog, n);
-    HGV_LAUNCH_CHECK();
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, ctx->stream, err, 1);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 2, 256)), dim3(256), 0, ctx->stream, prog, std::max(n, 1) + 2);
     HGV_LAUNCH_CHECK();
     if (n >= 2) {
-        HbArgs a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
-        if (b <= 32) launch_hb2st<32>(ctx, a);
-        else launch_hb2st<64>(ctx, a);
+        HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, ticket, hb_J(n, b)};
+        if (b <= 32) launch_hb2st<32, E>(ctx, a);
+        else launch_hb2st<64, E>(ctx, a);
     }
-    hipLaunchKernelGGL(tridiag_out_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
+    hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
     HGV_LAUNCH_CHECK();
 }
+
+template void hb2st_t<double2>(hgv_ctx_s *, int, int, const double2 *, int, double *, double *, double2 *, double2 *,
+                               Arena &);
+template void hb2st_t<float2>(hgv_ctx_s *, int, int, const float2 *, int, double *, double *, float2 *, float2 *,
+                              Arena &);
 
 // ---- Q2 back-transformation ------------------------------------------------------------------
 // Groups hold g <= b consecutive sweeps at one step j (any g <= b keeps every
 // pair of overlapping reflectors in order).  Reflector t of group (B, j) is
 // H_{B*g + t, j}; it occupies local rows t .. t+b-1 of the group, whose first
 // row is B*g + 1 + j*b.
-__device__ inline const double2 *v2_ptr(const double2 *V2, int b, int J, int s, int j) {
+template <class E>
+__device__ inline const E *v2_ptr(const E *V2, int b, int J, int s, int j) {
     return V2 + (((size_t)(s / b) * J + j) * b + (s % b)) * b;
 }
 __device__ inline size_t tau2_idx(int b, int J, int s, int j) { return ((size_t)(s / b) * J + j) * b + (s % b); }
 
 // T of every group: G[t1][t2] = sum_rows conj(V[row][t1]) V[row][t2] over the
 // overlap rows [t2, t1+b-1]; T_tt = tau_t, T[0:t, t] = -tau_t T[0:t, 0:t] G[0:t, t].
-template <int BMAX, int GMAX>
-__global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int J, const double2 *V2,
-                                                         const double2 *tau2, double2 *T2) {
+// The recurrence runs in double whatever the storage type.
+template <int BMAX, int GMAX, class E>
+__global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int J, const E *V2, const E *tau2,
+                                                         E *T2) {
     __shared__ double2 Vs[GMAX][BMAX + 1];
     __shared__ double2 Gs[GMAX][GMAX + 1];
     __shared__ double2 Ts[GMAX][GMAX + 1];
@@ -350,11 +374,11 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int
     for (int t = tid; t < g * b; t += 256) {
         int tt = t / b, i = t % b;
         int s = B * g + tt;
-        Vs[tt][i] = (s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : make_double2(0.0, 0.0);
+        Vs[tt][i] = (s <= n - 2) ? El<E>::to(v2_ptr(V2, b, J, s, j)[i]) : make_double2(0.0, 0.0);
     }
     if (tid < g) {
         int s = B * g + tid;
-        taus[tid] = (s <= n - 2) ? tau2[tau2_idx(b, J, s, j)] : make_double2(0.0, 0.0);
+        taus[tid] = (s <= n - 2) ? El<E>::to(tau2[tau2_idx(b, J, s, j)]) : make_double2(0.0, 0.0);
     }
     for (int t = tid; t < GMAX * GMAX; t += 256) Ts[t / GMAX][t % GMAX] = make_double2(0.0, 0.0);
     __syncthreads();
@@ -376,52 +400,78 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int
         if (tid == 0) Ts[c][c] = tc;
         __syncthreads();
     }
-    double2 *tout = T2 + (size_t)grp * g * g;
-    for (int t = tid; t < g * g; t += 256) tout[t] = Ts[t % g][t / g];   // column-major g x g
+    E *tout = T2 + (size_t)grp * g * g;
+    for (int t = tid; t < g * g; t += 256) tout[t] = El<E>::from(Ts[t % g][t / g]);   // column-major g x g
 }
 
-// Y (n x m) <- Q2 Y on MFMA tiles.  Workgroup = 16 columns of Y (so two or
-// three workgroups share a CU and hide each other's latencies); for every
-// group (walked from the last group of sweeps to the first, j ascending):
+// Y (n x m) <- Q2 Y (or Q2^H Y) on MFMA tiles.  Workgroup = 16 columns of Y (so
+// two or three workgroups share a CU and hide each other's latencies); for
+// every group, walked from the last group of sweeps to the first with j
+// ascending for Q2 (first to last, j descending, for Q2^H):
 //   W = V^H Y_rows  (two 16x16 tiles, the k range split over the 4 waves),
-//   W <- T W        (two tiles),
+//   W <- T W        (T^H W for Q2^H; two tiles),
 //   Y_rows -= V W   (six row tiles).
-// v_mfma_f64_16x16x4f64 does the products (four real products per complex
-// block).  V (the (g+b-1) x g parallelogram, column t non-zero on rows
-// t .. t+b-1) and T are read from memory straight into operand registers
-// (they are shared by all workgroups and stay in L2); only the Y rows and W
-// live in LDS.  k-steps of tiles that are entirely zero are skipped.
+// A complex block product is four real MFMAs: v_mfma_f64_16x16x4f64 for double
+// storage, v_mfma_f32_16x16x4f32 (fp32 accumulation) for float storage.  V (the
+// (g+b-1) x g parallelogram, column t non-zero on rows t .. t+b-1) and T are
+// read from memory straight into operand registers (they are shared by all
+// workgroups and stay in L2); only the Y rows and W live in LDS.  k-steps of
+// tiles that are entirely zero are skipped.
 typedef double q2v4d __attribute__((ext_vector_type(4)));
+typedef float q2v4f __attribute__((ext_vector_type(4)));
 
-__device__ inline void q2_cmfma(double2 a, double2 b, q2v4d &re, q2v4d &im) {
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, re, 0, 0, 0);
-    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, re, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, im, 0, 0, 0);
-    im = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, im, 0, 0, 0);
+template <class E> struct Q2M;
+template <> struct Q2M<double2> {
+    typedef q2v4d Acc;
+    __device__ static Acc mfma(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // lane l, register r of the 16x16 result -> row l/16 + 4r, column l%16
+    __device__ static int orow(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Q2M<float2> {
+    typedef q2v4f Acc;
+    __device__ static Acc mfma(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // lane l, register r of the 16x16 result -> row 4(l/16) + r, column l%16
+    __device__ static int orow(int lk, int r) { return 4 * lk + r; }
+};
+
+template <class E>
+__device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &re, typename Q2M<E>::Acc &im) {
+    re = Q2M<E>::mfma(a.x, b.x, re);
+    re = Q2M<E>::mfma(-a.y, b.y, re);
+    im = Q2M<E>::mfma(a.x, b.y, im);
+    im = Q2M<E>::mfma(a.y, b.x, im);
 }
 
-template <int BMAX>
-__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp,
-                                                       const double2 *V2, const double2 *T2, double2 *Y, int ldy) {
+template <int BMAX, class E>
+__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
+                                                       const E *V2, const E *T2, E *Y, int ldy) {
+    typedef typename Q2M<E>::Acc Acc;
     constexpr int NC = 16, GM = 32, RM = 96;
     constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
-    __shared__ double2 Ys[RM][NC + 1];
-    __shared__ double2 Wp[2][GM][NC + 1];     // partial W over the two k halves
-    __shared__ double2 W2[GM][NC + 1];
+    __shared__ E Ys[RM][NC + 1];
+    __shared__ E Wp[2][GM][NC + 1];           // partial W over the two k halves
+    __shared__ E W2[GM][NC + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int c0 = blockIdx.x * NC;
     const int nc = min(NC, m - c0);
-    const double2 zero = make_double2(0.0, 0.0);
-    for (int B = ngrp - 1; B >= 0; --B) {
+    const E zero = El<E>::mk(0.0, 0.0);
+    for (int Bi = 0; Bi < ngrp; ++Bi) {
+        const int B = adj ? Bi : ngrp - 1 - Bi;
         const int s0 = B * g;
-        for (int j = 0; j < J; ++j) {
+        // rows start at s0 + 1 + j b; the last step with rows left is j = jn - 1
+        const int jn = min(J, (n - 2 - s0) / b + 1);
+        for (int ji = 0; ji < jn; ++ji) {
+            const int j = adj ? jn - 1 - ji : ji;
             const int R0 = s0 + 1 + j * b;
-            if (R0 > n - 1) break;
             const int nrows = min(g + b - 1, n - R0);
-            const double2 *tg = T2 + ((size_t)B * J + j) * g * g;
+            const E *tg = T2 + ((size_t)B * J + j) * g * g;
             // element (r, t) of the parallelogram V
-            auto vget = [&](int r, int t) -> double2 {
+            auto vget = [&](int r, int t) -> E {
                 int i = r - t, s = s0 + t;
                 return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
             };
@@ -435,66 +485,76 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
             const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
             const int ka = (nks + 1) / 2;
             const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
-            double2 a1[K1];
+            E a1[K1];
 #pragma unroll
             for (int q = 0; q < K1; ++q) {
                 int kq = kbeg + q;
-                double2 v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
-                a1[q] = make_double2(v.x, -v.y);   // conj(V)
+                E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
+                a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
             }
             __syncthreads();
             {
-                q2v4d re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
 #pragma unroll
                 for (int q = 0; q < K1; ++q) {
                     int kq = kbeg + q;
-                    if (kq < kend) q2_cmfma(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
+                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Wp[kh][t0 + lk + 4 * i][lr] = make_double2(re[i], im[i]);
+                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
             }
             __syncthreads();
-            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]); T upper triangular
+            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
+            // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
             if (wave < 2) {
-                q2v4d re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-                for (int l4 = t0; l4 < GM; l4 += 4) {
+                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
+                for (int l4 = lbeg; l4 < lend; l4 += 4) {
                     int row = t0 + lr, col = l4 + lk;
-                    double2 tv = (row < g && col < g) ? tg[row + col * g] : zero;
-                    double2 w = zadd(Wp[0][l4 + lk][lr], Wp[1][l4 + lk][lr]);
-                    q2_cmfma(tv, w, re, im);
+                    E tv = zero;
+                    if (row < g && col < g) {
+                        if (adj) {
+                            E u = tg[col + row * g];
+                            tv = El<E>::mk(u.x, -u.y);
+                        } else {
+                            tv = tg[row + col * g];
+                        }
+                    }
+                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
+                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) W2[t0 + lk + 4 * i][lr] = make_double2(re[i], im[i]);
+                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
             }
             __syncthreads();
             // step 3: Y_rows -= V W2, row tiles wave and wave + 4
             for (int q = wave; q < 6; q += 4) {
                 const int r0 = 16 * q;
                 if (r0 >= nrows) continue;
-                q2v4d re, im;
+                Acc re, im;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    double2 y = Ys[r0 + lk + 4 * i][lr];
+                    E y = Ys[r0 + Q2M<E>::orow(lk, i)][lr];
                     re[i] = y.x;
                     im[i] = y.y;
                 }
                 const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-                double2 a3[8];
+                E a3[8];
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     int t4 = tlo + 4 * u;
-                    double2 v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
-                    a3[u] = make_double2(-v.x, -v.y);
+                    E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
+                    a3[u] = El<E>::mk(-v.x, -v.y);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     int t4 = tlo + 4 * u;
-                    if (t4 < thi) q2_cmfma(a3[u], W2[t4 + lk][lr], re, im);
+                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    int r = r0 + lk + 4 * i;
-                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = make_double2(re[i], im[i]);
+                    int r = r0 + Q2M<E>::orow(lk, i);
+                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(re[i], im[i]);
                 }
             }
         }
@@ -503,27 +563,33 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
 
 static int q2_group(int b) { return std::min(b, 32); }
 
-void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2, double2 *Y,
-                  int ldy, Arena &ar) {
+template <class E>
+void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
+                Arena &ar) {
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
     const int b = nb, g = q2_group(b);
     const int J = hb_J(n, b), ngrp = n >= 2 ? cdiv(n - 1, g) : 0;
-    double2 *T2 = ar.take<double2>(std::max<size_t>((size_t)ngrp * J * g * g, 1));
+    E *T2 = ar.take<E>(std::max<size_t>((size_t)ngrp * J * g * g, 1));
     if (ar.measuring() || n < 2 || m == 0) return;
     if (b <= 32)
-        hipLaunchKernelGGL((q2_tbuild_kernel<32, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
+        hipLaunchKernelGGL((q2_tbuild_kernel<32, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     else
-        hipLaunchKernelGGL((q2_tbuild_kernel<64, 32>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
+        hipLaunchKernelGGL((q2_tbuild_kernel<64, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     HGV_LAUNCH_CHECK();
     if (b <= 32)
-        hipLaunchKernelGGL((q2_mfma_kernel<32>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
-                           V2, T2, Y, ldy);
+        hipLaunchKernelGGL((q2_mfma_kernel<32, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J,
+                           ngrp, (int)adj, V2, T2, Y, ldy);
     else
-        hipLaunchKernelGGL((q2_mfma_kernel<64>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
-                           V2, T2, Y, ldy);
+        hipLaunchKernelGGL((q2_mfma_kernel<64, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J,
+                           ngrp, (int)adj, V2, T2, Y, ldy);
     HGV_LAUNCH_CHECK();
 }
+
+template void unmtr_q2_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, const double2 *, double2 *, int, bool,
+                                  Arena &);
+template void unmtr_q2_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, const float2 *, float2 *, int, bool,
+                                 Arena &);
 
 }  // namespace hgv

@@ -16,6 +16,10 @@
 // products (fixed order, so results are reproducible), forms the reflector,
 // applies it to its rows, and computes the partial inner products the next
 // column needs.  Each launch boundary is the grid-wide synchronisation.
+//
+// Every stage is a template on the storage type E (complex128, or complex64 for
+// the mixed-precision solve); the panel's inner products, norms, reflector
+// scalars and the T factors are always computed in FP64.
 #include <algorithm>
 
 #include "hgv_internal.h"
@@ -25,8 +29,9 @@ namespace hgv {
 constexpr int PNB = 64;    // largest panel width supported by the column kernel
 constexpr int PCH = 128;   // panel rows per workgroup
 
+template <class E>
 struct PanelArgs {
-    double2 *P; int ldp;   // panel, N x jb
+    E *P; int ldp;         // panel, N x jb
     int N, jb;
     int j;                 // column being reduced (-1: only prepare column 0)
     const double2 *part_in; double2 *part_out;   // [G][PNB] partial sums
@@ -50,8 +55,9 @@ __device__ inline void make_reflector(double2 alpha, double tail, double &beta, 
     scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
 }
 
-__global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
-    __shared__ double2 Ps[PCH][PNB + 1];
+template <class E>
+__global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a) {
+    __shared__ E Ps[PCH][PNB + 1];
     __shared__ double2 s[PNB], r0v[PNB], w[PNB];
     __shared__ double2 vrow[PCH];
     __shared__ double2 red[4][PNB];
@@ -68,6 +74,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
         int r = t % PCH, c = c0 + t / PCH;
         if (r < rows) Ps[r][c] = a.P[row0 + r + (size_t)c * a.ldp];
     }
+    auto ld = [&](int r, int c) -> double2 { return El<E>::to(Ps[r][c]); };
     if (j >= 0) {
         // finish the reduction of the partial sums for column j: 4 threads per
         // column sum interleaved quarters of the G partials (loads issued
@@ -103,7 +110,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
             int gr = row0 + tid;
             double2 v = make_double2(0.0, 0.0);
             if (gr == j) v = make_double2(1.0, 0.0);
-            else if (gr > j) v = zmul(scale, Ps[tid][j]);
+            else if (gr > j) v = zmul(scale, ld(tid, j));
             vrow[tid] = v;
         }
         __syncthreads();
@@ -113,9 +120,9 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
             int gr = row0 + r;
             if (r >= rows || gr < j) continue;
             if (cc == 0) {
-                Ps[r][c] = (gr == j) ? make_double2(beta, 0.0) : vrow[r];
+                Ps[r][c] = El<E>::from((gr == j) ? make_double2(beta, 0.0) : vrow[r]);
             } else {
-                Ps[r][c] = zsub(Ps[r][c], zmul(vrow[r], w[cc]));
+                Ps[r][c] = El<E>::from(zsub(ld(r, c), zmul(vrow[r], w[cc])));
             }
         }
         if (g == 0 && tid == 0) a.tau[j] = tau;
@@ -133,9 +140,9 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
                 int gr = row0 + r;
                 if (gr < jn) continue;
                 if (c == jn) {
-                    if (gr > jn) acc.x += zabs2(Ps[r][jn]);
+                    if (gr > jn) acc.x += zabs2(ld(r, jn));
                 } else {
-                    acc = zadd(acc, zcmul(Ps[r][jn], Ps[r][c]));
+                    acc = zadd(acc, zcmul(ld(r, jn), ld(r, c)));
                 }
             }
         }
@@ -145,7 +152,7 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
             double2 t = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
             a.part_out[(size_t)g * PNB + tid] = t;
             int lr = jn - row0;
-            if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) a.row_out[tid] = Ps[lr][tid];
+            if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) a.row_out[tid] = ld(lr, tid);
         }
     }
     // write back the updated columns
@@ -156,17 +163,19 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs a) {
 }
 
 // Explicit V (N x r): unit diagonal, zeros above, reflector entries below.
-__global__ void extract_v_kernel(int N, int r, const double2 *P, int ldp, double2 *V, int ldv) {
+template <class E>
+__global__ void extract_v_kernel(int N, int r, const E *P, int ldp, E *V, int ldv) {
     int i = blockIdx.x * 64 + (threadIdx.x & 63);
     int c = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (i >= N || c >= r) return;
-    double2 v = (i > c) ? P[i + (size_t)c * ldp] : (i == c ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0));
+    E v = (i > c) ? P[i + (size_t)c * ldp] : El<E>::mk(i == c ? 1.0 : 0.0, 0.0);
     V[i + (size_t)c * ldv] = v;
 }
 
 // T (r x r upper, ldt) from tau and G = V^H V:  T_jj = tau_j,
 // T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One workgroup, column by column.
-__global__ void build_t_kernel(int r, const double2 *tau, const double2 *G, int ldg, double2 *T, int ldt) {
+template <class E>
+__global__ void build_t_kernel(int r, const double2 *tau, const E *G, int ldg, E *T, int ldt) {
     __shared__ double2 Ts[PNB][PNB + 1];
     const int tid = threadIdx.x;
     for (int t = tid; t < PNB * PNB; t += blockDim.x) Ts[t % PNB][t / PNB] = make_double2(0.0, 0.0);
@@ -175,25 +184,27 @@ __global__ void build_t_kernel(int r, const double2 *tau, const double2 *G, int 
         double2 tj = tau[j];
         if (tid < j) {
             double2 acc = make_double2(0.0, 0.0);
-            for (int l = tid; l < j; ++l) acc = zadd(acc, zmul(Ts[tid][l], G[l + (size_t)j * ldg]));
+            for (int l = tid; l < j; ++l) acc = zadd(acc, zmul(Ts[tid][l], El<E>::to(G[l + (size_t)j * ldg])));
             Ts[tid][j] = zmul(make_double2(-tj.x, -tj.y), acc);
         }
         if (tid == 0) Ts[j][j] = tj;
         __syncthreads();
     }
-    for (int t = tid; t < r * r; t += blockDim.x) T[t % r + (size_t)(t / r) * ldt] = Ts[t % r][t / r];
+    for (int t = tid; t < r * r; t += blockDim.x) T[t % r + (size_t)(t / r) * ldt] = El<E>::from(Ts[t % r][t / r]);
 }
 
-__global__ void zero_kernel(double2 *p, size_t n) {
+template <class E>
+__global__ void zero_kernel(E *p, size_t n) {
     size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) p[i] = make_double2(0.0, 0.0);
+    for (; i < n; i += stride) p[i] = El<E>::mk(0.0, 0.0);
 }
 
-static void zero_async(hgv_ctx_s *ctx, double2 *p, size_t n) {
+template <class E>
+static void zero_async(hgv_ctx_s *ctx, E *p, size_t n) {
     if (n == 0) return;
     int blocks = (int)std::min<size_t>(cdivz(n, 256), 8192);
-    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, ctx->stream, p, n);
+    hipLaunchKernelGGL(zero_kernel<E>, dim3(blocks), dim3(256), 0, ctx->stream, p, n);
     HGV_LAUNCH_CHECK();
 }
 
@@ -201,11 +212,13 @@ static int num_panels(int n, int nb) { return (n - nb - 1 >= 0) ? (n - nb - 1) /
 
 // Panel QR + T for panel P (N x jb, r = min(N, jb) reflectors).  Leaves V in
 // P (below the diagonal), beta on the diagonal, R above; T (r x r) in T, ldt.
-static void panel_qr(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int jb, double2 *tau, double2 *part,
-                     double2 *rowb, double2 *Vw, double2 *Gm, double2 *T, int ldt, double2 *ws, size_t wsb) {
+template <class E>
+static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau, double2 *part, double2 *rowb,
+                     E *Vw, E *Gm, E *T, int ldt, void *ws, size_t wsb) {
+    typedef typename El<E>::Gemm Gm_t;
     const int r = std::min(N, jb);
     const int G = cdiv(N, PCH);
-    PanelArgs a;
+    PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
     for (int j = -1; j < r; ++j) {
         int ib = (j + 1) & 1, ob = (j + 2) & 1;
@@ -214,137 +227,152 @@ static void panel_qr(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int jb, double2
         a.part_out = part + (size_t)ob * G * PNB;
         a.row_in = rowb + ib * PNB;
         a.row_out = rowb + ob * PNB;
-        hipLaunchKernelGGL(panel_step_kernel, dim3(G), dim3(256), 0, ctx->stream, a);
+        hipLaunchKernelGGL(panel_step_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a);
         HGV_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(extract_v_kernel, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
+    hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
                        Vw, N);
     HGV_LAUNCH_CHECK();
-    ZGemm gg;  // G = V^H V
+    Gm_t gg;  // G = V^H V
     gg.m = r; gg.n = r; gg.k = N;
     gg.opa = 'C'; gg.A = Vw; gg.lda = N;
     gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
     gg.C = Gm; gg.ldc = r;
-    zgemm(ctx, gg, ws, wsb);
-    hipLaunchKernelGGL(build_t_kernel, dim3(1), dim3(64), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    gemm_any(ctx, gg, ws, wsb);
+    hipLaunchKernelGGL(build_t_kernel<E>, dim3(1), dim3(64), 0, ctx->stream, r, tau, Gm, r, T, ldt);
     HGV_LAUNCH_CHECK();
 }
 
-void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar) {
+template <class E>
+void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
+    typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
     const int Gmax = cdiv(std::max(n, 1), PCH);
     size_t wsb = zgemm_splitk_bytes(n);
-    double2 *ws = ar.take<double2>(wsb / sizeof(double2));
+    void *ws = ar.take<char>(wsb);
     double2 *part = ar.take<double2>((size_t)2 * Gmax * PNB);
     double2 *rowb = ar.take<double2>(2 * PNB);
     double2 *tau = ar.take<double2>(PNB);
-    double2 *Vw = ar.take<double2>((size_t)n * nb);
-    double2 *Y = ar.take<double2>((size_t)n * nb);
-    double2 *X = ar.take<double2>((size_t)n * nb);
-    double2 *Gm = ar.take<double2>((size_t)nb * nb);
-    double2 *M = ar.take<double2>((size_t)nb * nb);
-    double2 *M2 = ar.take<double2>((size_t)nb * nb);
+    E *Vw = ar.take<E>((size_t)n * nb);
+    E *Y = ar.take<E>((size_t)n * nb);
+    E *X = ar.take<E>((size_t)n * nb);
+    E *Gm = ar.take<E>((size_t)nb * nb);
+    E *M = ar.take<E>((size_t)nb * nb);
+    E *M2 = ar.take<E>((size_t)nb * nb);
     if (ar.measuring() || n == 0) return;
+    const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0), mhalf = El<E>::mk(-0.5, 0.0);
     zero_async(ctx, T1, (size_t)std::max(np, 1) * nb * nb);
     for (int p = 0; p < np; ++p) {
         const int k = p * nb;
         const int jb = std::min(nb, n - k);
         const int N = n - k - nb;
         const int r = std::min(N, jb);
-        double2 *P = A + (k + nb) + (size_t)k * lda;
-        double2 *T = T1 + (size_t)p * nb * nb;
-        panel_qr(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb);
-        double2 *A22 = A + (k + nb) + (size_t)(k + nb) * lda;
-        ZGemm g;
+        E *P = A + (k + nb) + (size_t)k * lda;
+        E *T = T1 + (size_t)p * nb * nb;
+        panel_qr<E>(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb);
+        E *A22 = A + (k + nb) + (size_t)(k + nb) * lda;
+        Gm_t g;
         // Y = V T
-        g = ZGemm();
+        g = Gm_t();
         g.m = N; g.n = r; g.k = r;
         g.A = Vw; g.lda = N; g.B = T; g.ldb = nb;
         g.C = Y; g.ldc = N;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
         // X = A22 Y  (A22 Hermitian, lower triangle stored)
-        g = ZGemm();
+        g = Gm_t();
         g.m = N; g.n = r; g.k = N;
         g.opa = 'H'; g.A = A22; g.lda = lda;
         g.B = Y; g.ldb = N;
         g.C = X; g.ldc = N;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
         // M = V^H X
-        g = ZGemm();
+        g = Gm_t();
         g.m = r; g.n = r; g.k = N;
         g.opa = 'C'; g.A = Vw; g.lda = N;
         g.B = X; g.ldb = N;
         g.C = M; g.ldc = r;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
         // M2 = T^H M
-        g = ZGemm();
+        g = Gm_t();
         g.m = r; g.n = r; g.k = r;
         g.opa = 'C'; g.A = T; g.lda = nb;
         g.B = M; g.ldb = r;
         g.C = M2; g.ldc = r;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
         // W = X - 1/2 V M2  (into X)
-        g = ZGemm();
+        g = Gm_t();
         g.m = N; g.n = r; g.k = r;
         g.A = Vw; g.lda = N; g.B = M2; g.ldb = r;
-        g.alpha = make_double2(-0.5, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.alpha = mhalf; g.beta = one;
         g.C = X; g.ldc = N;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
         // A22 <- A22 - V W^H - W V^H (lower)
-        g = ZGemm();
+        g = Gm_t();
         g.m = N; g.n = N; g.k = r;
         g.opa = 'N'; g.A = Vw; g.lda = N;
         g.opb = 'C'; g.B = X; g.ldb = N;
         g.opa2 = 'N'; g.A2 = X; g.lda2 = N;
         g.opb2 = 'C'; g.B2 = Vw; g.ldb2 = N;
-        g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.alpha = mone; g.beta = one;
         g.C = A22; g.ldc = lda;
         g.lower = 1;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
     }
 }
 
-// Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y, last panel first.
-void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A, int lda, const double2 *T1, double2 *Y,
-                  int ldy, Arena &ar) {
+// Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y (last panel
+// first), or Y <- Q1^H Y (first panel first, T^H in place of T).
+template <class E>
+void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
+                Arena &ar) {
+    typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
     size_t wsb = zgemm_splitk_bytes(n);
-    double2 *ws = ar.take<double2>(wsb / sizeof(double2));
-    double2 *Vw = ar.take<double2>((size_t)n * nb);
-    double2 *W1 = ar.take<double2>((size_t)nb * std::max(m, 1));
-    double2 *W2 = ar.take<double2>((size_t)nb * std::max(m, 1));
+    void *ws = ar.take<char>(wsb);
+    E *Vw = ar.take<E>((size_t)n * nb);
+    E *W1 = ar.take<E>((size_t)nb * std::max(m, 1));
+    E *W2 = ar.take<E>((size_t)nb * std::max(m, 1));
     if (ar.measuring() || n == 0 || m == 0) return;
-    for (int p = np - 1; p >= 0; --p) {
+    const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0);
+    for (int q = 0; q < np; ++q) {
+        const int p = adj ? q : np - 1 - q;
         const int k = p * nb;
         const int jb = std::min(nb, n - k);
         const int N = n - k - nb;
         const int r = std::min(N, jb);
-        const double2 *P = A + (k + nb) + (size_t)k * lda;
-        const double2 *T = T1 + (size_t)p * nb * nb;
-        double2 *Ys = Y + (k + nb);
-        hipLaunchKernelGGL(extract_v_kernel, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P,
+        const E *P = A + (k + nb) + (size_t)k * lda;
+        const E *T = T1 + (size_t)p * nb * nb;
+        E *Ys = Y + (k + nb);
+        hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P,
                            lda, Vw, N);
         HGV_LAUNCH_CHECK();
-        ZGemm g;  // W1 = V^H Ys
+        Gm_t g;  // W1 = V^H Ys
         g.m = r; g.n = m; g.k = N;
         g.opa = 'C'; g.A = Vw; g.lda = N;
         g.B = Ys; g.ldb = ldy;
         g.C = W1; g.ldc = r;
-        zgemm(ctx, g, ws, wsb);
-        g = ZGemm();  // W2 = T W1
+        gemm_any(ctx, g, ws, wsb);
+        g = Gm_t();  // W2 = T W1  (T^H W1 for Q1^H)
         g.m = r; g.n = m; g.k = r;
-        g.A = T; g.lda = nb; g.B = W1; g.ldb = r;
+        g.opa = adj ? 'C' : 'N'; g.A = T; g.lda = nb; g.B = W1; g.ldb = r;
         g.C = W2; g.ldc = r;
-        zgemm(ctx, g, ws, wsb);
-        g = ZGemm();  // Ys -= V W2
+        gemm_any(ctx, g, ws, wsb);
+        g = Gm_t();  // Ys -= V W2
         g.m = N; g.n = m; g.k = r;
         g.A = Vw; g.lda = N; g.B = W2; g.ldb = r;
-        g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
+        g.alpha = mone; g.beta = one;
         g.C = Ys; g.ldc = ldy;
-        zgemm(ctx, g, ws, wsb);
+        gemm_any(ctx, g, ws, wsb);
     }
 }
+
+template void he2hb_t<double2>(hgv_ctx_s *, int, int, double2 *, int, double2 *, Arena &);
+template void he2hb_t<float2>(hgv_ctx_s *, int, int, float2 *, int, float2 *, Arena &);
+template void unmtr_q1_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, int, const double2 *, double2 *, int,
+                                  bool, Arena &);
+template void unmtr_q1_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, int, const float2 *, float2 *, int, bool,
+                                 Arena &);
 
 }  // namespace hgv

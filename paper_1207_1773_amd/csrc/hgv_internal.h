@@ -22,6 +22,11 @@ struct hgv_ctx_s {
     std::vector<double> ev_flops;
     double gemm_ms = 0.0, gemm_flops = 0.0;
     int gemm_launches = 0;
+    // Streams and events of batched solves (created on first use, default
+    // priority); problems of a batch run concurrently on them.
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> side_ev;
+    hipEvent_t fork_ev = nullptr;
     int magic = 0x68677631;
 };
 
@@ -141,6 +146,33 @@ struct CGemm {
 };
 void cgemm(hgv_ctx_s *ctx, const CGemm &g, float2 *splitk_ws, size_t splitk_bytes);
 
+// Storage-type traits: every stage that also runs in complex64 (the mixed-
+// precision path) is a template on the storage type E; arithmetic that the
+// method keeps in FP64 (norms, reflector scalars, T factors) converts through
+// these.
+template <class E>
+struct El;
+template <>
+struct El<double2> {
+    typedef ZGemm Gemm;
+    __host__ __device__ static double2 to(double2 a) { return a; }
+    __host__ __device__ static double2 from(double2 a) { return a; }
+    __host__ __device__ static double2 mk(double r, double i) { return make_double2(r, i); }
+};
+template <>
+struct El<float2> {
+    typedef CGemm Gemm;
+    __host__ __device__ static double2 to(float2 a) { return make_double2(a.x, a.y); }
+    __host__ __device__ static float2 from(double2 a) { return make_float2((float)a.x, (float)a.y); }
+    __host__ __device__ static float2 mk(double r, double i) { return make_float2((float)r, (float)i); }
+};
+inline void gemm_any(hgv_ctx_s *ctx, const ZGemm &g, void *ws, size_t wsb) {
+    zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
+}
+inline void gemm_any(hgv_ctx_s *ctx, const CGemm &g, void *ws, size_t wsb) {
+    cgemm(ctx, g, static_cast<float2 *>(ws), wsb);
+}
+
 // ---- small helpers (misc.hip) ---------------------------------------------------
 void fill_upper_from_lower(hgv_ctx_s *ctx, int n, double2 *A, int lda);
 void zero_strict_upper(hgv_ctx_s *ctx, int n, double2 *A, int lda);
@@ -160,16 +192,41 @@ void trsm_right_lc(hgv_ctx_s *ctx, int m, int n, const double2 *L, int ldl, doub
 void trsm_left_ln(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
 void trsm_left_lc(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
 
-void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar);
-void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e,
-               double2 *V2, double2 *tau2, Arena &ar);
+template <class E>
+void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar);
+// Y <- Q1 Y (adj = false) or Y <- Q1^H Y (adj = true)
+template <class E>
+void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
+                Arena &ar);
+template <class E>
+void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar);
+template <class E>
+void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
+                Arena &ar);
+inline void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar) {
+    he2hb_t<double2>(ctx, n, nb, A, lda, T1, ar);
+}
+inline void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e,
+                      double2 *V2, double2 *tau2, Arena &ar) {
+    hb2st_t<double2>(ctx, n, nb, A, lda, d, e, V2, tau2, ar);
+}
 size_t v2_elems(int n, int nb);
 size_t v2_taus(int n, int nb);
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu,
                double *lambda, double *Z, int ldz, Arena &ar, int *d_info);
-void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2,
-                  double2 *Y, int ldy, Arena &ar);
-void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A, int lda,
-                  const double2 *T1, double2 *Y, int ldy, Arena &ar);
+inline void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2,
+                         double2 *Y, int ldy, Arena &ar) {
+    unmtr_q2_t<double2>(ctx, n, nb, m, V2, tau2, Y, ldy, false, ar);
+}
+inline void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A, int lda,
+                         const double2 *T1, double2 *Y, int ldy, Arena &ar) {
+    unmtr_q1_t<double2>(ctx, n, nb, m, A, lda, T1, Y, ldy, false, ar);
+}
+
+// ---- adjoint (adjoint.hip) --------------------------------------------------------
+void gauge_fix_run(hgv_ctx_s *ctx, int n, int m, double2 *X, int ldx);
+void adjoint_run(hgv_ctx_s *ctx, int n, int il, int iu, const double *lam, const double2 *Xall, int ldxa,
+                 const double *wbar, const double2 *Xbar, int ldxb, double2 *Abar, int ldab, double2 *Bbar, int ldbb,
+                 Arena &ar);
 
 }  // namespace hgv

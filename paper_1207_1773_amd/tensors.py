@@ -13,8 +13,8 @@ import torch
 from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HGV_ST_POTRF, HGV_ST_Q1,
                HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
                hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
-               hgv_zhegst, hgv_zhegvx, hgv_zhegvx_bufsize, hgv_zpotrf, hgv_ztrsm_lh, hgv_zunmtr_q1,
-               hgv_zunmtr_q2, load)
+               hgv_zhegst, hgv_zhegvx, hgv_zhegvx_batched, hgv_zhegvx_batched_bufsize, hgv_zhegvx_bufsize,
+               hgv_zpotrf, hgv_ztrsm_lh, hgv_zunmtr_q1, hgv_zunmtr_q2, load)
 
 
 def colmajor(M, dtype=torch.complex128):
@@ -197,6 +197,49 @@ class Context:
         hgv_zhegvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
                    _ptr(w), w.numel(), opts, _ptr(info), st)
         return W[:m], from_colmajor(Xc)[:n, :m], int(info.item()), (st.as_dict() if st is not None else None)
+
+
+class BatchedSolve:
+    """Buffers of one batched solve: column-major inputs (kept pristine), working copies,
+    outputs and the workspace.  run() restores the working copies and launches
+    hgv_zhegvx_batched on the current stream; it allocates nothing, so it can be captured
+    in a HIP graph and replayed."""
+
+    def __init__(self, ctx, As, Bs, il, iu, nb=None):
+        self.ctx = ctx
+        dev = ctx.device
+        self.n = [int(A.shape[0]) for A in As]
+        self.il = list(il)
+        self.iu = list(iu)
+        self.nb = list(nb) if nb is not None else None
+        self.A0 = [colmajor(A.to(dev)) for A in As]
+        self.B0 = [colmajor(B.to(dev)) for B in Bs]
+        self.A = [a.clone() for a in self.A0]
+        self.B = [b.clone() for b in self.B0]
+        m = [u - l + 1 for l, u in zip(self.il, self.iu)]
+        self.W = [torch.zeros(max(k, 1), dtype=torch.float64, device=dev) for k in m]
+        self.X = [torch.zeros((max(k, 1), max(nn, 1)), dtype=torch.complex128, device=dev)
+                  for k, nn in zip(m, self.n)]
+        self.info = torch.zeros(max(len(self.n), 1), dtype=torch.int32, device=dev)
+        self.work = ctx._work(hgv_zhegvx_batched_bufsize(ctx.handle, self.n, self.il, self.iu, self.nb))
+        self.m = m
+
+    def run(self):
+        for a, a0 in zip(self.A, self.A0):
+            a.copy_(a0)
+        for b, b0 in zip(self.B, self.B0):
+            b.copy_(b0)
+        self.ctx._sync_stream()
+        P = lambda ts: [t.data_ptr() for t in ts]
+        ld = [max(x, 1) for x in self.n]
+        hgv_zhegvx_batched(self.ctx.handle, self.n, P(self.A), ld, P(self.B), ld, self.il, self.iu, P(self.W),
+                           P(self.X), ld, self.nb, ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
+                           ctypes.c_void_p(self.info.data_ptr()))
+
+    def results(self):
+        return ([w[:k] for w, k in zip(self.W, self.m)],
+                [from_colmajor(x)[:nn, :k] for x, nn, k in zip(self.X, self.n, self.m)],
+                self.info[:len(self.n)].tolist())
 
 
 def eigh(A, B, il=1, iu=None, precision="fp64", nb=0):
