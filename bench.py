@@ -9,9 +9,10 @@ device copy of the pencil (the solve destroys A and overwrites B).
 
 Prints ONE JSON line (rank 0).  Extra fields: per-stage milliseconds, the accuracy of
 the last step (residual, B-orthogonality, eigenvalue error against the constructed
-spectrum), the lower-fraction solves (10 % / 25 % of the eigenpairs), the GEMM
-roofline from HIP events recorded around every MFMA GEMM launch, and the CPU oracle
-timed on a bounded sample.
+spectrum), the lower-fraction solves (10 % / 25 % of the eigenpairs) in FP64 and in
+mixed precision (complex64 reduction + FP64 refinement) side by side with their
+residuals, the GEMM roofline from HIP events recorded around every MFMA GEMM launch,
+and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -39,6 +40,8 @@ def main():
     ap.add_argument("--frac", type=float, default=1.0, help="fraction of eigenpairs (lowest) in the timed step")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--fractions", type=str, default="0.1,0.25", help="extra untimed-by-contract fractions")
+    ap.add_argument("--mixed-fractions", type=str, default="0.1,0.25,1.0",
+                    help="fractions also solved in mixed precision (side by side with FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
     args = ap.parse_args()
@@ -73,10 +76,27 @@ def main():
     Ac = torch.empty_like(Ac0)
     Bc = torch.empty_like(Bc0)
 
-    def step(mm, stats):
+    def step(mm, stats, precision="fp64"):
         Ac.copy_(Ac0)
         Bc.copy_(Bc0)
-        return ctx.zhegvx(Ac, Bc, 1, mm, "fp64", args.nb, stats=stats, inplace=True)
+        return ctx.zhegvx(Ac, Bc, 1, mm, precision, args.nb, stats=stats, inplace=True)
+
+    n1 = lambda M: float(M.abs().sum(0).max())
+
+    def accuracy(W, X, mm, cols=2000):
+        """residual ||AX - BX W||_1 / (n ||A||_1 ||X||_1), ||X^H B X - I||_1 and the eigenvalue error
+        against the constructed spectrum, on the first `cols` pairs (all eigenvalues)."""
+        Wn = W.cpu().numpy()
+        lerr = float(np.abs(Wn - D_sorted[:mm]).max() / np.abs(D_sorted).max())
+        Xs = X[:, : min(mm, cols)]
+        Ws = W[: min(mm, cols)].to(torch.complex128)
+        BX = B @ Xs
+        R = A @ Xs - BX * Ws[None, :]
+        res = n1(R) / (n * n1(A) * n1(Xs))
+        G = Xs.conj().T @ BX
+        orth = n1(G - torch.eye(G.shape[0], dtype=G.dtype, device=dev))
+        return {"residual": res, "orthogonality": orth, "orth_over_n": orth / n,
+                "max_rel_eig_err_vs_constructed": lerr, "checked_columns": int(Xs.shape[1])}
 
     for i in range(args.warmup):
         step(m, False)
@@ -111,33 +131,42 @@ def main():
     tflops = flops / (ms_per_step * 1e-3) / 1e12
 
     # accuracy of the last timed step (verification on the device with torch products)
-    Wn = W.cpu().numpy()
-    lam_err = float(np.abs(Wn - D_sorted[:m]).max() / np.abs(D_sorted).max())
-    Xs = X[:, : min(m, 2000)]
-    Ws = W[: min(m, 2000)].to(torch.complex128)
-    AX = A @ Xs
-    BX = B @ Xs
-    R = AX - BX * Ws[None, :]
-    n1 = lambda M: float(M.abs().sum(0).max())
-    res = n1(R) / (n * n1(A) * n1(Xs))
-    G = Xs.conj().T @ BX
-    orth = n1(G - torch.eye(G.shape[0], dtype=G.dtype, device=dev))
+    acc_main = accuracy(W, X, m)
+    acc_main["info"] = info
 
-    extra = {}
-    for f in [float(x) for x in args.fractions.split(",") if x]:
+    def timed_fraction(f, precision):
         mf = max(1, int(math.ceil(f * n)))
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        r = step(mf, True)
+        r = step(mf, True, precision)
         e1.record()
         torch.cuda.synchronize()
         msf = e0.elapsed_time(e1)
-        extra["%d%%" % round(100 * f)] = {"m": mf, "s": msf / 1e3,
-                                          "tflops": solve_flops(n, mf) / (msf * 1e-3) / 1e12,
-                                          "stage_ms": r[3]["ms"], "info": r[2]}
-        print("[bench] fraction %.2f: %.1f ms" % (f, msf), file=sys.stderr, flush=True)
+        st_f = r[3]
+        rec = {"m": mf, "s": msf / 1e3, "tflops": solve_flops(n, mf) / (msf * 1e-3) / 1e12,
+               "stage_ms": {k: v for k, v in st_f["ms"].items() if v > 0}, "info": r[2]}
+        if precision == "mixed":
+            rec.update({"refine_iters": st_f["refine_iters"], "refine_resid": st_f["refine_resid"],
+                        "fallback": st_f["fallback"]})
+        rec["accuracy"] = accuracy(r[0], r[1], mf)
+        print("[bench] %s fraction %.2f: %.1f ms" % (precision, f, msf), file=sys.stderr, flush=True)
+        return rec
+
+    extra = {}
+    for f in [float(x) for x in args.fractions.split(",") if x]:
+        extra["%d%%" % round(100 * f)] = timed_fraction(f, "fp64")
+    mixed = {}
+    for f in [float(x) for x in args.mixed_fractions.split(",") if x]:
+        key = "%d%%" % round(100 * f)
+        rec = timed_fraction(f, "mixed")
+        base = extra.get(key)
+        if base is None and abs(f * n - m) < 1:
+            base = {"s": ms_per_step / 1e3}
+        if base is not None:
+            rec["speedup_vs_fp64"] = base["s"] / rec["s"]
+        mixed[key] = rec
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -177,10 +206,9 @@ def main():
                    "n": n, "m": m, "precision": "fp64"},
         "seconds_per_solve": ms_per_step / 1e3,
         "stage_ms": stage_avg,
-        "accuracy": {"residual": res, "orthogonality": orth, "orth_over_n": orth / n,
-                     "max_rel_eig_err_vs_constructed": lam_err, "info": info,
-                     "checked_columns": int(Xs.shape[1])},
+        "accuracy": acc_main,
         "fractions": extra,
+        "mixed": mixed,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
                      "kernel": "gemm_kernel<complex double, 64x64> (all MFMA GEMM launches of a step)",

@@ -61,8 +61,12 @@ typedef struct {
     int precision;         /* HGV_FP64 (default) or HGV_MIXED: complex64 band
                               reduction / back-transforms + fp64 refinement */
     int nb;                /* band width = panel width; 0 picks the tuned default */
-    int max_refine_iters;  /* HGV_MIXED only; 0 -> 3 */
-    double refine_tol;     /* HGV_MIXED only; target residual, 0 -> 1e-15 */
+    int max_refine_iters;  /* HGV_MIXED only: corrections before the FP64
+                              fallback; 0 -> 3; < 0 -> none (forces the
+                              fallback unless the first check passes) */
+    double refine_tol;     /* HGV_MIXED only: target of max_i ||A'y_i -
+                              theta_i y_i||_2 / ||A'||_2 (A' = L^-1 A L^-H);
+                              0 -> 32 eps sqrt(n) */
 } hgv_opts;
 
 /* Stage indices of hgv_stats.ms / flops. */
@@ -79,8 +83,10 @@ typedef struct {
     double gemm_ms;              /* summed duration of every MFMA GEMM launch     */
     double gemm_flops;           /* algorithmic flops of those launches           */
     int gemm_launches;
-    int refine_iters;            /* HGV_MIXED: refinement iterations performed    */
+    int refine_iters;            /* HGV_MIXED: refinement corrections applied     */
     int nb;                      /* band width used                               */
+    double refine_resid;         /* HGV_MIXED: final residual measure (refine_tol) */
+    int fallback;                /* HGV_MIXED: 1 if the FP64 path gave the result */
 } hgv_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -107,6 +113,16 @@ int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
  *                      its lower triangle holds the Cholesky factor L.
  *   W [out]            m = iu-il+1 doubles.
  *   X [out]            n x m, ldx >= max(1,n); X^H B X = I.
+ * opts->precision = HGV_MIXED: potrf / hegst in FP64; band reduction, bulge
+ * chasing and both back-transforms in complex64 (FP32 MFMA, reflector norms
+ * and scalars in FP64); tridiagonal solve in FP64; then FP64 refinement of the
+ * pairs (Rayleigh-Ritz on the subspace widened by up to 32 guard pairs on each
+ * side, corrections through the complex64 factorisation) until
+ * max_i ||A'y_i - theta_i y_i||_2 <= refine_tol ||A'||_2.  The check reads one
+ * double back to the host per iteration; if max_refine_iters corrections do
+ * not reach the tolerance the FP64 path recomputes the result.  While the
+ * stream is being captured into a graph the iteration count is fixed
+ * (max_refine_iters) and d_info = 2n+1 reports a missed tolerance.
  * Argument numbers for -i: ctx 1, n 2, A 3, lda 4, B 5, ldb 6, il 7, iu 8,
  * W 9, X 10, ldx 11, work 12, work_bytes 13, opts 14. */
 int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
@@ -122,13 +138,16 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
  * width per problem (e.g. from the autotuner of the Python package).  The
  * problems run concurrently on streams owned by the context, forked from and
  * joined back into the context's stream, so the whole call can be captured in
- * one HIP graph.  d_info is a device array of `batch` ints. */
+ * one HIP graph.  d_info is a device array of `batch` ints.  opts (NULL: FP64)
+ * applies to every problem; with HGV_MIXED each problem runs exactly
+ * max_refine_iters corrections (no host-side check inside a batch) and gets
+ * d_info = 2n+1 when its final residual measure exceeds refine_tol. */
 int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu,
-                               const int *nb, size_t *bytes);
+                               const int *nb, const hgv_opts *opts, size_t *bytes);
 int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *A, const int *lda,
                        hgv_c128 *const *B, const int *ldb, const int *il, const int *iu, double *const *W,
-                       hgv_c128 *const *X, const int *ldx, const int *nb, void *work, size_t work_bytes,
-                       int *d_info);
+                       hgv_c128 *const *X, const int *ldx, const int *nb, const hgv_opts *opts, void *work,
+                       size_t work_bytes, int *d_info);
 
 /* ---- stages (each one step of Algorithm 1 / Algorithm 2) ----------------- */
 /* Workspace bytes of one stage call below (stage = HGV_ST_*; m = number of

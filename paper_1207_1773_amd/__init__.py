@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_float * HGV_NSTAGES), ("flops", ctypes.c_double * HGV_NSTAGES),
                 ("gemm_ms", ctypes.c_double), ("gemm_flops", ctypes.c_double),
-                ("gemm_launches", ctypes.c_int), ("refine_iters", ctypes.c_int), ("nb", ctypes.c_int)]
+                ("gemm_launches", ctypes.c_int), ("refine_iters", ctypes.c_int), ("nb", ctypes.c_int),
+                ("refine_resid", ctypes.c_double), ("fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {
@@ -53,7 +54,7 @@ class Stats(ctypes.Structure):
             "flops": {STAGE_NAMES[i]: float(self.flops[i]) for i in range(HGV_NSTAGES)},
             "gemm_ms": float(self.gemm_ms), "gemm_flops": float(self.gemm_flops),
             "gemm_launches": int(self.gemm_launches), "refine_iters": int(self.refine_iters),
-            "nb": int(self.nb),
+            "nb": int(self.nb), "refine_resid": float(self.refine_resid), "fallback": int(self.fallback),
         }
 
 
@@ -103,8 +104,8 @@ def load():
         "hgv_gauge_fix": (I, [P, I, I, P, I]),
         "hgv_zhegvx_backward_bufsize": (I, [P, I, I, I, ctypes.POINTER(SZ)]),
         "hgv_zhegvx_backward": (I, [P, I, I, I, P, P, I, P, P, I, P, I, P, I, P, SZ]),
-        "hgv_zhegvx_batched_bufsize": (I, [P, I, P, P, P, P, ctypes.POINTER(SZ)]),
-        "hgv_zhegvx_batched": (I, [P, I, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]),
+        "hgv_zhegvx_batched_bufsize": (I, [P, I, P, P, P, P, ctypes.POINTER(Opts), ctypes.POINTER(SZ)]),
+        "hgv_zhegvx_batched": (I, [P, I, P, P, P, P, P, P, P, P, P, P, P, ctypes.POINTER(Opts), P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -235,18 +236,20 @@ def _parr(vals):
     return (ctypes.c_void_p * len(vals))(*vals)
 
 
-def hgv_zhegvx_batched_bufsize(ctx, n, il, iu, nb=None):
+def hgv_zhegvx_batched_bufsize(ctx, n, il, iu, nb=None, opts=None):
     out = SZ()
     _check(load().hgv_zhegvx_batched_bufsize(ctx, len(n), _iarr(n), _iarr(il), _iarr(iu),
-                                             _iarr(nb) if nb is not None else None, ctypes.byref(out)),
+                                             _iarr(nb) if nb is not None else None,
+                                             ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)),
            "hgv_zhegvx_batched_bufsize")
     return out.value
 
 
-def hgv_zhegvx_batched(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, nb, work, work_bytes, d_info):
+def hgv_zhegvx_batched(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, nb, work, work_bytes, d_info, opts=None):
     _check(load().hgv_zhegvx_batched(ctx, len(n), _iarr(n), _parr(A), _iarr(lda), _parr(B), _iarr(ldb), _iarr(il),
                                      _iarr(iu), _parr(W), _parr(X), _iarr(ldx),
-                                     _iarr(nb) if nb is not None else None, work, work_bytes, d_info),
+                                     _iarr(nb) if nb is not None else None,
+                                     ctypes.byref(opts) if opts is not None else None, work, work_bytes, d_info),
            "hgv_zhegvx_batched")
 
 

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void gauge_fix_kernel(int n, double2 *X, int l
         }
         __syncthreads();
     }
-    const int k = bi[0];
+    const int k = (bi[0] < n) ? bi[0] : 0;   // (only non-finite columns leave no maximum)
     double2 piv = x[k];
     double mag = sqrt(zabs2(piv));
     double2 ph = (mag > 0.0) ? make_double2(piv.x / mag, -piv.y / mag) : make_double2(1.0, 0.0);
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void adj_prep_kernel(int n, const double2 *X, 
         }
         __syncthreads();
     }
-    const int k = bi[0];
+    const int k = (bi[0] < n) ? bi[0] : 0;
     const double2 ghx = red[0];
     const double xk = x[k].x;
     const double c = (xk != 0.0) ? ghx.y / xk : 0.0;

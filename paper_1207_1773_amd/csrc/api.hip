@@ -2,6 +2,8 @@
 // checks (before any launch), workspace planning, stage sequencing for the
 // full solve of Algorithm 1, optional per-stage event timing.
 #include <algorithm>
+#include <cfloat>
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -42,65 +44,6 @@ int resolve_nb(int n, const hgv_opts *o) {
     return std::max(1, nb);
 }
 
-// Event pairs around stages when statistics are requested.
-struct StageTimer {
-    hgv_ctx_s *ctx;
-    hgv_stats *st;
-    hipEvent_t ev[HGV_NSTAGES + 1][2] = {};
-    bool used[HGV_NSTAGES] = {};
-    StageTimer(hgv_ctx_s *c, hgv_stats *s) : ctx(c), st(s) {
-        if (!st) return;
-        std::memset(st, 0, sizeof(*st));
-        for (int i = 0; i < HGV_NSTAGES; ++i) {
-            HGV_HIP(hipEventCreate(&ev[i][0]));
-            HGV_HIP(hipEventCreate(&ev[i][1]));
-        }
-        ctx->time_gemm = true;
-        ctx->gemm_ms = 0.0;
-        ctx->gemm_flops = 0.0;
-        ctx->gemm_launches = 0;
-    }
-    void begin(int s) {
-        if (st) HGV_HIP(hipEventRecord(ev[s][0], ctx->stream));
-    }
-    void end(int s, double flops) {
-        if (!st) return;
-        HGV_HIP(hipEventRecord(ev[s][1], ctx->stream));
-        used[s] = true;
-        st->flops[s] += flops;
-    }
-    void finish() {
-        if (!st) return;
-        HGV_HIP(hipStreamSynchronize(ctx->stream));
-        for (int i = 0; i < HGV_NSTAGES; ++i) {
-            if (used[i]) HGV_HIP(hipEventElapsedTime(&st->ms[i], ev[i][0], ev[i][1]));
-        }
-        double ms = 0.0, fl = 0.0;
-        for (size_t i = 0; i < ctx->ev_pending.size(); ++i) {
-            float t = 0.f;
-            HGV_HIP(hipEventElapsedTime(&t, ctx->ev_pending[i].first, ctx->ev_pending[i].second));
-            ms += t;
-            fl += ctx->ev_flops[i];
-            ctx->ev_free.push_back(ctx->ev_pending[i].first);
-            ctx->ev_free.push_back(ctx->ev_pending[i].second);
-        }
-        st->gemm_ms = ms;
-        st->gemm_flops = fl;
-        st->gemm_launches = (int)ctx->ev_pending.size();
-        ctx->ev_pending.clear();
-        ctx->ev_flops.clear();
-        ctx->time_gemm = false;
-    }
-    ~StageTimer() {
-        if (!st) return;
-        ctx->time_gemm = false;
-        for (int i = 0; i < HGV_NSTAGES; ++i) {
-            (void)hipEventDestroy(ev[i][0]);
-            (void)hipEventDestroy(ev[i][1]);
-        }
-    }
-};
-
 // Complex copy of a real n x m matrix (Z -> Y).
 __global__ void real_to_complex_kernel(int n, int m, const double *Z, int ldz, double2 *Y, int ldy) {
     int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -113,12 +56,15 @@ __global__ void copy_doubles_kernel(int n, const double *a, double *b) {
     if (i < n) b[i] = a[i];
 }
 
-// Full solve (Algorithm 1 with the two-stage Algorithm 2), FP64.  Shared by
-// the size query (arena without base) and the run.
-void zhegvx_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb, int il, int iu,
-                 double *W, double2 *X, int ldx, Arena &ar, int nb, int *d_info, StageTimer *tm) {
+}  // namespace
+
+namespace hgv {
+
+void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *X, int ldx,
+                   Arena &ar, int nb, int *d_info, StageTimer *tm) {
     const int m = iu - il + 1;
     const int np = cdiv(n, nb);
+    const size_t mk0 = ar.mark();
     double2 *T1 = ar.take<double2>((size_t)np * nb * nb);
     double *d = ar.take<double>(n);
     double *e = ar.take<double>(std::max(n - 1, 1));
@@ -129,17 +75,6 @@ void zhegvx_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb
     const size_t mk = ar.mark();
     const bool run = !ar.measuring();
     const double N = n, M = m;
-
-    if (run) set_info(ctx, d_info, 0);
-    if (tm) tm->begin(HGV_ST_POTRF);
-    potrf_run(ctx, n, B, ldb, ar, d_info, n);
-    ar.release(mk);
-    if (tm) tm->end(HGV_ST_POTRF, 4.0 / 3.0 * N * N * N);
-
-    if (tm) tm->begin(HGV_ST_HEGST);
-    hegst_run(ctx, n, A, lda, B, ldb, ar);
-    ar.release(mk);
-    if (tm) tm->end(HGV_ST_HEGST, 4.0 * N * N * N);
 
     if (tm) tm->begin(HGV_ST_HE2HB);
     he2hb_run(ctx, n, nb, A, lda, T1, ar);
@@ -173,6 +108,45 @@ void zhegvx_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb
     unmtr_q1_run(ctx, n, nb, m, A, lda, T1, X, ldx, ar);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_Q1, 8.0 * N * N * M);
+    ar.release(mk0);
+}
+
+}  // namespace hgv
+
+namespace {
+
+// Full solve (Algorithm 1 with the two-stage Algorithm 2): potrf and hegst in
+// FP64, the standard eigensolve in FP64 or mixed precision, x = L^-H y in
+// FP64.  Shared by the size query (arena without base) and the run.
+void zhegvx_full(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb, int il, int iu, double *W,
+                 double2 *X, int ldx, Arena &ar, int nb, const hgv_opts *opts, int *d_info, StageTimer *tm,
+                 MixedResult *mres, bool fixed_iters) {
+    const int m = iu - il + 1;
+    const size_t mk = ar.mark();
+    const bool run = !ar.measuring();
+    const double N = n, M = m;
+
+    if (run) set_info(ctx, d_info, 0);
+    if (tm) tm->begin(HGV_ST_POTRF);
+    potrf_run(ctx, n, B, ldb, ar, d_info, n);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_POTRF, 4.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_HEGST);
+    hegst_run(ctx, n, A, lda, B, ldb, ar);
+    ar.release(mk);
+    if (tm) tm->end(HGV_ST_HEGST, 4.0 * N * N * N);
+
+    if (opts && opts->precision == HGV_MIXED) {
+        int iters = opts->max_refine_iters > 0 ? opts->max_refine_iters : 3;
+        double tol = opts->refine_tol > 0.0 ? opts->refine_tol : 32.0 * DBL_EPSILON * std::sqrt((double)n);
+        MixedResult local;
+        mixed_standard(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, opts->max_refine_iters < 0 ? 0 : iters, tol,
+                       fixed_iters, d_info, tm, mres ? mres : &local);
+    } else {
+        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, tm);
+    }
+    ar.release(mk);
 
     if (tm) tm->begin(HGV_ST_TRSM);
     trsm_lh_run(ctx, n, m, B, ldb, X, ldx, ar);
@@ -250,8 +224,8 @@ int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -5;
     return guarded(ctx, [&]() {
         Arena ar;
-        zhegvx_fp64(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts),
-                    nullptr, nullptr);
+        zhegvx_full(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts), opts,
+                    nullptr, nullptr, nullptr, false);
         *bytes = ar.peak + 256;
         return HGV_OK;
     });
@@ -284,16 +258,24 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
     if (n > 0 && !work) return -12;
     if (work_bytes < need) return HGV_E_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(work) & 255) return -12;
-    if (opts && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
     return guarded(ctx, [&]() {
+        // under stream capture the refinement runs a fixed number of
+        // iterations (no host-side convergence check)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HGV_HIP(hipStreamIsCapturing(ctx->stream, &cap));
+        const bool fixed = cap != hipStreamCaptureStatusNone;
         StageTimer tm(ctx, stats);
         Arena ar(work, work_bytes);
         int nb = resolve_nb(n, opts);
-        zhegvx_fp64(ctx, n, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(B), ldb, il, iu,
-                    W, reinterpret_cast<double2 *>(X), ldx, ar, nb, d_info, stats ? &tm : nullptr);
+        MixedResult mres;
+        zhegvx_full(ctx, n, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(B), ldb, il, iu, W,
+                    reinterpret_cast<double2 *>(X), ldx, ar, nb, opts, d_info, stats ? &tm : nullptr, &mres, fixed);
         if (stats) {
             tm.finish();
             stats->nb = nb;
+            stats->refine_iters = mres.iters;
+            stats->refine_resid = mres.rho;
+            stats->fallback = mres.fallback;
         }
         return HGV_OK;
     });
@@ -536,11 +518,12 @@ static int batch_nb(const int *nb, int i, int n) {
 }
 
 int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu, const int *nb,
-                               size_t *bytes) {
+                               const hgv_opts *opts, size_t *bytes) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
     if (batch < 0) return -2;
     if (batch > 0 && (!n || !il || !iu)) return -3;
-    if (!bytes) return -7;
+    if (!bytes) return -8;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -7;
     *bytes = 0;
     size_t total = 256;
     for (int i = 0; i < batch; ++i) {
@@ -549,7 +532,8 @@ int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int
         if (il[i] < 1 || il[i] > n[i] || iu[i] < il[i] || iu[i] > n[i]) return -4;
         int b = batch_nb(nb, i, n[i]);
         if (b > 64) return -6;
-        hgv_opts o{HGV_FP64, b, 0, 0.0};
+        hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
+        o.nb = b;
         size_t need = 0;
         int st = hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &need);
         if (st != HGV_OK) return st;
@@ -561,8 +545,8 @@ int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int
 
 int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *A, const int *lda,
                        hgv_c128 *const *B, const int *ldb, const int *il, const int *iu, double *const *W,
-                       hgv_c128 *const *X, const int *ldx, const int *nb, void *work, size_t work_bytes,
-                       int *d_info) {
+                       hgv_c128 *const *X, const int *ldx, const int *nb, const hgv_opts *opts, void *work,
+                       size_t work_bytes, int *d_info) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
     if (batch < 0) return -2;
     if (batch == 0) return HGV_OK;
@@ -574,8 +558,9 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
         if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || !X[i])) return -4;
     }
     size_t need = 0;
-    int st = hgv_zhegvx_batched_bufsize(ctx, batch, n, il, iu, nb, &need);
-    if (st != HGV_OK) return st;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
+    int st = hgv_zhegvx_batched_bufsize(ctx, batch, n, il, iu, nb, opts, &need);
+    if (st != HGV_OK) return st == -7 ? -14 : st;
     if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -15;
     if (work_bytes < need) return HGV_E_WORKSPACE;
     return guarded(ctx, [&]() {
@@ -598,7 +583,8 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
         for (int i = 0; i < batch; ++i) {
             off[i] = at;
             if (n[i] == 0) continue;
-            hgv_opts o{HGV_FP64, batch_nb(nb, i, n[i]), 0, 0.0};
+            hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
+            o.nb = batch_nb(nb, i, n[i]);
             size_t b = 0;
             (void)hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &b);
             at += align256(b);
@@ -621,9 +607,11 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
                     continue;
                 }
                 Arena ar(static_cast<char *>(work) + off[idx], work_bytes - off[idx]);
-                zhegvx_fp64(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx],
+                hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
+                o.nb = batch_nb(nb, idx, n[idx]);
+                zhegvx_full(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx],
                             reinterpret_cast<double2 *>(B[idx]), ldb[idx], il[idx], iu[idx], W[idx],
-                            reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, batch_nb(nb, idx, n[idx]), inf, nullptr);
+                            reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, o.nb, &o, inf, nullptr, nullptr, true);
             }
         } catch (...) {
             ctx->stream = user;

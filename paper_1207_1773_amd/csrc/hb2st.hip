@@ -17,8 +17,9 @@
 // triangle with offsets 0 .. 2b-1 (the bulge reaches offset 2b-1):
 // element (r, c), r >= c, at AB[(r - c) + c * 2b].
 //
-// Parallel schedule (a workgroup runs one sweep at a time and takes the next
-// sweep from a ticket counter): task (s, j) touches rows/columns that overlap those of
+// Parallel schedule (one persistent workgroup per sweep at a time, sweeps
+// dealt round-robin, all workgroups co-resident by a cooperative launch):
+// task (s, j) touches rows/columns that overlap those of
 // task (s-1, j+1) but of no later task of sweep s-1, so it starts once sweep
 // s-1 has completed min(j+2, all) tasks.  Tasks that may run concurrently
 // touch disjoint data, and every task's arithmetic is fixed, so the result
@@ -47,7 +48,6 @@ struct HbArgs {
     E *tau2;
     int *prog;            // tasks completed per sweep
     int *err;             // set when a wait gives up
-    int *ticket;          // next sweep to take
     int J;                // tasks of sweep 0 (max over sweeps)
 };
 
@@ -101,17 +101,8 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
     auto bld = [&](size_t idx) -> double2 { return El<E>::to(AB[idx]); };
     auto bst = [&](size_t idx, double2 v) { AB[idx] = El<E>::from(v); };
     double2 Dr[NU];
-    __shared__ int sh_sweep;
 
-    for (;;) {
-        // take the next sweep; a sweep only waits for its predecessor, which was
-        // taken earlier by a workgroup that is already running, so the lowest
-        // unfinished sweep always progresses whatever the residency
-        if (tid == 0) sh_sweep = atomicAdd(a.ticket, 1);
-        __syncthreads();
-        const int s = sh_sweep;
-        __syncthreads();
-        if (s >= n - 1) break;
+    for (int s = blockIdx.x; s < n - 1; s += gridDim.x) {
         const int nt = hb_tasks(n, b, s);
         for (int j = 0; j < nt; ++j) {
             // ---- wait for sweep s-1 ------------------------------------------------
@@ -313,8 +304,9 @@ static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
     // a sweep starts two tasks behind its predecessor, so about J/2 sweeps are
     // in flight at once; more workgroups would only poll
     int G = std::max(1, std::min({cus * std::max(per, 1), a.n - 1, a.J / 2 + 4}));
-    hipLaunchKernelGGL((hb2st_kernel<BM, E>), dim3(G), dim3(256), 0, ctx->stream, a);
-    HGV_LAUNCH_CHECK();
+    void *args[] = {&a};
+    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM, E>), dim3(G), dim3(256), args, 0,
+                                       ctx->stream));
 }
 
 template <class E>
@@ -322,19 +314,18 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
     const int b = nb, ldb = 2 * nb;
     E *AB = ar.take<E>((size_t)ldb * std::max(n, 1));
-    int *prog = ar.take<int>(std::max(n, 1) + 2);
+    int *prog = ar.take<int>(std::max(n, 1) + 1);
     int *err = prog + std::max(n, 1);
-    int *ticket = err + 1;
     if (ar.measuring() || n == 0) return;
     hipLaunchKernelGGL(band_copy_kernel<E>, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB,
                        ldb);
     HGV_LAUNCH_CHECK();
     zero2(ctx, V2, v2_elems(n, nb));
     zero2(ctx, tau2, v2_taus(n, nb));
-    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 2, 256)), dim3(256), 0, ctx->stream, prog, std::max(n, 1) + 2);
+    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, ctx->stream, prog, std::max(n, 1) + 1);
     HGV_LAUNCH_CHECK();
     if (n >= 2) {
-        HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, ticket, hb_J(n, b)};
+        HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
         if (b <= 32) launch_hb2st<32, E>(ctx, a);
         else launch_hb2st<64, E>(ctx, a);
     }
@@ -446,13 +437,23 @@ __device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &re, typename Q2M
     im = Q2M<E>::mfma(a.y, b.x, im);
 }
 
-template <int BMAX, class E>
-__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
-                                                       const E *V2, const E *T2, E *Y, int ldy) {
+// Super-blocks: the groups B = KS*SB .. KS*SB + KS - 1 of one step j touch the
+// rows [KS*SB*g + 1 + j b, (KS*SB + KS) g + j b + b - 1].  Applying, for j
+// ascending, these KS groups (B descending) before moving on keeps every pair
+// of overlapping groups in the order of Q2 (a group (B, j) overlaps (B - 1, j')
+// only for j' >= j, and (B + 1, j') only for j' <= j), so a workgroup keeps the
+// window of Y rows of one super-block in an LDS ring buffer: each step stores
+// the b rows that leave the window and loads the b rows that enter it, and Y
+// crosses HBM twice per super-block instead of twice per group.  Q2^H runs the
+// exact reverse order (super-blocks ascending, j descending, B ascending).
+template <int BMAX, int KS, class E>
+__global__ __launch_bounds__(256) void q2_sb_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
+                                                     const E *V2, const E *T2, E *Y, int ldy) {
     typedef typename Q2M<E>::Acc Acc;
     constexpr int NC = 16, GM = 32, RM = 96;
+    constexpr int HR = KS * GM + BMAX;        // ring rows (>= window height KS g + b - 1)
     constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
-    __shared__ E Ys[RM][NC + 1];
+    __shared__ E Yr[HR][NC + 1];
     __shared__ E Wp[2][GM][NC + 1];           // partial W over the two k halves
     __shared__ E W2[GM][NC + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -460,108 +461,147 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
     const int c0 = blockIdx.x * NC;
     const int nc = min(NC, m - c0);
     const E zero = El<E>::mk(0.0, 0.0);
-    for (int Bi = 0; Bi < ngrp; ++Bi) {
-        const int B = adj ? Bi : ngrp - 1 - Bi;
-        const int s0 = B * g;
-        // rows start at s0 + 1 + j b; the last step with rows left is j = jn - 1
-        const int jn = min(J, (n - 2 - s0) / b + 1);
+    auto slot = [&](int row) { return row % HR; };
+    for (int t = tid; t < HR * (NC + 1); t += 256) Yr[t / (NC + 1)][t % (NC + 1)] = zero;
+    // rows [lo, hi] between the ring and Y
+    auto store_rows = [&](int lo, int hi) {
+        const int len = hi - lo + 1;
+        for (int t = tid; t < len * NC; t += 256) {
+            int r = t % len, c = t / len;
+            if (c < nc) Y[lo + r + (size_t)(c0 + c) * ldy] = Yr[slot(lo + r)][c];
+        }
+    };
+    auto load_rows = [&](int lo, int hi) {
+        const int len = hi - lo + 1;
+        for (int t = tid; t < len * NC; t += 256) {
+            int r = t % len, c = t / len;
+            Yr[slot(lo + r)][c] = (c < nc) ? Y[lo + r + (size_t)(c0 + c) * ldy] : zero;
+        }
+    };
+    const int nsb = (ngrp + KS - 1) / KS;
+    for (int si = 0; si < nsb; ++si) {
+        const int SB = adj ? si : nsb - 1 - si;
+        const int Blo = SB * KS, Bhi = min(ngrp, Blo + KS) - 1;
+        const int S0 = Blo * g;
+        // steps with rows: the lowest group of the block has the most
+        const int jn = min(J, (n - 2 - S0) / b + 1);
+        int plo = 0, phi = -1;                 // window held in the ring
         for (int ji = 0; ji < jn; ++ji) {
             const int j = adj ? jn - 1 - ji : ji;
-            const int R0 = s0 + 1 + j * b;
-            const int nrows = min(g + b - 1, n - R0);
-            const E *tg = T2 + ((size_t)B * J + j) * g * g;
-            // element (r, t) of the parallelogram V
-            auto vget = [&](int r, int t) -> E {
-                int i = r - t, s = s0 + t;
-                return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
-            };
+            const int lo = S0 + 1 + j * b;
+            const int hi = min(n - 1, (Bhi + 1) * g + j * b + b - 1);
             __syncthreads();
-            for (int t = tid; t < RM * NC; t += 256) {
-                int r = t % RM, c = t / RM;
-                Ys[r][c] = (r < nrows && c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : zero;
-            }
-            // step-1 operands: wave -> (t tile, k half)
-            const int t0 = 16 * (wave & 1), kh = wave >> 1;
-            const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
-            const int ka = (nks + 1) / 2;
-            const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
-            E a1[K1];
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                int kq = kbeg + q;
-                E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
-                a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
+            if (phi >= plo) {
+                // rows that leave: [plo, lo - 1] and [hi + 1, phi]
+                if (lo - 1 >= plo) store_rows(plo, min(phi, lo - 1));
+                if (phi >= hi + 1) store_rows(max(plo, hi + 1), phi);
             }
             __syncthreads();
-            {
-                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+            if (phi < plo) {
+                load_rows(lo, hi);
+            } else {
+                if (plo - 1 >= lo) load_rows(lo, min(hi, plo - 1));
+                if (hi >= phi + 1) load_rows(max(lo, phi + 1), hi);
+            }
+            plo = lo;
+            phi = hi;
+            for (int Bi = 0; Bi <= Bhi - Blo; ++Bi) {
+                const int B = adj ? Blo + Bi : Bhi - Bi;
+                const int s0 = B * g;
+                const int R0 = s0 + 1 + j * b;
+                if (R0 > n - 1) continue;
+                const int nrows = min(g + b - 1, n - R0);
+                const E *tg = T2 + ((size_t)B * J + j) * g * g;
+                auto vget = [&](int r, int t) -> E {
+                    int i = r - t, s = s0 + t;
+                    return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
+                };
+                // step-1 operands: wave -> (t tile, k half)
+                const int t0 = 16 * (wave & 1), kh = wave >> 1;
+                const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
+                const int ka = (nks + 1) / 2;
+                const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
+                E a1[K1];
 #pragma unroll
                 for (int q = 0; q < K1; ++q) {
                     int kq = kbeg + q;
-                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
+                    E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
+                    a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
                 }
+                __syncthreads();
+                {
+                    Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
-            }
-            __syncthreads();
-            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
-            // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
-            if (wave < 2) {
-                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-                const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
-                for (int l4 = lbeg; l4 < lend; l4 += 4) {
-                    int row = t0 + lr, col = l4 + lk;
-                    E tv = zero;
-                    if (row < g && col < g) {
-                        if (adj) {
-                            E u = tg[col + row * g];
-                            tv = El<E>::mk(u.x, -u.y);
-                        } else {
-                            tv = tg[row + col * g];
-                        }
+                    for (int q = 0; q < K1; ++q) {
+                        int kq = kbeg + q;
+                        if (kq < kend) q2_cmfma<E>(a1[q], Yr[slot(R0 + t0 + 4 * kq + lk)][lr], re, im);
                     }
-                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
-                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
                 }
+                __syncthreads();
+                // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
+                // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
+                if (wave < 2) {
+                    Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                    const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
+                    for (int l4 = lbeg; l4 < lend; l4 += 4) {
+                        int row = t0 + lr, col = l4 + lk;
+                        E tv = zero;
+                        if (row < g && col < g) {
+                            if (adj) {
+                                E u = tg[col + row * g];
+                                tv = El<E>::mk(u.x, -u.y);
+                            } else {
+                                tv = tg[row + col * g];
+                            }
+                        }
+                        E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
+                        q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
+                    }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
-            }
-            __syncthreads();
-            // step 3: Y_rows -= V W2, row tiles wave and wave + 4
-            for (int q = wave; q < 6; q += 4) {
-                const int r0 = 16 * q;
-                if (r0 >= nrows) continue;
-                Acc re, im;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    E y = Ys[r0 + Q2M<E>::orow(lk, i)][lr];
-                    re[i] = y.x;
-                    im[i] = y.y;
+                    for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
                 }
-                const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-                E a3[8];
+                __syncthreads();
+                // step 3: Y_rows -= V W2, row tiles wave and wave + 4
+                for (int q = wave; q < 6; q += 4) {
+                    const int r0 = 16 * q;
+                    if (r0 >= nrows) continue;
+                    Acc re, im;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int t4 = tlo + 4 * u;
-                    E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
-                    a3[u] = El<E>::mk(-v.x, -v.y);
-                }
+                    for (int i = 0; i < 4; ++i) {
+                        E y = Yr[slot(R0 + r0 + Q2M<E>::orow(lk, i))][lr];
+                        re[i] = y.x;
+                        im[i] = y.y;
+                    }
+                    const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+                    E a3[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int t4 = tlo + 4 * u;
-                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
-                }
+                    for (int u = 0; u < 8; ++u) {
+                        int t4 = tlo + 4 * u;
+                        E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
+                        a3[u] = El<E>::mk(-v.x, -v.y);
+                    }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    int r = r0 + Q2M<E>::orow(lk, i);
-                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(re[i], im[i]);
+                    for (int u = 0; u < 8; ++u) {
+                        int t4 = tlo + 4 * u;
+                        if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        int r = r0 + Q2M<E>::orow(lk, i);
+                        if (r < nrows) Yr[slot(R0 + r)][lr] = El<E>::mk(re[i], im[i]);
+                    }
                 }
             }
         }
+        __syncthreads();
+        if (phi >= plo) store_rows(plo, phi);
     }
 }
 
 static int q2_group(int b) { return std::min(b, 32); }
+constexpr int Q2_KS = 4;   // groups per super-block
 
 template <class E>
 void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
@@ -579,11 +619,11 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
                            tau2, T2);
     HGV_LAUNCH_CHECK();
     if (b <= 32)
-        hipLaunchKernelGGL((q2_mfma_kernel<32, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J,
-                           ngrp, (int)adj, V2, T2, Y, ldy);
+        hipLaunchKernelGGL((q2_sb_kernel<32, Q2_KS, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g,
+                           J, ngrp, (int)adj, V2, T2, Y, ldy);
     else
-        hipLaunchKernelGGL((q2_mfma_kernel<64, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g, J,
-                           ngrp, (int)adj, V2, T2, Y, ldy);
+        hipLaunchKernelGGL((q2_sb_kernel<64, Q2_KS, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g,
+                           J, ngrp, (int)adj, V2, T2, Y, ldy);
     HGV_LAUNCH_CHECK();
 }
 

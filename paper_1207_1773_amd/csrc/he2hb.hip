@@ -33,9 +33,8 @@ template <class E>
 struct PanelArgs {
     E *P; int ldp;         // panel, N x jb
     int N, jb;
-    int j;                 // column being reduced (-1: only prepare column 0)
-    const double2 *part_in; double2 *part_out;   // [G][PNB] partial sums
-    const double2 *row_in; double2 *row_out;     // row j (resp. j+1) of the panel, [PNB]
+    double2 *part;         // [2][G][PNB] partial sums (double-buffered by step)
+    double2 *rowb;         // [2][PNB] pivot row of the next column (double-buffered)
     double2 *tau;          // [jb]
     int G;
 };
@@ -56,18 +55,32 @@ __device__ inline void make_reflector(double2 alpha, double tail, double &beta, 
 }
 
 template <class E>
-__global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a) {
-    __shared__ E Ps[PCH][PNB + 1];
-    __shared__ double2 s[PNB], r0v[PNB], w[PNB];
-    __shared__ double2 vrow[PCH];
-    __shared__ double2 red[4][PNB];
+struct PanelShared {
+    E Ps[PCH][PNB + 1];
+    double2 s[PNB], r0v[PNB], w[PNB];
+    double2 vrow[PCH];
+    double2 red[4][PNB];
+};
+
+// Step j (-1: only prepare column 0) of the panel QR on row chunk g.
+template <class E>
+__device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int j, int g) {
+    auto &Ps = sh.Ps;
+    auto &s = sh.s;
+    auto &r0v = sh.r0v;
+    auto &w = sh.w;
+    auto &vrow = sh.vrow;
+    auto &red = sh.red;
     const int tid = threadIdx.x;
-    const int g = blockIdx.x;
     const int row0 = g * PCH;
     const int rows = min(PCH, a.N - row0);
-    const int j = a.j;
     const int c0 = max(j, 0);
     const int ncol = a.jb - c0;
+    const int ib = (j + 1) & 1, ob = (j + 2) & 1;
+    const double2 *part_in = a.part + (size_t)ib * a.G * PNB;
+    double2 *part_out = a.part + (size_t)ob * a.G * PNB;
+    const double2 *row_in = a.rowb + ib * PNB;
+    double2 *row_out = a.rowb + ob * PNB;
 
     // load the chunk's columns c0..jb-1
     for (int t = tid; t < PCH * ncol; t += 256) {
@@ -83,12 +96,12 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a) {
         const int c = tid & 63, qq = tid >> 6;
         double2 acc = make_double2(0.0, 0.0);
         if (c < ncol) {
-            const double2 *src = a.part_in + j + c;
+            const double2 *src = part_in + j + c;
 #pragma unroll 8
             for (int q = qq; q < a.G; q += 4) acc = zadd(acc, src[(size_t)q * PNB]);
         }
         red[qq][c] = acc;
-        if (tid < ncol) r0v[tid] = a.row_in[j + tid];
+        if (tid < ncol) r0v[tid] = row_in[j + tid];
         __syncthreads();
         if (tid < ncol) s[tid] = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
     }
@@ -150,9 +163,9 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a) {
         __syncthreads();
         if (tid < PNB) {
             double2 t = zadd(zadd(red[0][tid], red[1][tid]), zadd(red[2][tid], red[3][tid]));
-            a.part_out[(size_t)g * PNB + tid] = t;
+            part_out[(size_t)g * PNB + tid] = t;
             int lr = jn - row0;
-            if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) a.row_out[tid] = ld(lr, tid);
+            if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) row_out[tid] = ld(lr, tid);
         }
     }
     // write back the updated columns
@@ -160,6 +173,13 @@ __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a) {
         int r = t % PCH, c = c0 + t / PCH;
         if (r < rows) a.P[row0 + r + (size_t)c * a.ldp] = Ps[r][c];
     }
+}
+
+// Step j (-1: only prepare column 0) of the panel QR; workgroup g = row chunk g.
+template <class E>
+__global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a, int j) {
+    __shared__ PanelShared<E> sh;
+    panel_chunk_step<E>(a, sh, j, blockIdx.x);
 }
 
 // Explicit V (N x r): unit diagonal, zeros above, reflector entries below.
@@ -220,14 +240,9 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
     const int G = cdiv(N, PCH);
     PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
+    a.part = part; a.rowb = rowb;
     for (int j = -1; j < r; ++j) {
-        int ib = (j + 1) & 1, ob = (j + 2) & 1;
-        a.j = j;
-        a.part_in = part + (size_t)ib * G * PNB;
-        a.part_out = part + (size_t)ob * G * PNB;
-        a.row_in = rowb + ib * PNB;
-        a.row_out = rowb + ob * PNB;
-        hipLaunchKernelGGL(panel_step_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a);
+        hipLaunchKernelGGL(panel_step_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a, j);
         HGV_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
@@ -321,47 +336,112 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
     }
 }
 
-// Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y (last panel
-// first), or Y <- Q1^H Y (first panel first, T^H in place of T).
+// Copy the r x r upper-triangular T (ld nb) into the diagonal block of T_big.
+template <class E>
+__global__ void place_t_kernel(int r, const E *T, int ldt, E *Tb, int ldb) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= r || c >= r) return;
+    Tb[i + (size_t)c * ldb] = T[i + (size_t)c * ldt];
+}
+
+// Q1 = H_0 H_1 ... (one block reflector I - V_p T_p V_p^H per panel) is applied
+// in groups of Q1_MERGE consecutive panels merged into one block reflector
+// I - V T V^H (V: the panels' reflectors side by side, each panel's block
+// starting nb rows below the previous one; T upper triangular with the
+// off-diagonal blocks T[0:c, c:c+r] = -T[0:c, 0:c] (V[:, 0:c]^H V[:, c:c+r]) T_p),
+// so that every pass over Y has inner dimension Q1_MERGE * nb.
+constexpr int Q1_MERGE = 4;
+
+// Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y (last
+// group first), or Y <- Q1^H Y (first group first, T^H in place of T).
 template <class E>
 void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
                 Arena &ar) {
     typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
+    const int R = Q1_MERGE * nb;
     size_t wsb = zgemm_splitk_bytes(n);
     void *ws = ar.take<char>(wsb);
-    E *Vw = ar.take<E>((size_t)n * nb);
-    E *W1 = ar.take<E>((size_t)nb * std::max(m, 1));
-    E *W2 = ar.take<E>((size_t)nb * std::max(m, 1));
-    if (ar.measuring() || n == 0 || m == 0) return;
+    E *Vb = ar.take<E>((size_t)std::max(n, 1) * R);
+    E *S = ar.take<E>((size_t)R * R);
+    E *Tb = ar.take<E>((size_t)R * R);
+    E *X = ar.take<E>((size_t)R * nb);
+    E *W1 = ar.take<E>((size_t)R * std::max(m, 1));
+    E *W2 = ar.take<E>((size_t)R * std::max(m, 1));
+    if (ar.measuring() || n == 0 || m == 0 || np == 0) return;
     const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0);
-    for (int q = 0; q < np; ++q) {
-        const int p = adj ? q : np - 1 - q;
-        const int k = p * nb;
-        const int jb = std::min(nb, n - k);
-        const int N = n - k - nb;
-        const int r = std::min(N, jb);
-        const E *P = A + (k + nb) + (size_t)k * lda;
-        const E *T = T1 + (size_t)p * nb * nb;
-        E *Ys = Y + (k + nb);
-        hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P,
-                           lda, Vw, N);
-        HGV_LAUNCH_CHECK();
+    const int ngrp = cdiv(np, Q1_MERGE);
+    for (int q = 0; q < ngrp; ++q) {
+        const int gi = adj ? q : ngrp - 1 - q;
+        const int p0 = gi * Q1_MERGE, p1 = std::min(np, p0 + Q1_MERGE);
+        const int k0 = p0 * nb;
+        const int Nb = n - k0 - nb;                    // rows of the merged V (start at row k0 + nb)
+        if (Nb <= 0) continue;
+        // columns of panel p: c_p .. c_p + r_p - 1
+        int cols[Q1_MERGE + 1], rs[Q1_MERGE];
+        cols[0] = 0;
+        for (int p = p0; p < p1; ++p) {
+            const int k = p * nb, jb = std::min(nb, n - k), N = n - k - nb;
+            rs[p - p0] = std::max(0, std::min(N, jb));
+            cols[p - p0 + 1] = cols[p - p0] + rs[p - p0];
+        }
+        const int Rg = cols[p1 - p0];
+        if (Rg == 0) continue;
+        zero_async(ctx, Vb, (size_t)Nb * Rg);
+        zero_async(ctx, Tb, (size_t)Rg * Rg);
+        for (int p = p0; p < p1; ++p) {
+            const int k = p * nb, N = n - k - nb, r = rs[p - p0];
+            if (r == 0) continue;
+            const int off = (p - p0) * nb;
+            hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r,
+                               A + (k + nb) + (size_t)k * lda, lda, Vb + off + (size_t)cols[p - p0] * Nb, Nb);
+            HGV_LAUNCH_CHECK();
+            hipLaunchKernelGGL(place_t_kernel<E>, dim3(cdiv(r, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, r,
+                               T1 + (size_t)p * nb * nb, nb, Tb + cols[p - p0] + (size_t)cols[p - p0] * Rg, Rg);
+            HGV_LAUNCH_CHECK();
+        }
+        if (p1 - p0 > 1) {
+            Gm_t g;  // S = V^H V
+            g.m = Rg; g.n = Rg; g.k = Nb;
+            g.opa = 'C'; g.A = Vb; g.lda = Nb;
+            g.B = Vb; g.ldb = Nb;
+            g.C = S; g.ldc = Rg;
+            gemm_any(ctx, g, ws, wsb);
+            for (int p = p0 + 1; p < p1; ++p) {
+                const int c = cols[p - p0], r = rs[p - p0];
+                if (r == 0) continue;
+                g = Gm_t();  // X = S[0:c, c:c+r] T_p
+                g.m = c; g.n = r; g.k = r;
+                g.A = S + (size_t)c * Rg; g.lda = Rg;
+                g.B = T1 + (size_t)p * nb * nb; g.ldb = nb;
+                g.C = X; g.ldc = c;
+                gemm_any(ctx, g, ws, wsb);
+                g = Gm_t();  // T[0:c, c:c+r] = -T[0:c, 0:c] X
+                g.m = c; g.n = r; g.k = c;
+                g.A = Tb; g.lda = Rg;
+                g.B = X; g.ldb = c;
+                g.alpha = mone;
+                g.C = Tb + (size_t)c * Rg; g.ldc = Rg;
+                gemm_any(ctx, g, ws, wsb);
+            }
+        }
+        E *Ys = Y + (k0 + nb);
         Gm_t g;  // W1 = V^H Ys
-        g.m = r; g.n = m; g.k = N;
-        g.opa = 'C'; g.A = Vw; g.lda = N;
+        g.m = Rg; g.n = m; g.k = Nb;
+        g.opa = 'C'; g.A = Vb; g.lda = Nb;
         g.B = Ys; g.ldb = ldy;
-        g.C = W1; g.ldc = r;
+        g.C = W1; g.ldc = Rg;
         gemm_any(ctx, g, ws, wsb);
         g = Gm_t();  // W2 = T W1  (T^H W1 for Q1^H)
-        g.m = r; g.n = m; g.k = r;
-        g.opa = adj ? 'C' : 'N'; g.A = T; g.lda = nb; g.B = W1; g.ldb = r;
-        g.C = W2; g.ldc = r;
+        g.m = Rg; g.n = m; g.k = Rg;
+        g.opa = adj ? 'C' : 'N'; g.A = Tb; g.lda = Rg; g.B = W1; g.ldb = Rg;
+        g.C = W2; g.ldc = Rg;
         gemm_any(ctx, g, ws, wsb);
         g = Gm_t();  // Ys -= V W2
-        g.m = N; g.n = m; g.k = r;
-        g.A = Vw; g.lda = N; g.B = W2; g.ldb = r;
+        g.m = Nb; g.n = m; g.k = Rg;
+        g.A = Vb; g.lda = Nb; g.B = W2; g.ldb = Rg;
         g.alpha = mone; g.beta = one;
         g.C = Ys; g.ldc = ldy;
         gemm_any(ctx, g, ws, wsb);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "hgv.h"
@@ -222,6 +223,85 @@ inline void unmtr_q1_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *A,
                          const double2 *T1, double2 *Y, int ldy, Arena &ar) {
     unmtr_q1_t<double2>(ctx, n, nb, m, A, lda, T1, Y, ldy, false, ar);
 }
+
+// ---- full-solve drivers (api.hip, refine.hip) -------------------------------------
+// Event pairs around stages when statistics are requested.
+struct StageTimer {
+    hgv_ctx_s *ctx;
+    hgv_stats *st;
+    hipEvent_t ev[HGV_NSTAGES + 1][2] = {};
+    bool used[HGV_NSTAGES] = {};
+    StageTimer(hgv_ctx_s *c, hgv_stats *s) : ctx(c), st(s) {
+        if (!st) return;
+        std::memset(st, 0, sizeof(*st));
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            HGV_HIP(hipEventCreate(&ev[i][0]));
+            HGV_HIP(hipEventCreate(&ev[i][1]));
+        }
+        ctx->time_gemm = true;
+        ctx->gemm_ms = 0.0;
+        ctx->gemm_flops = 0.0;
+        ctx->gemm_launches = 0;
+    }
+    void begin(int s) {
+        if (st) HGV_HIP(hipEventRecord(ev[s][0], ctx->stream));
+    }
+    void end(int s, double flops) {
+        if (!st) return;
+        HGV_HIP(hipEventRecord(ev[s][1], ctx->stream));
+        used[s] = true;
+        st->flops[s] += flops;
+    }
+    void finish() {
+        if (!st) return;
+        HGV_HIP(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            if (used[i]) HGV_HIP(hipEventElapsedTime(&st->ms[i], ev[i][0], ev[i][1]));
+        }
+        double ms = 0.0, fl = 0.0;
+        for (size_t i = 0; i < ctx->ev_pending.size(); ++i) {
+            float t = 0.f;
+            HGV_HIP(hipEventElapsedTime(&t, ctx->ev_pending[i].first, ctx->ev_pending[i].second));
+            ms += t;
+            fl += ctx->ev_flops[i];
+            ctx->ev_free.push_back(ctx->ev_pending[i].first);
+            ctx->ev_free.push_back(ctx->ev_pending[i].second);
+        }
+        st->gemm_ms = ms;
+        st->gemm_flops = fl;
+        st->gemm_launches = (int)ctx->ev_pending.size();
+        ctx->ev_pending.clear();
+        ctx->ev_flops.clear();
+        ctx->time_gemm = false;
+    }
+    ~StageTimer() {
+        if (!st) return;
+        ctx->time_gemm = false;
+        for (int i = 0; i < HGV_NSTAGES; ++i) {
+            (void)hipEventDestroy(ev[i][0]);
+            (void)hipEventDestroy(ev[i][1]);
+        }
+    }
+};
+
+// Standard eigensolve of the lower triangle of A (n x n, destroyed) in FP64:
+// he2hb, hb2st, stedc for pairs il..iu, then Y = Q1 Q2 Z into Y (n x m).  The
+// eigenvalues il..iu go to W (device).  Used by the generalized solve, by the
+// Rayleigh-Ritz step of the refinement and as its fallback.
+void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
+                   Arena &ar, int nb, int *d_info, StageTimer *tm);
+// Mixed precision standard eigensolve of A' (n x n, FP64, lower triangle;
+// kept intact unless the refinement falls back to standard_fp64): complex64
+// band reduction, bulge chasing and back-transforms, FP64 tridiagonal solve,
+// then FP64 refinement of the eigenpairs il..iu to the residual tolerance.
+struct MixedResult {
+    int iters = 0;       // corrections applied
+    int fallback = 0;    // 1: the FP64 path produced the result
+    double rho = 0.0;    // final max_i ||A' y_i - theta_i y_i||_2 / ||A'||_2 (host-checked runs)
+};
+void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
+                    Arena &ar, int nb, int max_iters, double tol, bool fixed_iters, int *d_info, StageTimer *tm,
+                    MixedResult *res);
 
 // ---- adjoint (adjoint.hip) --------------------------------------------------------
 void gauge_fix_run(hgv_ctx_s *ctx, int n, int m, double2 *X, int ldx);

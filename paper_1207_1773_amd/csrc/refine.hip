@@ -1,0 +1,396 @@
+// refine.hip -- mixed-precision standard eigensolve: the band reduction, the
+// bulge chasing and both back-transforms run on complex64 data (FP32 MFMA,
+// reflector norms and scalars in FP64), the tridiagonal solve in FP64, and the
+// eigenpairs are then refined in FP64:
+//
+//   1. Rayleigh-Ritz on the working subspace (the wanted pairs il..iu widened
+//      by up to kGuard pairs on each side): Cholesky QR of Y, H = Y^H A' Y,
+//      H = U Theta U^H by the FP64 standard solver, Y <- Y U.
+//   2. R = A' Y - Y Theta in FP64 (the one unavoidable FP64 pass over A');
+//      rho = max_i ||r_i||_2 / ||A'||_2.  Stop when rho <= tol.
+//   3. Newton-type correction through the complex64 factorisation
+//      A' ~ Q T Q^H (Q = Q1 Q2, T tridiagonal):  for every column
+//        y_i <- y_i - Q P (T - theta_i I)^-1 P Q^H r_i,
+//      P = I - Z Z^T the projector onto the complement of the working
+//      subspace in T's eigenbasis (Z: T's eigenvectors of the working range).
+//      The complex64 back-transform kernels apply Q^H and Q; the shifted
+//      tridiagonal systems are solved in FP64 by Gaussian elimination with
+//      partial pivoting, one column per thread.
+// Each correction multiplies the error outside the working subspace by about
+// ||A' - Q T Q^H|| / (distance of theta_i to the eigenvalues outside it), so
+// the guard pairs keep the wanted pairs away from the slow boundary.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+
+#include "hgv_internal.h"
+
+namespace hgv {
+
+namespace {
+
+constexpr int kGuard = 32;
+
+__global__ void to_c64_kernel(int n, int m, const double2 *A, int lda, float2 *B, int ldb) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < n && j < m) {
+        double2 v = A[i + (size_t)j * lda];
+        B[i + (size_t)j * ldb] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+__global__ void to_c128_kernel(int n, int m, const float2 *A, int lda, double2 *B, int ldb) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < n && j < m) {
+        float2 v = A[i + (size_t)j * lda];
+        B[i + (size_t)j * ldb] = make_double2(v.x, v.y);
+    }
+}
+
+// Z (real) -> complex64 and complex128 copies
+__global__ void real_to_both_kernel(int n, int m, const double *Z, int ldz, float2 *Yc, double2 *Zc, int ld) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < n && j < m) {
+        double v = Z[i + (size_t)j * ldz];
+        Yc[i + (size_t)j * ld] = make_float2((float)v, 0.0f);
+        Zc[i + (size_t)j * ld] = make_double2(v, 0.0);
+    }
+}
+
+// Y -= D (D complex64)
+__global__ void sub_c64_kernel(int n, int m, const float2 *D, int ldd, double2 *Y, int ldy) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < n && j < m) {
+        float2 v = D[i + (size_t)j * ldd];
+        double2 &y = Y[i + (size_t)j * ldy];
+        y.x -= (double)v.x;
+        y.y -= (double)v.y;
+    }
+}
+
+// R = AY - Y diag(theta); colres[j] = ||r_j||_2.  One block per column.
+__global__ __launch_bounds__(256) void residual_kernel(int n, const double2 *AY, const double2 *Y, int ld,
+                                                       const double *theta, double2 *R, double *colres) {
+    __shared__ double part[256];
+    const int j = blockIdx.x, tid = threadIdx.x;
+    const double t = theta[j];
+    const double2 *ay = AY + (size_t)j * ld, *y = Y + (size_t)j * ld;
+    double2 *r = R + (size_t)j * ld;
+    double s = 0.0;
+    for (int i = tid; i < n; i += 256) {
+        double2 v = make_double2(ay[i].x - t * y[i].x, ay[i].y - t * y[i].y);
+        r[i] = v;
+        s += v.x * v.x + v.y * v.y;
+    }
+    part[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) part[tid] += part[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) colres[j] = sqrt(part[0]);
+}
+
+// rho = max_j colres[j] / ||A'||_2 with ||A'||_2 estimated by the extreme
+// eigenvalues of the complex64 tridiagonal matrix; in fixed-iteration mode a
+// missed tolerance is reported through d_info.
+__global__ __launch_bounds__(256) void rho_kernel(int m, const double *colres, const double *lam, int n,
+                                                  double *rho, double tol, int *d_info, int code) {
+    __shared__ double part[256];
+    const int tid = threadIdx.x;
+    double mx = 0.0;
+    for (int j = tid; j < m; j += 256) mx = fmax(mx, colres[j]);
+    part[tid] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) part[tid] = fmax(part[tid], part[tid + w]);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double an = fmax(fabs(lam[0]), fabs(lam[n - 1]));
+        double r = part[0] / fmax(an, DBL_MIN);
+        rho[0] = r;
+        if (code && d_info && !(r <= tol) && *d_info == 0) *d_info = code;
+    }
+}
+
+// (T - theta_j I) w = p for every column j of P (in place), T symmetric
+// tridiagonal (diagonal d, off-diagonal e), by Gaussian elimination with
+// partial pivoting.  One thread per column; the eliminated rows (at most
+// three non-zeros after pivoting) go to U in [k][j] order so that the
+// threads of a wave touch consecutive addresses.  Pivots smaller than
+// eps ||T|| are replaced by +-eps ||T|| (the shift is an eigenvalue
+// approximation, so the matrix may be numerically singular; the component
+// that this perturbs is removed by the projection that follows).
+__global__ __launch_bounds__(64) void tri_solve_kernel(int n, int m, const double *d, const double *e,
+                                                        const double *theta, const double *lam, double2 *P, int ldp,
+                                                        double *U) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= m) return;
+    const double sig = theta[j];
+    const double tn = fmax(fabs(lam[0]), fabs(lam[n - 1]));
+    const double tiny = fmax(tn * DBL_EPSILON, DBL_MIN);
+    double2 *p = P + (size_t)j * ldp;
+    double *u0 = U, *u1 = U + (size_t)n * m, *u2 = U + 2 * (size_t)n * m;
+    auto fix = [&](double v) { return fabs(v) >= tiny ? v : (v < 0.0 ? -tiny : tiny); };
+    // current row k: entries at columns k, k+1, k+2 and its right-hand side
+    double c0 = d[0] - sig, c1 = n > 1 ? e[0] : 0.0, c2 = 0.0;
+    double2 rc = p[0];
+    for (int k = 0; k + 1 < n; ++k) {
+        const double n0 = e[k], n1 = d[k + 1] - sig, n2 = (k + 2 < n) ? e[k + 1] : 0.0;
+        const double2 rn = p[k + 1];
+        double r0, r1, r2;
+        double2 rk;
+        if (fabs(c0) >= fabs(n0)) {
+            const double piv = fix(c0);
+            const double l = n0 / piv;
+            r0 = piv; r1 = c1; r2 = c2; rk = rc;
+            c0 = n1 - l * c1;
+            c1 = n2 - l * c2;
+            rc = make_double2(rn.x - l * rc.x, rn.y - l * rc.y);
+        } else {
+            const double l = c0 / n0;
+            r0 = n0; r1 = n1; r2 = n2; rk = rn;
+            c0 = c1 - l * n1;
+            c1 = c2 - l * n2;
+            rc = make_double2(rc.x - l * rn.x, rc.y - l * rn.y);
+        }
+        c2 = 0.0;
+        u0[(size_t)k * m + j] = r0;
+        u1[(size_t)k * m + j] = r1;
+        u2[(size_t)k * m + j] = r2;
+        p[k] = rk;
+    }
+    // back substitution
+    const double last = fix(c0);
+    double2 x1 = make_double2(rc.x / last, rc.y / last), x2 = make_double2(0.0, 0.0);
+    p[n - 1] = x1;
+    for (int k = n - 2; k >= 0; --k) {
+        const double a0 = u0[(size_t)k * m + j], a1 = u1[(size_t)k * m + j], a2 = u2[(size_t)k * m + j];
+        const double2 b = p[k];
+        const double inv = 1.0 / a0;
+        double2 x = make_double2((b.x - a1 * x1.x - a2 * x2.x) * inv, (b.y - a1 * x1.y - a2 * x2.y) * inv);
+        p[k] = x;
+        x2 = x1;
+        x1 = x;
+    }
+}
+
+__global__ void copy_vals_kernel(int m, const double *a, double *b) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) b[i] = a[i];
+}
+
+inline dim3 grid2(int n, int m) { return dim3(cdiv(n, 64), cdiv(m, 4)); }
+
+}  // namespace
+
+void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *X, int ldx,
+                    Arena &ar, int nb, int max_iters, double tol, bool fixed_iters, int *d_info, StageTimer *tm,
+                    MixedResult *res) {
+    const int m = iu - il + 1;
+    const int il2 = std::max(1, il - kGuard), iu2 = std::min(n, iu + kGuard);
+    const int mw = iu2 - il2 + 1, off = il - il2;
+    const int np = cdiv(n, nb);
+    const bool run = !ar.measuring();
+    const double N = n, MW = mw;
+    const size_t mk0 = ar.mark();
+
+    float2 *Ac = ar.take<float2>((size_t)n * n);
+    float2 *T1c = ar.take<float2>((size_t)np * nb * nb);
+    float2 *V2c = ar.take<float2>(v2_elems(n, nb));
+    float2 *tau2c = ar.take<float2>(v2_taus(n, nb));
+    double *d = ar.take<double>(n);
+    double *e = ar.take<double>(std::max(n - 1, 1));
+    double *lam = ar.take<double>(n);
+    double *Z = ar.take<double>((size_t)n * mw);
+    double2 *Zc = ar.take<double2>((size_t)n * mw);
+    float2 *Yc = ar.take<float2>((size_t)n * mw);
+    double2 *Y = ar.take<double2>((size_t)n * mw);
+    double2 *AY = ar.take<double2>((size_t)n * mw);
+    double2 *Y2 = ar.take<double2>((size_t)n * mw);
+    double2 *AY2 = ar.take<double2>((size_t)n * mw);
+    double2 *R = ar.take<double2>((size_t)n * mw);
+    double2 *S = ar.take<double2>((size_t)mw * mw);
+    double2 *Um = ar.take<double2>((size_t)mw * mw);
+    double *theta = ar.take<double>(mw);
+    double *colres = ar.take<double>(mw);
+    double *rho_d = ar.take<double>(1);
+    int *info2 = ar.take<int>(1);
+    double *Ut = ar.take<double>(3 * (size_t)n * mw);
+    const size_t wsb = zgemm_splitk_bytes(n);
+    double2 *ws = ar.take<double2>(wsb / sizeof(double2));
+    const size_t mk1 = ar.mark();
+
+    auto gemm = [&](char opa, char opb, int gm, int gn, int gk, const double2 *a, int la, const double2 *b, int lb,
+                    double2 *c, int lc, double2 alpha, double2 beta, int lower) {
+        if (!run) return;
+        ZGemm g;
+        g.m = gm; g.n = gn; g.k = gk;
+        g.opa = opa; g.A = a; g.lda = la;
+        g.opb = opb; g.B = b; g.ldb = lb;
+        g.alpha = alpha; g.beta = beta;
+        g.C = c; g.ldc = lc;
+        g.lower = lower;
+        zgemm(ctx, g, ws, wsb);
+    };
+    const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
+
+    // ---- complex64 reduction and back-transform of T's eigenvectors ----
+    if (run) {
+        hipLaunchKernelGGL(to_c64_kernel, grid2(n, n), dim3(256), 0, ctx->stream, n, n, A, lda, Ac, n);
+        HGV_LAUNCH_CHECK();
+    }
+    if (tm) tm->begin(HGV_ST_HE2HB);
+    he2hb_t<float2>(ctx, n, nb, Ac, n, T1c, ar);
+    ar.release(mk1);
+    if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_HB2ST);
+    hb2st_t<float2>(ctx, n, nb, Ac, n, d, e, V2c, tau2c, ar);
+    ar.release(mk1);
+    if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+
+    if (tm) tm->begin(HGV_ST_STEDC);
+    stedc_run(ctx, n, d, e, il2, iu2, lam, Z, n, ar, d_info);
+    ar.release(mk1);
+    if (run) {
+        hipLaunchKernelGGL(real_to_both_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, Z, n, Yc, Zc, n);
+        HGV_LAUNCH_CHECK();
+    }
+    if (tm) tm->end(HGV_ST_STEDC, 4.0 / 3.0 * N * N * N);
+
+    if (tm) tm->begin(HGV_ST_Q2);
+    unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, false, ar);
+    ar.release(mk1);
+    if (tm) tm->end(HGV_ST_Q2, 8.0 * N * N * MW);
+
+    if (tm) tm->begin(HGV_ST_Q1);
+    unmtr_q1_t<float2>(ctx, n, nb, mw, Ac, n, T1c, Yc, n, false, ar);
+    ar.release(mk1);
+    if (run) {
+        hipLaunchKernelGGL(to_c128_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, Yc, n, Y, n);
+        HGV_LAUNCH_CHECK();
+    }
+    if (tm) tm->end(HGV_ST_Q1, 8.0 * N * N * MW);
+
+    // ---- FP64 refinement ----
+    const int nbw = std::min(nb, 64);
+    auto rayleigh_ritz = [&]() {
+        // Cholesky QR: S = Y^H Y = L L^H, Y <- Y L^-H
+        gemm('C', 'N', mw, mw, n, Y, n, Y, n, S, mw, one, zero, 1);
+        potrf_run(ctx, mw, S, mw, ar, info2, 0);
+        ar.release(mk1);
+        trsm_right_lc(ctx, n, mw, S, mw, Y, n, ar);
+        ar.release(mk1);
+        // H = Y^H A' Y (lower), H = U Theta U^H
+        gemm('H', 'N', n, mw, n, A, lda, Y, n, AY, n, one, zero, 0);
+        gemm('C', 'N', mw, mw, n, Y, n, AY, n, S, mw, one, zero, 1);
+        standard_fp64(ctx, mw, S, mw, 1, mw, theta, Um, mw, ar, std::min(nbw, hgv_default_nb(mw, HGV_FP64)),
+                      info2, nullptr);
+        ar.release(mk1);
+        // rotate the basis and its image
+        gemm('N', 'N', n, mw, mw, Y, n, Um, mw, Y2, n, one, zero, 0);
+        gemm('N', 'N', n, mw, mw, AY, n, Um, mw, AY2, n, one, zero, 0);
+        std::swap(Y, Y2);
+        std::swap(AY, AY2);
+        if (run) {
+            hipLaunchKernelGGL(residual_kernel, dim3(mw), dim3(256), 0, ctx->stream, n, AY, Y, n, theta, R,
+                               colres);
+            HGV_LAUNCH_CHECK();
+        }
+    };
+    auto correct = [&]() {
+        // P = Q^H R in complex64 (Q1^H first, then Q2^H)
+        if (run) {
+            hipLaunchKernelGGL(to_c64_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, R, n, Yc, n);
+            HGV_LAUNCH_CHECK();
+        }
+        unmtr_q1_t<float2>(ctx, n, nb, mw, Ac, n, T1c, Yc, n, true, ar);
+        ar.release(mk1);
+        unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, true, ar);
+        ar.release(mk1);
+        if (run) {
+            hipLaunchKernelGGL(to_c128_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, Yc, n, R, n);
+            HGV_LAUNCH_CHECK();
+        }
+        // project onto the complement of span(Z), solve, project again
+        gemm('C', 'N', mw, mw, n, Zc, n, R, n, S, mw, one, zero, 0);
+        gemm('N', 'N', n, mw, mw, Zc, n, S, mw, R, n, mone, one, 0);
+        if (run) {
+            hipLaunchKernelGGL(tri_solve_kernel, dim3(cdiv(mw, 64)), dim3(64), 0, ctx->stream, n, mw, d, e, theta,
+                               lam, R, n, Ut);
+            HGV_LAUNCH_CHECK();
+        }
+        gemm('C', 'N', mw, mw, n, Zc, n, R, n, S, mw, one, zero, 0);
+        gemm('N', 'N', n, mw, mw, Zc, n, S, mw, R, n, mone, one, 0);
+        // Y <- Y - Q W in complex64 (Q2 first, then Q1)
+        if (run) {
+            hipLaunchKernelGGL(to_c64_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, R, n, Yc, n);
+            HGV_LAUNCH_CHECK();
+        }
+        unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, false, ar);
+        ar.release(mk1);
+        unmtr_q1_t<float2>(ctx, n, nb, mw, Ac, n, T1c, Yc, n, false, ar);
+        ar.release(mk1);
+        if (run) {
+            hipLaunchKernelGGL(sub_c64_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, Yc, n, Y, n);
+            HGV_LAUNCH_CHECK();
+        }
+    };
+
+    if (tm) tm->begin(HGV_ST_REFINE);
+    bool converged = false;
+    int iters = 0;
+    double rho = 0.0;
+    for (int it = 0;; ++it) {
+        rayleigh_ritz();
+        const bool last = it >= max_iters;
+        if (run) {
+            int code = (fixed_iters && last) ? 2 * n + 1 : 0;
+            hipLaunchKernelGGL(rho_kernel, dim3(1), dim3(256), 0, ctx->stream, mw, colres, lam, n, rho_d, tol,
+                               d_info, code);
+            HGV_LAUNCH_CHECK();
+        }
+        if (!run) {
+            // size query: one correction covers every buffer the loop uses
+            correct();
+            break;
+        }
+        if (!fixed_iters) {
+            HGV_HIP(hipMemcpyAsync(&rho, rho_d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            HGV_HIP(hipStreamSynchronize(ctx->stream));
+            if (rho <= tol) {
+                converged = true;
+                break;
+            }
+        }
+        if (last) break;
+        correct();
+        ++iters;
+    }
+    if (run && (converged || fixed_iters)) {
+        hipLaunchKernelGGL(copy_vals_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m, theta + off, W);
+        HGV_LAUNCH_CHECK();
+        copy_matrix(ctx, n, m, Y + (size_t)off * n, n, X, ldx);
+    }
+    if (tm) tm->end(HGV_ST_REFINE, iters * (8.0 * N * N * MW + 32.0 * N * N * MW) + (iters + 1) * 8.0 * N * N * MW);
+    if (res) {
+        res->iters = iters;
+        res->rho = rho;
+        res->fallback = 0;
+    }
+    ar.release(mk0);
+    if (!run || (!converged && !fixed_iters)) {
+        // the FP64 path recomputes the result from A' (still intact)
+        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, run ? tm : nullptr);
+        ar.release(mk0);
+        if (res && run) res->fallback = 1;
+    }
+}
+
+}  // namespace hgv

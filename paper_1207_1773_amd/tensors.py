@@ -177,9 +177,12 @@ class Context:
         return from_colmajor(Cc)
 
     # ---- full solve ------------------------------------------------------------------------------
-    def zhegvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, inplace=False):
+    def zhegvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, inplace=False, max_refine_iters=0,
+               refine_tol=0.0):
         """Eigenpairs il..iu of (A, B).  Returns (W, X, info, stats_dict_or_None).
 
+        precision "mixed" runs the complex64 reduction with FP64 refinement
+        (max_refine_iters / refine_tol as in hgv_opts; 0 picks the defaults).
         With inplace=True, A and B must already be column-major buffers (as made by
         ``colmajor``); they are then destroyed / overwritten by L."""
         self._sync_stream()
@@ -188,7 +191,7 @@ class Context:
         m = iu - il + 1
         Ac = A if inplace else colmajor(A)
         Bc = B if inplace else colmajor(B)
-        opts = Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), 0, 0.0)
+        opts = _opts(precision, nb, max_refine_iters, refine_tol)
         W = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
         Xc = torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex128, device=self.device)
         w = self._work(hgv_zhegvx_bufsize(self.handle, n, il, iu, opts))
@@ -199,14 +202,21 @@ class Context:
         return W[:m], from_colmajor(Xc)[:n, :m], int(info.item()), (st.as_dict() if st is not None else None)
 
 
+def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0):
+    if precision not in ("fp64", "mixed"):
+        raise ValueError("precision must be 'fp64' or 'mixed'")
+    return Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), int(max_refine_iters), float(refine_tol))
+
+
 class BatchedSolve:
     """Buffers of one batched solve: column-major inputs (kept pristine), working copies,
     outputs and the workspace.  run() restores the working copies and launches
     hgv_zhegvx_batched on the current stream; it allocates nothing, so it can be captured
     in a HIP graph and replayed."""
 
-    def __init__(self, ctx, As, Bs, il, iu, nb=None):
+    def __init__(self, ctx, As, Bs, il, iu, nb=None, precision="fp64", max_refine_iters=0, refine_tol=0.0):
         self.ctx = ctx
+        self.opts = _opts(precision, 0, max_refine_iters, refine_tol)
         dev = ctx.device
         self.n = [int(A.shape[0]) for A in As]
         self.il = list(il)
@@ -221,7 +231,7 @@ class BatchedSolve:
         self.X = [torch.zeros((max(k, 1), max(nn, 1)), dtype=torch.complex128, device=dev)
                   for k, nn in zip(m, self.n)]
         self.info = torch.zeros(max(len(self.n), 1), dtype=torch.int32, device=dev)
-        self.work = ctx._work(hgv_zhegvx_batched_bufsize(ctx.handle, self.n, self.il, self.iu, self.nb))
+        self.work = ctx._work(hgv_zhegvx_batched_bufsize(ctx.handle, self.n, self.il, self.iu, self.nb, self.opts))
         self.m = m
 
     def run(self):
@@ -234,7 +244,7 @@ class BatchedSolve:
         ld = [max(x, 1) for x in self.n]
         hgv_zhegvx_batched(self.ctx.handle, self.n, P(self.A), ld, P(self.B), ld, self.il, self.iu, P(self.W),
                            P(self.X), ld, self.nb, ctypes.c_void_p(self.work.data_ptr()), self.work.numel(),
-                           ctypes.c_void_p(self.info.data_ptr()))
+                           ctypes.c_void_p(self.info.data_ptr()), self.opts)
 
     def results(self):
         return ([w[:k] for w, k in zip(self.W, self.m)],
