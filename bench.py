@@ -44,6 +44,8 @@ def main():
                     help="fractions also solved in mixed precision (side by side with FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=2048)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only copy a device buffer of this size 5 times and exit (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -59,6 +61,15 @@ def main():
     from inputs import constructed
 
     dev = torch.device("cuda:0")
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}), flush=True)
+        return
     ctx = hgv.Context.get(dev)
     n = args.n
     m = max(1, int(math.ceil(args.frac * n)))
@@ -185,6 +196,9 @@ def main():
                                                                     tcpu * (n / args.cpu_n) ** 3)}
 
     stage_avg = {k: v / args.steps for k, v in stage_ms.items() if v > 0}
+    stage_tflops = {k: st["flops"][k] / (v * 1e-3) / 1e12 for k, v in stage_avg.items() if st["flops"].get(k)}
+    nbw = st["nb"] if st else max(args.nb, 1)
+    hb2st_gbs = (24.0 * n * n * nbw / (stage_avg["hb2st"] * 1e-3) / 1e9) if stage_avg.get("hb2st") else None
     gemm_avg_ms = gemm_ms / max(gemm_launches, 1)
     achieved = (gemm_flops / (gemm_ms * 1e-3) / 1e12) if gemm_ms > 0 else None
     out = {
@@ -206,12 +220,15 @@ def main():
                    "n": n, "m": m, "precision": "fp64"},
         "seconds_per_solve": ms_per_step / 1e3,
         "stage_ms": stage_avg,
+        "stage_tflops": stage_tflops,
+        "hb2st_algorithmic_gbs": hb2st_gbs,
         "accuracy": acc_main,
         "fractions": extra,
         "mixed": mixed,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
-                     "kernel": "gemm_kernel<complex double, 64x64> (all MFMA GEMM launches of a step)",
+                     "kernel": "hgv::gemm_kernel<hgv::TZ, 64, 64> (complex-double MFMA GEMM tiles, every launch "
+                               "of a step; split-K reductions excluded)",
                      "launches_per_step": gemm_launches / args.steps,
                      "avg_launch_ms": gemm_avg_ms,
                      "gemm_share_of_step": (gemm_ms / args.steps) / ms_per_step},

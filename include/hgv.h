@@ -80,7 +80,9 @@ enum {
 typedef struct {
     float ms[HGV_NSTAGES];       /* elapsed time per stage (HIP events)           */
     double flops[HGV_NSTAGES];   /* algorithmic flops per stage (LAPACK counts)   */
-    double gemm_ms;              /* summed duration of every MFMA GEMM launch     */
+    double gemm_ms;              /* summed duration of the complex-double MFMA
+                                    GEMM tile kernel launches (HIP events around
+                                    each launch, split-K reductions excluded)    */
     double gemm_flops;           /* algorithmic flops of those launches           */
     int gemm_launches;
     int refine_iters;            /* HGV_MIXED: refinement corrections applied     */
@@ -195,13 +197,17 @@ int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, i
                double *lambda, double *Z, int ldz, void *work, size_t work_bytes,
                int *d_info);
 
-/* Alg. 2 step 3, first part: Y <- Q2 Y (Y n x m complex, ldy >= n). */
-int hgv_zunmtr_q2(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *V2,
+/* Alg. 2 step 3, first part: Y <- Q2 Y (trans 'N') or Y <- Q2^H Y (trans 'C');
+ * Y n x m complex, ldy >= n.  Argument numbers for -i: ctx 1, trans 2, n 3,
+ * nb 4, m 5, V2 6, tau2 7, Y 8, ldy 9, work 10. */
+int hgv_zunmtr_q2(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *V2,
                   const hgv_c128 *tau2, hgv_c128 *Y, int ldy, void *work, size_t work_bytes);
 
-/* Alg. 2 step 3, second part: Y <- Q1 Y, with Q1 from hgv_zhe2hb (reflectors in
- * A below the band, factors in T1). */
-int hgv_zunmtr_q1(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *A, int lda,
+/* Alg. 2 step 3, second part: Y <- Q1 Y (trans 'N') or Y <- Q1^H Y (trans 'C'),
+ * with Q1 from hgv_zhe2hb (reflectors in A below the band, factors in T1).
+ * Argument numbers: ctx 1, trans 2, n 3, nb 4, m 5, A 6, lda 7, T1 8, Y 9,
+ * ldy 10, work 11. */
+int hgv_zunmtr_q1(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *A, int lda,
                   const hgv_c128 *T1, hgv_c128 *Y, int ldy, void *work, size_t work_bytes);
 
 /* Alg. 1 step 4: X <- L^-H X (X n x m, L lower from hgv_zpotrf). */

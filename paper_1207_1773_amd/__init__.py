@@ -97,8 +97,8 @@ def load():
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
         "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
-        "hgv_zunmtr_q2": (I, [P, I, I, I, P, P, P, I, P, SZ]),
-        "hgv_zunmtr_q1": (I, [P, I, I, I, P, I, P, P, I, P, SZ]),
+        "hgv_zunmtr_q2": (I, [P, ctypes.c_char, I, I, I, P, P, P, I, P, SZ]),
+        "hgv_zunmtr_q1": (I, [P, ctypes.c_char, I, I, I, P, I, P, P, I, P, SZ]),
         "hgv_ztrsm_lh": (I, [P, I, I, P, I, P, I, P, SZ]),
         "hgv_zgemm": (I, [P, ctypes.c_char, ctypes.c_char, I, I, I, c128, P, I, P, I, c128, P, I]),
         "hgv_gauge_fix": (I, [P, I, I, P, I]),
@@ -195,12 +195,14 @@ def hgv_dstedc(ctx, n, d, e, il, iu, lam, Z, ldz, work, work_bytes, d_info):
     _check(load().hgv_dstedc(ctx, n, d, e, il, iu, lam, Z, ldz, work, work_bytes, d_info), "hgv_dstedc")
 
 
-def hgv_zunmtr_q2(ctx, n, nb, m, V2, tau2, Y, ldy, work, work_bytes):
-    _check(load().hgv_zunmtr_q2(ctx, n, nb, m, V2, tau2, Y, ldy, work, work_bytes), "hgv_zunmtr_q2")
+def hgv_zunmtr_q2(ctx, trans, n, nb, m, V2, tau2, Y, ldy, work, work_bytes):
+    _check(load().hgv_zunmtr_q2(ctx, trans.encode() if isinstance(trans, str) else trans, n, nb, m, V2, tau2, Y,
+                                ldy, work, work_bytes), "hgv_zunmtr_q2")
 
 
-def hgv_zunmtr_q1(ctx, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes):
-    _check(load().hgv_zunmtr_q1(ctx, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes), "hgv_zunmtr_q1")
+def hgv_zunmtr_q1(ctx, trans, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes):
+    _check(load().hgv_zunmtr_q1(ctx, trans.encode() if isinstance(trans, str) else trans, n, nb, m, A, lda, T1, Y,
+                                ldy, work, work_bytes), "hgv_zunmtr_q1")
 
 
 def hgv_ztrsm_lh(ctx, n, m, L, ldl, X, ldx, work, work_bytes):

@@ -421,43 +421,46 @@ int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, i
     });
 }
 
-int hgv_zunmtr_q2(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *V2, const hgv_c128 *tau2, hgv_c128 *Y,
-                  int ldy, void *work, size_t work_bytes) {
+int hgv_zunmtr_q2(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *V2, const hgv_c128 *tau2,
+                  hgv_c128 *Y, int ldy, void *work, size_t work_bytes) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
-    if (n < 0) return -2;
-    if (nb < 1) return -3;
-    if (m < 0) return -4;
-    if (n > 0 && !V2) return -5;
-    if (n > 0 && !tau2) return -6;
-    if (n > 0 && m > 0 && !Y) return -7;
-    if (ldy < std::max(1, n)) return -8;
-    int st = check_work(ctx, HGV_ST_Q2, n, nb, m, work, work_bytes, 9);
+    if (trans != 'N' && trans != 'C') return -2;
+    if (n < 0) return -3;
+    if (nb < 1) return -4;
+    if (m < 0) return -5;
+    if (n > 0 && !V2) return -6;
+    if (n > 0 && !tau2) return -7;
+    if (n > 0 && m > 0 && !Y) return -8;
+    if (ldy < std::max(1, n)) return -9;
+    int st = check_work(ctx, HGV_ST_Q2, n, nb, m, work, work_bytes, 10);
     if (st) return st;
     return guarded(ctx, [&]() {
         Arena ar(work, work_bytes);
-        unmtr_q2_run(ctx, n, nb, m, reinterpret_cast<const double2 *>(V2), reinterpret_cast<const double2 *>(tau2),
-                     reinterpret_cast<double2 *>(Y), ldy, ar);
+        unmtr_q2_t<double2>(ctx, n, nb, m, reinterpret_cast<const double2 *>(V2),
+                            reinterpret_cast<const double2 *>(tau2), reinterpret_cast<double2 *>(Y), ldy, trans == 'C',
+                            ar);
         return HGV_OK;
     });
 }
-
-int hgv_zunmtr_q1(hgv_ctx_t ctx, int n, int nb, int m, const hgv_c128 *A, int lda, const hgv_c128 *T1,
+int hgv_zunmtr_q1(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *A, int lda, const hgv_c128 *T1,
                   hgv_c128 *Y, int ldy, void *work, size_t work_bytes) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
-    if (n < 0) return -2;
-    if (nb < 1) return -3;
-    if (m < 0) return -4;
-    if (n > 0 && !A) return -5;
-    if (lda < std::max(1, n)) return -6;
-    if (n > 0 && !T1) return -7;
-    if (n > 0 && m > 0 && !Y) return -8;
-    if (ldy < std::max(1, n)) return -9;
-    int st = check_work(ctx, HGV_ST_Q1, n, nb, m, work, work_bytes, 10);
+    if (trans != 'N' && trans != 'C') return -2;
+    if (n < 0) return -3;
+    if (nb < 1) return -4;
+    if (m < 0) return -5;
+    if (n > 0 && !A) return -6;
+    if (lda < std::max(1, n)) return -7;
+    if (n > 0 && !T1) return -8;
+    if (n > 0 && m > 0 && !Y) return -9;
+    if (ldy < std::max(1, n)) return -10;
+    int st = check_work(ctx, HGV_ST_Q1, n, nb, m, work, work_bytes, 11);
     if (st) return st;
     return guarded(ctx, [&]() {
         Arena ar(work, work_bytes);
-        unmtr_q1_run(ctx, n, nb, m, reinterpret_cast<const double2 *>(A), lda,
-                     reinterpret_cast<const double2 *>(T1), reinterpret_cast<double2 *>(Y), ldy, ar);
+        unmtr_q1_t<double2>(ctx, n, nb, m, reinterpret_cast<const double2 *>(A), lda,
+                            reinterpret_cast<const double2 *>(T1), reinterpret_cast<double2 *>(Y), ldy, trans == 'C',
+                            ar);
         return HGV_OK;
     });
 }

@@ -22,6 +22,8 @@
 //    operand panels;
 //  * split-K (deterministic: partial tiles summed in a fixed order by a
 //    second kernel) for outputs with too few tiles to fill 256 CUs.
+#include <type_traits>
+
 #include "hgv_internal.h"
 
 namespace hgv {
@@ -389,8 +391,11 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     g.splits = splits;
     g.P = splits > 1 ? ws : nullptr;
 
+    // optional accounting of the complex-double tile kernel alone (the events
+    // bracket gemm_kernel<TZ>; the split-K reduction is a separate kernel)
+    const bool timed = ctx->time_gemm && std::is_same<T, TZ>::value;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->time_gemm) {
+    if (timed) {
         if (ctx->ev_free.size() < 2) {
             hipEvent_t x, y;
             HGV_HIP(hipEventCreate(&x));
@@ -405,16 +410,16 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     dim3 grid(g.tiles_m * g.tiles_n, splits);
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
     HGV_LAUNCH_CHECK();
+    if (timed) {
+        HGV_HIP(hipEventRecord(e1, ctx->stream));
+        ctx->ev_pending.push_back({e0, e1});
+        ctx->ev_flops.push_back(flops);
+    }
     if (splits > 1) {
         size_t total = (size_t)a.m * a.n;
         int blocks = (int)std::min<size_t>(cdivz(total, 256), 4096);
         hipLaunchKernelGGL((splitk_reduce<T>), dim3(blocks), dim3(256), 0, ctx->stream, g);
         HGV_LAUNCH_CHECK();
-    }
-    if (ctx->time_gemm) {
-        HGV_HIP(hipEventRecord(e1, ctx->stream));
-        ctx->ev_pending.push_back({e0, e1});
-        ctx->ev_flops.push_back(flops);
     }
 }
 

@@ -437,6 +437,121 @@ __device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &re, typename Q2M
     im = Q2M<E>::mfma(a.y, b.x, im);
 }
 
+template <int BMAX, class E>
+__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
+                                                       const E *V2, const E *T2, E *Y, int ldy) {
+    typedef typename Q2M<E>::Acc Acc;
+    constexpr int NC = 16, GM = 32, RM = 96;
+    constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
+    __shared__ E Ys[RM][NC + 1];
+    __shared__ E Wp[2][GM][NC + 1];           // partial W over the two k halves
+    __shared__ E W2[GM][NC + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int c0 = blockIdx.x * NC;
+    const int nc = min(NC, m - c0);
+    const E zero = El<E>::mk(0.0, 0.0);
+    for (int Bi = 0; Bi < ngrp; ++Bi) {
+        const int B = adj ? Bi : ngrp - 1 - Bi;
+        const int s0 = B * g;
+        // rows start at s0 + 1 + j b; the last step with rows left is j = jn - 1
+        const int jn = min(J, (n - 2 - s0) / b + 1);
+        for (int ji = 0; ji < jn; ++ji) {
+            const int j = adj ? jn - 1 - ji : ji;
+            const int R0 = s0 + 1 + j * b;
+            const int nrows = min(g + b - 1, n - R0);
+            const E *tg = T2 + ((size_t)B * J + j) * g * g;
+            // element (r, t) of the parallelogram V
+            auto vget = [&](int r, int t) -> E {
+                int i = r - t, s = s0 + t;
+                return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
+            };
+            __syncthreads();
+            for (int t = tid; t < RM * NC; t += 256) {
+                int r = t % RM, c = t / RM;
+                Ys[r][c] = (r < nrows && c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : zero;
+            }
+            // step-1 operands: wave -> (t tile, k half)
+            const int t0 = 16 * (wave & 1), kh = wave >> 1;
+            const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
+            const int ka = (nks + 1) / 2;
+            const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
+            E a1[K1];
+#pragma unroll
+            for (int q = 0; q < K1; ++q) {
+                int kq = kbeg + q;
+                E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
+                a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
+            }
+            __syncthreads();
+            {
+                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+#pragma unroll
+                for (int q = 0; q < K1; ++q) {
+                    int kq = kbeg + q;
+                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
+            }
+            __syncthreads();
+            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
+            // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
+            if (wave < 2) {
+                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
+                for (int l4 = lbeg; l4 < lend; l4 += 4) {
+                    int row = t0 + lr, col = l4 + lk;
+                    E tv = zero;
+                    if (row < g && col < g) {
+                        if (adj) {
+                            E u = tg[col + row * g];
+                            tv = El<E>::mk(u.x, -u.y);
+                        } else {
+                            tv = tg[row + col * g];
+                        }
+                    }
+                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
+                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
+            }
+            __syncthreads();
+            // step 3: Y_rows -= V W2, row tiles wave and wave + 4
+            for (int q = wave; q < 6; q += 4) {
+                const int r0 = 16 * q;
+                if (r0 >= nrows) continue;
+                Acc re, im;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    E y = Ys[r0 + Q2M<E>::orow(lk, i)][lr];
+                    re[i] = y.x;
+                    im[i] = y.y;
+                }
+                const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+                E a3[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int t4 = tlo + 4 * u;
+                    E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
+                    a3[u] = El<E>::mk(-v.x, -v.y);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    int t4 = tlo + 4 * u;
+                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int r = r0 + Q2M<E>::orow(lk, i);
+                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(re[i], im[i]);
+                }
+            }
+        }
+    }
+}
+
 // Super-blocks: the groups B = KS*SB .. KS*SB + KS - 1 of one step j touch the
 // rows [KS*SB*g + 1 + j b, (KS*SB + KS) g + j b + b - 1].  Applying, for j
 // ascending, these KS groups (B descending) before moving on keeps every pair
@@ -618,12 +733,29 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
         hipLaunchKernelGGL((q2_tbuild_kernel<64, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     HGV_LAUNCH_CHECK();
-    if (b <= 32)
-        hipLaunchKernelGGL((q2_sb_kernel<32, Q2_KS, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g,
-                           J, ngrp, (int)adj, V2, T2, Y, ldy);
-    else
-        hipLaunchKernelGGL((q2_sb_kernel<64, Q2_KS, E>), dim3(cdiv(m, 16)), dim3(256), 0, ctx->stream, n, m, b, g,
-                           J, ngrp, (int)adj, V2, T2, Y, ldy);
+    // The super-block kernel keeps Y rows in LDS (fewer global round trips
+    // per group) but its larger LDS footprint allows two workgroups per CU
+    // instead of three; with more column tiles than two per CU the per-group
+    // kernel's occupancy wins.
+    int cus = 0;
+    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int tiles = cdiv(m, 16);
+    const bool sb = tiles <= 2 * cus;
+    if (b <= 32) {
+        if (sb)
+            hipLaunchKernelGGL((q2_sb_kernel<32, Q2_KS, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J,
+                               ngrp, (int)adj, V2, T2, Y, ldy);
+        else
+            hipLaunchKernelGGL((q2_mfma_kernel<32, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
+                               (int)adj, V2, T2, Y, ldy);
+    } else {
+        if (sb)
+            hipLaunchKernelGGL((q2_sb_kernel<64, Q2_KS, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J,
+                               ngrp, (int)adj, V2, T2, Y, ldy);
+        else
+            hipLaunchKernelGGL((q2_mfma_kernel<64, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
+                               (int)adj, V2, T2, Y, ldy);
+    }
     HGV_LAUNCH_CHECK();
 }
 

@@ -133,24 +133,26 @@ class Context:
                    _ptr(info))
         return lam[:n], from_colmajor(Zc)[:n, :m], int(info.item())
 
-    def q2(self, V2, tau2, Y, nb):
-        """Alg. 2 step 3 (first part): Q2 Y."""
+    def q2(self, V2, tau2, Y, nb, adj=False):
+        """Alg. 2 step 3 (first part): Q2 Y (Q2^H Y with adj=True)."""
         self._sync_stream()
         n, m = Y.shape
         Yc = colmajor(Y)
         w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_Q2, n, nb, m))
-        hgv_zunmtr_q2(self.handle, n, nb, m, _ptr(V2), _ptr(tau2), _ptr(Yc), max(n, 1), _ptr(w), w.numel())
+        hgv_zunmtr_q2(self.handle, "C" if adj else "N", n, nb, m, _ptr(V2), _ptr(tau2), _ptr(Yc), max(n, 1), _ptr(w),
+                      w.numel())
         return from_colmajor(Yc)
 
-    def q1(self, Ab, T1, Y, nb):
-        """Alg. 2 step 3 (second part): Q1 Y with reflectors from he2hb (Ab as returned by he2hb)."""
+    def q1(self, Ab, T1, Y, nb, adj=False):
+        """Alg. 2 step 3 (second part): Q1 Y (Q1^H Y with adj=True) with reflectors from he2hb
+        (Ab as returned by he2hb)."""
         self._sync_stream()
         n, m = Y.shape
         Ac = colmajor(Ab)
         Yc = colmajor(Y)
         w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_Q1, n, nb, m))
-        hgv_zunmtr_q1(self.handle, n, nb, m, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(Yc), max(n, 1), _ptr(w),
-                      w.numel())
+        hgv_zunmtr_q1(self.handle, "C" if adj else "N", n, nb, m, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(Yc), max(n, 1),
+                      _ptr(w), w.numel())
         return from_colmajor(Yc)
 
     def trsm_lh(self, L, X):

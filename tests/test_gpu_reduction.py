@@ -98,6 +98,41 @@ def test_q2_q1_on_rectangular_blocks(ctx, n, nb, m):
     assert rel_fro(QY, Q2 @ Y) < _tol(n)
 
 
+@pytest.mark.parametrize("n,nb", [(200, 64), (150, 32)])
+def test_q2_many_columns_and_adjoint(ctx, n, nb):
+    """Q2 on 8300 columns (the per-group kernel; fewer columns take the LDS super-block
+    kernel) equals the explicit Q2 formed on the identity, and Q2^H undoes Q2 on both."""
+    band = random_band(n, nb, 700 + n)
+    d, e, V2, tau2 = ctx.hb2st(to_dev(band), nb)
+    Q2 = to_np(ctx.q2(V2, tau2, to_dev(np.eye(n, dtype=complex)), nb))
+    rng = np.random.default_rng(n + 1)
+    for m in (8300, 37):
+        Y = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+        QY = to_np(ctx.q2(V2, tau2, to_dev(Y), nb))
+        assert rel_fro(QY, Q2 @ Y) < _tol(n)
+        QhY = to_np(ctx.q2(V2, tau2, to_dev(Y), nb, adj=True))
+        assert rel_fro(QhY, Q2.conj().T @ Y) < _tol(n)
+        back = to_np(ctx.q2(V2, tau2, to_dev(QY), nb, adj=True))
+        assert rel_fro(back, Y) < _tol(n)
+
+
+@pytest.mark.parametrize("n,nb,m", [(300, 32, 20), (700, 64, 9), (260, 16, 300)])
+def test_q1_adjoint(ctx, n, nb, m):
+    """Q1^H Q1 Y = Y and Q1^H Y equals the explicit Q1^H (merged-panel application)."""
+    A = rand_herm(n, 900 + n)
+    Ab, T1 = ctx.he2hb(to_dev(np.tril(A)), nb)
+    Q1 = to_np(ctx.q1(Ab, T1, to_dev(np.eye(n, dtype=complex)), nb))
+    rng = np.random.default_rng(m)
+    Y = rng.standard_normal((n, m)) + 1j * rng.standard_normal((n, m))
+    QY = to_np(ctx.q1(Ab, T1, to_dev(Y), nb))
+    assert rel_fro(QY, Q1 @ Y) < _tol(n)
+    QhY = to_np(ctx.q1(Ab, T1, to_dev(Y), nb, adj=True))
+    assert rel_fro(QhY, Q1.conj().T @ Y) < _tol(n)
+    assert rel_fro(to_np(ctx.q1(Ab, T1, to_dev(QY), nb, adj=True)), Y) < _tol(n)
+    # Q1 is unitary
+    assert rel_fro(Q1.conj().T @ Q1, np.eye(n)) < _tol(n)
+
+
 def test_two_stage_eigenvalues_match_oracle(ctx):
     """he2hb + hb2st on A' = L^-1 A L^-H keeps the oracle's eigenvalues of the pencil."""
     n, nb = 400, 32
