@@ -24,20 +24,28 @@ static int split_point(int n) {
     return n1;
 }
 
-// Inverse of the lower-triangular sz x sz block held in S (LDS) into Inv (LDS):
-// column c solves L x = e_c by forward substitution (one thread per column).
-__device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LEAF + 1], int sz, int tid,
-                                       int nthreads) {
-    for (int c = tid; c < LEAF; c += nthreads) {
-        for (int i = 0; i < LEAF; ++i) {
-            if (i < c || i >= sz || c >= sz) {
-                Inv[i][c] = make_double2(0.0, 0.0);
-                continue;
-            }
-            double2 s = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-            for (int k = c; k < i; ++k) s = zsub(s, zmul(S[i][k], Inv[k][c]));
-            Inv[i][c] = zdiv(s, S[i][i]);
+// Inverse of the lower-triangular sz x sz block held in S (LDS) into Inv (LDS),
+// 256 threads: column c (independent of the others) solves L x = e_c by
+// forward substitution; the four lanes 4c .. 4c+3 of a wave share a column
+// and split every inner product, combined with two butterfly shuffles.
+__device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LEAF + 1], int sz, int tid) {
+    const int c = tid >> 2, q = tid & 3;
+    for (int i = 0; i < LEAF; ++i) {
+        if (i < c || i >= sz || c >= sz) {
+            Inv[i][c] = make_double2(0.0, 0.0);
+            continue;
         }
+        double2 s = make_double2(0.0, 0.0);
+        for (int k = c + q; k < i; k += 4) s = zadd(s, zmul(S[i][k], Inv[k][c]));
+#pragma unroll
+        for (int o = 1; o < 4; o <<= 1) {
+            s.x += __shfl_xor(s.x, o, 64);
+            s.y += __shfl_xor(s.y, o, 64);
+        }
+        const double2 rhs = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+        // the butterfly leaves the same sum in the four lanes, so each lane
+        // stores the (identical) value and later reads only what it stored
+        Inv[i][c] = zdiv(zsub(rhs, s), S[i][i]);
     }
 }
 
@@ -96,80 +104,81 @@ __global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, 
             }
             __syncthreads();
         }
-        tri_inverse_lds(S, Iv, n, tid, 256);
+        tri_inverse_lds(S, Iv, n, tid);
         __syncthreads();
         for (int t = tid; t < LEAF * LEAF; t += 256) Linv[t] = Iv[t % LEAF][t / LEAF];
     }
 }
 
 // Inverse of every 64 x 64 diagonal block of the lower-triangular L.
-__global__ __launch_bounds__(64) void trtri_diag_kernel(int n, const double2 *L, int ldl, double2 *Linv) {
+__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double2 *L, int ldl, double2 *Linv) {
     __shared__ double2 S[LEAF][LEAF + 1];
     __shared__ double2 Iv[LEAF][LEAF + 1];
     const int blk = blockIdx.x, tid = threadIdx.x;
     const int o = blk * LEAF, sz = min(LEAF, n - o);
-    for (int t = tid; t < LEAF * LEAF; t += 64) {
+    for (int t = tid; t < LEAF * LEAF; t += 256) {
         int i = t % LEAF, j = t / LEAF;
         S[i][j] = (i < sz && j < sz && i >= j) ? L[(o + i) + (size_t)(o + j) * ldl] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    tri_inverse_lds(S, Iv, sz, tid, 64);
+    tri_inverse_lds(S, Iv, sz, tid);
     __syncthreads();
     double2 *out = Linv + (size_t)blk * LEAF * LEAF;
-    for (int t = tid; t < LEAF * LEAF; t += 64) out[t] = Iv[t % LEAF][t / LEAF];
+    for (int t = tid; t < LEAF * LEAF; t += 256) out[t] = Iv[t % LEAF][t / LEAF];
 }
 
 // ---- leaf reduction to standard form (n <= 64), one workgroup ---------------------
-// C = L^-1 A L^-H for the block: W = L^-1 A (A full Hermitian from its lower
-// triangle), then C = L^-1 W^H; the lower triangle of (C + C^H)/2 is written.
-__global__ __launch_bounds__(64) void hegs2_kernel(int n, double2 *A, int lda, const double2 *L, int ldl) {
+// C = L^-1 A L^-H for the block with the block's inverse Li = L^-1 (64 x 64,
+// column-major, zero outside the n x n triangle): W = Li A (A full Hermitian
+// from its lower triangle), C = W Li^H; the lower triangle of (C + C^H)/2 is
+// written.  256 threads, each owning 16 elements of the product.
+__global__ __launch_bounds__(256) void hegs2_kernel(int n, double2 *A, int lda, const double2 *Li) {
     __shared__ double2 Ls[LEAF][LEAF + 1];
-    __shared__ double2 Ws[LEAF][LEAF + 1];
-    const int lane = threadIdx.x;
-    for (int t = lane; t < n * n; t += 64) {
-        int i = t % n, j = t / n;
-        Ls[i][j] = (i >= j) ? L[i + (size_t)j * ldl] : make_double2(0.0, 0.0);
-        double2 a;
-        if (i > j) a = A[i + (size_t)j * lda];
-        else if (i == j) a = make_double2(A[i + (size_t)i * lda].x, 0.0);
-        else a = zconj(A[j + (size_t)i * lda]);
-        Ws[i][j] = a;
-    }
-    __syncthreads();
-    // pass 1: column `lane` of W = L^-1 A (in place in Ws, column by column)
-    if (lane < n) {
-        for (int j = 0; j < n; ++j) {
-            double2 s = Ws[j][lane];
-            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], Ws[k][lane]));
-            Ws[j][lane] = zdiv(s, Ls[j][j]);
+    __shared__ double2 As[LEAF][LEAF + 1];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < LEAF * LEAF; t += 256) {
+        int i = t % LEAF, j = t / LEAF;
+        Ls[i][j] = (i < n && j < n) ? Li[i + (size_t)j * LEAF] : make_double2(0.0, 0.0);
+        double2 a = make_double2(0.0, 0.0);
+        if (i < n && j < n) {
+            if (i > j) a = A[i + (size_t)j * lda];
+            else if (i == j) a = make_double2(A[i + (size_t)i * lda].x, 0.0);
+            else a = zconj(A[j + (size_t)i * lda]);
         }
+        As[i][j] = a;
     }
     __syncthreads();
-    // transpose-conjugate W in place: Ws <- W^H
-    for (int t = lane; t < n * n; t += 64) {
+    // thread -> row r = tid % 64, columns c = tid / 64 + 4 u (u = 0..15)
+    const int r = tid & 63, c0 = tid >> 6;
+    double2 acc[16];
+    // W = Li A  (Li lower triangular: k <= r)
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc[u] = make_double2(0.0, 0.0);
+    for (int k = 0; k <= r && k < n; ++k) {
+        const double2 l = Ls[r][k];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) zfma(acc[u], l, As[k][c0 + 4 * u]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) As[r][c0 + 4 * u] = acc[u];
+    __syncthreads();
+    // C = W Li^H:  C[r][c] = sum_k W[r][k] conj(Li[c][k]),  k <= c
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const int c = c0 + 4 * u;
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int k = 0; k <= c && k < n; ++k) zfma(s2, As[r][k], zconj(Ls[c][k]));
+        acc[u] = s2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) As[r][c0 + 4 * u] = acc[u];
+    __syncthreads();
+    for (int t = tid; t < n * n; t += 256) {
         int i = t % n, j = t / n;
-        if (i < j) {
-            double2 x = Ws[i][j], y = Ws[j][i];
-            Ws[i][j] = zconj(y);
-            Ws[j][i] = zconj(x);
-        } else if (i == j) {
-            Ws[i][i] = zconj(Ws[i][i]);
-        }
-    }
-    __syncthreads();
-    // pass 2: C = L^-1 W^H
-    if (lane < n) {
-        for (int j = 0; j < n; ++j) {
-            double2 s = Ws[j][lane];
-            for (int k = 0; k < j; ++k) s = zsub(s, zmul(Ls[j][k], Ws[k][lane]));
-            Ws[j][lane] = zdiv(s, Ls[j][j]);
-        }
-    }
-    __syncthreads();
-    for (int t = lane; t < n * n; t += 64) {
-        int i = t % n, j = t / n;
-        if (i > j) A[i + (size_t)j * lda] = zscale(0.5, zadd(Ws[i][j], zconj(Ws[j][i])));
-        else if (i == j) A[i + (size_t)i * lda] = make_double2(Ws[i][i].x, 0.0);
+        if (i > j) A[i + (size_t)j * lda] = zscale(0.5, zadd(As[i][j], zconj(As[j][i])));
+        else if (i == j) A[i + (size_t)i * lda] = make_double2(As[i][i].x, 0.0);
     }
 }
 
@@ -284,7 +293,7 @@ static TriCtx tri_scratch(hgv_ctx_s *ctx, Arena &ar, int n, double2 **Linv) {
 
 static void invert_diag_blocks(hgv_ctx_s *ctx, int n, const double2 *L, int ldl, double2 *Linv) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(trtri_diag_kernel, dim3(cdiv(n, LEAF)), dim3(64), 0, ctx->stream, n, L, ldl, Linv);
+    hipLaunchKernelGGL(trtri_diag_kernel, dim3(cdiv(n, LEAF)), dim3(256), 0, ctx->stream, n, L, ldl, Linv);
     HGV_LAUNCH_CHECK();
 }
 
@@ -344,7 +353,7 @@ void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_inf
 static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2 *L, int ldl, const double2 *Linv) {
     if (n <= 0) return;
     if (n <= LEAF) {
-        hipLaunchKernelGGL(hegs2_kernel, dim3(1), dim3(64), 0, t.ctx->stream, n, A, lda, L, ldl);
+        hipLaunchKernelGGL(hegs2_kernel, dim3(1), dim3(256), 0, t.ctx->stream, n, A, lda, Linv);
         HGV_LAUNCH_CHECK();
         return;
     }

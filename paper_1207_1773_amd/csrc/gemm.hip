@@ -82,6 +82,7 @@ struct GemmDev {
     E *C; int ldc;
     int lower;
     int splits;        // split-K factor (gridDim.y)
+    int lower_tiles;   // grid enumerates only the tiles on or below the diagonal
     E *P;              // partial tiles when splits > 1: splits x (m x n), ld m
     int tiles_m, tiles_n;
 };
@@ -213,7 +214,7 @@ __device__ inline float2 e_add(float2 a, float2 b) { return make_float2(a.x + b.
 __device__ inline double e_add(double a, double b) { return a + b; }
 
 template <class T, int BM, int BN>
-__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
+__global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g) {
     typedef typename T::E E;
     typedef typename T::Acc Acc;
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -227,17 +228,40 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
     const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    // tile selection: XCD-aware remap, then column groups of 8 row tiles
-    const int total = g.tiles_m * g.tiles_n;
-    int id = remap_xcd(blockIdx.x, total);
-    constexpr int GROUP = 8;
-    int per_group = GROUP * g.tiles_n;
-    int grp = id / per_group;
-    int first_m = grp * GROUP;
-    int gm_cnt = min(g.tiles_m - first_m, GROUP);
-    int within = id % per_group;
-    int tm = first_m + within % gm_cnt;
-    int tn = within / gm_cnt;
+    // tile selection: XCD-aware remap (each XCD takes a contiguous range of
+    // tile ids), then either column groups of 8 row tiles, or, for outputs
+    // restricted to the lower triangle with square tiles, the lower tiles
+    // only, numbered row by row (so every XCD gets the same number of tiles
+    // and consecutive tiles share their row panel of A)
+    int tm, tn;
+    if (g.lower_tiles) {
+        const int total = (int)gridDim.x;
+        const int id = remap_xcd(blockIdx.x, total);
+        const int K = min(g.tiles_m, g.tiles_n);
+        const int T0 = K * (K + 1) / 2;
+        if (id < T0) {
+            int r = (int)((sqrt(8.0 * id + 1.0) - 1.0) * 0.5);
+            while (r > 0 && r * (r + 1) / 2 > id) --r;
+            while ((r + 1) * (r + 2) / 2 <= id) ++r;
+            tm = r;
+            tn = id - r * (r + 1) / 2;
+        } else {
+            const int q = id - T0;
+            tm = K + q / g.tiles_n;
+            tn = q % g.tiles_n;
+        }
+    } else {
+        const int total = g.tiles_m * g.tiles_n;
+        int id = remap_xcd(blockIdx.x, total);
+        constexpr int GROUP = 8;
+        int per_group = GROUP * g.tiles_n;
+        int grp = id / per_group;
+        int first_m = grp * GROUP;
+        int gm_cnt = min(g.tiles_m - first_m, GROUP);
+        int within = id % per_group;
+        tm = first_m + within % gm_cnt;
+        tn = within / gm_cnt;
+    }
     const int m0 = tm * BM, n0 = tn * BN;
     if (g.lower && m0 + BM - 1 < n0) return;  // tile entirely above the diagonal
 
@@ -249,14 +273,17 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
     const int c_beg = z * per;
     const int c_end = min(nchunks, c_beg + per);
 
-    Acc accR[FM][FN], accI[FM][FN];
+    // imaginary accumulators only for the complex types
+    constexpr int FMI = T::cplx ? FM : 1, FNI = T::cplx ? FN : 1;
+    Acc accR[FM][FN], accI[FMI][FNI];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            accR[i][j] = Acc{0, 0, 0, 0};
-            accI[i][j] = Acc{0, 0, 0, 0};
-        }
+        for (int j = 0; j < FN; ++j) accR[i][j] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < FMI; ++i)
+#pragma unroll
+        for (int j = 0; j < FNI; ++j) accI[i][j] = Acc{0, 0, 0, 0};
 
     E ra[NA], rb[NB];
     int ia[NA], ib[NB];
@@ -292,7 +319,8 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) mfma_step<T>(af[i], bf[j], accR[i][j], accI[i][j]);
+                for (int j = 0; j < FN; ++j)
+                    mfma_step<T>(af[i], bf[j], accR[i][j], accI[T::cplx ? i : 0][T::cplx ? j : 0]);
         }
     }
 
@@ -307,7 +335,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmDev<T> g) {
                 int col = n0 + wn * WN + j * 16 + (lane & 15);
                 if (row >= g.m || col >= g.n) continue;
                 if (g.lower && row < col) continue;
-                E v = make_e<T>(accR[i][j][r], accI[i][j][r]);
+                E v = make_e<T>(accR[i][j][r], accI[T::cplx ? i : 0][T::cplx ? j : 0][r]);
                 if (g.splits > 1) {
                     g.P[(size_t)z * g.m * g.n + row + (size_t)col * g.m] = v;
                 } else {
@@ -372,17 +400,26 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         // C = beta C only (alpha * empty sum); realised as a split-free launch
         // with no chunks.
     }
-    // tile shape: 64x64 (4 waves of 32x32) for the complex types; 128x64 for real
+    // tile shape: 64x64 (4 waves of 32x32) for the complex types; 128x128 for
+    // real (one MFMA per 16x16x4 block, so the larger tile keeps the operand
+    // bytes per flop as low as the complex tile's)
     constexpr int BM = T::cplx ? 64 : 128;
-    constexpr int BN = 64;
+    constexpr int BN = T::cplx ? 64 : 128;
     g.tiles_m = cdiv(a.m, BM);
     g.tiles_n = cdiv(a.n, BN);
     int tiles = g.tiles_m * g.tiles_n;
-    if (a.lower) tiles = tiles;  // upper tiles exit at once
+    g.lower_tiles = 0;
+    if (a.lower && BM == BN) {
+        // lower tiles of row tile tm: tn = 0 .. min(tm, tiles_n - 1)
+        const int K = std::min(g.tiles_m, g.tiles_n);
+        tiles = K * (K + 1) / 2 + (g.tiles_m - K) * g.tiles_n;
+        g.lower_tiles = 1;
+    }
     int chunks = cdiv(std::max(a.k, 0), BK) * g.nseg;
     int splits = 1;
     // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
-    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 16) splits *= 2;
+    // (every split keeps at least 8 chunks of depth BK)
+    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 8) splits *= 2;
     size_t need = (size_t)splits * a.m * a.n * sizeof(E);
     while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
         splits /= 2;
@@ -407,7 +444,7 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         e1 = ctx->ev_free.back(); ctx->ev_free.pop_back();
         HGV_HIP(hipEventRecord(e0, ctx->stream));
     }
-    dim3 grid(g.tiles_m * g.tiles_n, splits);
+    dim3 grid(tiles, splits);
     hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
     HGV_LAUNCH_CHECK();
     if (timed) {
