@@ -9,10 +9,10 @@
 //  * workgroup = 4 wave64s arranged 2 x 2; each wave owns a (BM/2) x (BN/2)
 //    sub-tile made of 16x16 MFMA blocks; registers are capped so that two
 //    workgroups share a CU (two waves per SIMD hide LDS and MFMA latency);
-//  * complex double: four real v_mfma_f64_16x16x4f64 per 16x16x4 complex block
-//    (re*re, -im*im into the real accumulator, re*im, im*re into the
-//    imaginary one); real double: one; complex float: four
-//    v_mfma_f32_16x16x4f32 with fp32 accumulation;
+//  * complex double: three real v_mfma_f64_16x16x4f64 per 16x16x4 complex
+//    block (the 3M form: re*re, im*im and (re+im)*(re+im) accumulated
+//    separately, combined in the epilogue); real double: one; complex float:
+//    three v_mfma_f32_16x16x4f32 with fp32 accumulation;
 //  * A and B tiles of depth 16 are staged through LDS (interleaved complex,
 //    one padding element per row against bank conflicts) with the next
 //    tile's global loads issued before the current tile's MFMAs;
@@ -174,27 +174,32 @@ __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int 
     }
 }
 
+// One 16x16x4 block product.  Complex types use three real products per
+// block (the 3M form):  P1 += Ar Br,  P2 += Ai Bi,  P3 += (Ar + Ai)(Br + Bi),
+// re = P1 - P2,  im = P3 - P1 - P2  (normwise the same error bound as the
+// four-product form up to a small constant; componentwise the imaginary part
+// is relative to (|Ar| + |Ai|)(|Br| + |Bi|)).
 template <class T>
-__device__ inline void mfma_step(typename T::E a, typename T::E b, typename T::Acc &ar, typename T::Acc &ai);
+__device__ inline void mfma_step(typename T::E a, typename T::E b, typename T::Acc &p1, typename T::Acc &p2,
+                                 typename T::Acc &p3);
 
 template <>
-__device__ inline void mfma_step<TZ>(double2 a, double2 b, v4d &ar, v4d &ai) {
-    ar = TZ::mfma(a.x, b.x, ar);
-    ar = TZ::mfma(-a.y, b.y, ar);
-    ai = TZ::mfma(a.x, b.y, ai);
-    ai = TZ::mfma(a.y, b.x, ai);
+__device__ inline void mfma_step<TZ>(double2 a, double2 b, v4d &p1, v4d &p2, v4d &p3) {
+    p1 = TZ::mfma(a.x, b.x, p1);
+    p2 = TZ::mfma(a.y, b.y, p2);
+    p3 = TZ::mfma(a.x + a.y, b.x + b.y, p3);
 }
 template <>
-__device__ inline void mfma_step<TC>(float2 a, float2 b, v4f &ar, v4f &ai) {
-    ar = TC::mfma(a.x, b.x, ar);
-    ar = TC::mfma(-a.y, b.y, ar);
-    ai = TC::mfma(a.x, b.y, ai);
-    ai = TC::mfma(a.y, b.x, ai);
+__device__ inline void mfma_step<TC>(float2 a, float2 b, v4f &p1, v4f &p2, v4f &p3) {
+    p1 = TC::mfma(a.x, b.x, p1);
+    p2 = TC::mfma(a.y, b.y, p2);
+    p3 = TC::mfma(a.x + a.y, b.x + b.y, p3);
 }
 template <>
-__device__ inline void mfma_step<TD>(double a, double b, v4d &ar, v4d &ai) {
-    (void)ai;
-    ar = TD::mfma(a, b, ar);
+__device__ inline void mfma_step<TD>(double a, double b, v4d &p1, v4d &p2, v4d &p3) {
+    (void)p2;
+    (void)p3;
+    p1 = TD::mfma(a, b, p1);
 }
 
 template <class T>
@@ -273,17 +278,20 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
     const int c_beg = z * per;
     const int c_end = min(nchunks, c_beg + per);
 
-    // imaginary accumulators only for the complex types
+    // P2 and P3 of the 3M form only for the complex types
     constexpr int FMI = T::cplx ? FM : 1, FNI = T::cplx ? FN : 1;
-    Acc accR[FM][FN], accI[FMI][FNI];
+    Acc acc1[FM][FN], acc2[FMI][FNI], acc3[FMI][FNI];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) accR[i][j] = Acc{0, 0, 0, 0};
+        for (int j = 0; j < FN; ++j) acc1[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < FMI; ++i)
 #pragma unroll
-        for (int j = 0; j < FNI; ++j) accI[i][j] = Acc{0, 0, 0, 0};
+        for (int j = 0; j < FNI; ++j) {
+            acc2[i][j] = Acc{0, 0, 0, 0};
+            acc3[i][j] = Acc{0, 0, 0, 0};
+        }
 
     E ra[NA], rb[NB];
     int ia[NA], ib[NB];
@@ -320,7 +328,8 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    mfma_step<T>(af[i], bf[j], accR[i][j], accI[T::cplx ? i : 0][T::cplx ? j : 0]);
+                    mfma_step<T>(af[i], bf[j], acc1[i][j], acc2[T::cplx ? i : 0][T::cplx ? j : 0],
+                                 acc3[T::cplx ? i : 0][T::cplx ? j : 0]);
         }
     }
 
@@ -335,7 +344,10 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
                 int col = n0 + wn * WN + j * 16 + (lane & 15);
                 if (row >= g.m || col >= g.n) continue;
                 if (g.lower && row < col) continue;
-                E v = make_e<T>(accR[i][j][r], accI[T::cplx ? i : 0][T::cplx ? j : 0][r]);
+                const typename T::S p1 = acc1[i][j][r];
+                const typename T::S p2 = acc2[T::cplx ? i : 0][T::cplx ? j : 0][r];
+                const typename T::S p3 = acc3[T::cplx ? i : 0][T::cplx ? j : 0][r];
+                E v = make_e<T>(p1 - p2, p3 - p1 - p2);
                 if (g.splits > 1) {
                     g.P[(size_t)z * g.m * g.n + row + (size_t)col * g.m] = v;
                 } else {

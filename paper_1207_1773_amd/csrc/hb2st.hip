@@ -402,8 +402,9 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int
 //   W = V^H Y_rows  (two 16x16 tiles, the k range split over the 4 waves),
 //   W <- T W        (T^H W for Q2^H; two tiles),
 //   Y_rows -= V W   (six row tiles).
-// A complex block product is four real MFMAs: v_mfma_f64_16x16x4f64 for double
-// storage, v_mfma_f32_16x16x4f32 (fp32 accumulation) for float storage.  V (the
+// A complex block product is three real MFMAs (3M form): v_mfma_f64_16x16x4f64
+// for double storage, v_mfma_f32_16x16x4f32 (fp32 accumulation) for float
+// storage.  V (the
 // (g+b-1) x g parallelogram, column t non-zero on rows t .. t+b-1) and T are
 // read from memory straight into operand registers (they are shared by all
 // workgroups and stay in L2); only the Y rows and W live in LDS.  k-steps of
@@ -429,12 +430,14 @@ template <> struct Q2M<float2> {
     __device__ static int orow(int lk, int r) { return 4 * lk + r; }
 };
 
+// complex block product in the 3M form (see gemm.hip): P1 += Ar Br,
+// P2 += Ai Bi, P3 += (Ar + Ai)(Br + Bi); re = P1 - P2, im = P3 - P1 - P2
 template <class E>
-__device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &re, typename Q2M<E>::Acc &im) {
-    re = Q2M<E>::mfma(a.x, b.x, re);
-    re = Q2M<E>::mfma(-a.y, b.y, re);
-    im = Q2M<E>::mfma(a.x, b.y, im);
-    im = Q2M<E>::mfma(a.y, b.x, im);
+__device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &p1, typename Q2M<E>::Acc &p2,
+                                typename Q2M<E>::Acc &p3) {
+    p1 = Q2M<E>::mfma(a.x, b.x, p1);
+    p2 = Q2M<E>::mfma(a.y, b.y, p2);
+    p3 = Q2M<E>::mfma(a.x + a.y, b.x + b.y, p3);
 }
 
 template <int BMAX, class E>
@@ -485,20 +488,20 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
             }
             __syncthreads();
             {
-                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
                 for (int q = 0; q < K1; ++q) {
                     int kq = kbeg + q;
-                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], re, im);
+                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], p1, p2, p3);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
+                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
             }
             __syncthreads();
             // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
             // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
             if (wave < 2) {
-                Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+                Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
                 const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
                 for (int l4 = lbeg; l4 < lend; l4 += 4) {
                     int row = t0 + lr, col = l4 + lk;
@@ -512,22 +515,22 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
                         }
                     }
                     E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
-                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
+                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), p1, p2, p3);
                 }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
+                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
             }
             __syncthreads();
             // step 3: Y_rows -= V W2, row tiles wave and wave + 4
             for (int q = wave; q < 6; q += 4) {
                 const int r0 = 16 * q;
                 if (r0 >= nrows) continue;
-                Acc re, im;
+                Acc p1, p2 = {0, 0, 0, 0}, p3;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     E y = Ys[r0 + Q2M<E>::orow(lk, i)][lr];
-                    re[i] = y.x;
-                    im[i] = y.y;
+                    p1[i] = y.x;
+                    p3[i] = y.x + y.y;
                 }
                 const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
                 E a3[8];
@@ -540,12 +543,12 @@ __global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     int t4 = tlo + 4 * u;
-                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
+                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], p1, p2, p3);
                 }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     int r = r0 + Q2M<E>::orow(lk, i);
-                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(re[i], im[i]);
+                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
                 }
             }
         }
@@ -594,20 +597,127 @@ __global__ __launch_bounds__(256) void q2_sb_kernel(int n, int m, int b, int g, 
         }
     };
     const int nsb = (ngrp + KS - 1) / KS;
-    for (int si = 0; si < nsb; ++si) {
+    // ---- the sequence of groups: super-block si, step ji, group Bi within the block
+    struct Blk {
+        int Blo, Bhi, S0, jn;
+    };
+    auto block = [&](int si) {
+        Blk k;
         const int SB = adj ? si : nsb - 1 - si;
-        const int Blo = SB * KS, Bhi = min(ngrp, Blo + KS) - 1;
-        const int S0 = Blo * g;
-        // steps with rows: the lowest group of the block has the most
-        const int jn = min(J, (n - 2 - S0) / b + 1);
-        int plo = 0, phi = -1;                 // window held in the ring
-        for (int ji = 0; ji < jn; ++ji) {
-            const int j = adj ? jn - 1 - ji : ji;
-            const int lo = S0 + 1 + j * b;
-            const int hi = min(n - 1, (Bhi + 1) * g + j * b + b - 1);
+        k.Blo = SB * KS;
+        k.Bhi = min(ngrp, k.Blo + KS) - 1;
+        k.S0 = k.Blo * g;
+        k.jn = min(J, (n - 2 - k.S0) / b + 1);   // the lowest group of the block has the most steps
+        return k;
+    };
+    struct Grp {
+        int B, j, s0, R0, nrows;
+    };
+    auto group = [&](int si, int ji, int Bi) {
+        const Blk k = block(si);
+        Grp q;
+        q.j = adj ? k.jn - 1 - ji : ji;
+        q.B = adj ? k.Blo + Bi : k.Bhi - Bi;
+        q.s0 = q.B * g;
+        q.R0 = q.s0 + 1 + q.j * b;
+        q.nrows = min(g + b - 1, n - q.R0);
+        return q;
+    };
+    // next group in application order whose rows start inside the matrix
+    auto advance = [&](int &si, int &ji, int &Bi) {
+        for (;;) {
+            ++Bi;
+            if (si >= nsb) return;
+            const Blk k = block(si);
+            if (Bi > k.Bhi - k.Blo) {
+                Bi = 0;
+                if (++ji >= k.jn) {
+                    ji = 0;
+                    if (++si >= nsb) return;
+                }
+            }
+            if (group(si, ji, Bi).R0 <= n - 1) return;
+        }
+    };
+    // ---- operand registers of one group (loaded one phase ahead of their use)
+    const int t0 = 16 * (wave & 1), kh = wave >> 1;
+    auto vget = [&](const Grp &q, int r, int t) -> E {
+        int i = r - t, s = q.s0 + t;
+        return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, q.j)[i] : zero;
+    };
+    E a1[K1], tv[GM / 4], a3[2][8];
+    int kbeg = 0, kend = 0;
+    auto load_a1 = [&](const Grp &q) {
+        // step-1 operands: wave -> (t tile, k half), conj(V)
+        const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
+        const int ka = (nks + 1) / 2;
+        kbeg = kh ? ka : 0;
+        kend = kh ? nks : ka;
+#pragma unroll
+        for (int u = 0; u < K1; ++u) {
+            int kq = kbeg + u;
+            E v = (kq < kend) ? vget(q, t0 + 4 * kq + lk, t0 + lr) : zero;
+            a1[u] = El<E>::mk(v.x, -v.y);
+        }
+    };
+    const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
+    auto load_tv = [&](const Grp &q) {
+        if (wave >= 2) return;
+        const E *tg = T2 + ((size_t)q.B * J + q.j) * g * g;
+#pragma unroll
+        for (int u = 0; u < GM / 4; ++u) {
+            const int l4 = lbeg + 4 * u;
+            const int row = t0 + lr, col = l4 + lk;
+            E v = zero;
+            if (l4 < lend && row < g && col < g) {
+                if (adj) {
+                    E w = tg[col + row * g];
+                    v = El<E>::mk(w.x, -w.y);
+                } else {
+                    v = tg[row + col * g];
+                }
+            }
+            tv[u] = v;
+        }
+    };
+    auto load_a3 = [&](const Grp &q) {
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+            const int r0 = 16 * (wave + 4 * qq);
+            const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t4 = tlo + 4 * u;
+                E v = (r0 < 96 && r0 < q.nrows && t4 < thi) ? vget(q, r0 + lr, t4 + lk) : zero;
+                a3[qq][u] = El<E>::mk(-v.x, -v.y);
+            }
+        }
+    };
+
+    int si = 0, ji = 0, Bi = -1;
+    advance(si, ji, Bi);
+    int csi = -1, cji = -1;                    // step whose window the ring holds
+    int plo = 0, phi = -1;
+    if (si < nsb) {
+        const Grp q = group(si, ji, Bi);
+        load_a1(q);
+        load_tv(q);
+        load_a3(q);
+    }
+    while (si < nsb) {
+        const Grp q = group(si, ji, Bi);
+        if (si != csi || ji != cji) {
+            // new step: move the ring window (store the rows that leave, load
+            // the rows that enter); a new super-block starts from an empty ring
+            const Blk k = block(si);
+            const int lo = k.S0 + 1 + q.j * b;
+            const int hi = min(n - 1, (k.Bhi + 1) * g + q.j * b + b - 1);
             __syncthreads();
-            if (phi >= plo) {
-                // rows that leave: [plo, lo - 1] and [hi + 1, phi]
+            if (si != csi) {
+                if (phi >= plo) store_rows(plo, phi);
+                plo = 0;
+                phi = -1;
+            } else {
                 if (lo - 1 >= plo) store_rows(plo, min(phi, lo - 1));
                 if (phi >= hi + 1) store_rows(max(plo, hi + 1), phi);
             }
@@ -620,99 +730,75 @@ __global__ __launch_bounds__(256) void q2_sb_kernel(int n, int m, int b, int g, 
             }
             plo = lo;
             phi = hi;
-            for (int Bi = 0; Bi <= Bhi - Blo; ++Bi) {
-                const int B = adj ? Blo + Bi : Bhi - Bi;
-                const int s0 = B * g;
-                const int R0 = s0 + 1 + j * b;
-                if (R0 > n - 1) continue;
-                const int nrows = min(g + b - 1, n - R0);
-                const E *tg = T2 + ((size_t)B * J + j) * g * g;
-                auto vget = [&](int r, int t) -> E {
-                    int i = r - t, s = s0 + t;
-                    return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
-                };
-                // step-1 operands: wave -> (t tile, k half)
-                const int t0 = 16 * (wave & 1), kh = wave >> 1;
-                const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
-                const int ka = (nks + 1) / 2;
-                const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
-                E a1[K1];
+            csi = si;
+            cji = ji;
+        }
+        int nsi = si, nji = ji, nBi = Bi;
+        advance(nsi, nji, nBi);
+        const bool more = nsi < nsb;
+        const Grp nq = more ? group(nsi, nji, nBi) : q;
+        __syncthreads();
+        // step 1: W partials = V^H Y_rows (this wave's t tile and k half)
+        {
+            Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    int kq = kbeg + q;
-                    E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
-                    a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
-                }
-                __syncthreads();
-                {
-                    Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+            for (int u = 0; u < K1; ++u) {
+                int kq = kbeg + u;
+                if (kq < kend) q2_cmfma<E>(a1[u], Yr[slot(q.R0 + t0 + 4 * kq + lk)][lr], p1, p2, p3);
+            }
 #pragma unroll
-                    for (int q = 0; q < K1; ++q) {
-                        int kq = kbeg + q;
-                        if (kq < kend) q2_cmfma<E>(a1[q], Yr[slot(R0 + t0 + 4 * kq + lk)][lr], re, im);
-                    }
+            for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+        }
+        if (more) load_a1(nq);
+        __syncthreads();
+        // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
+        // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
+        if (wave < 2) {
+            Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
-                }
-                __syncthreads();
-                // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
-                // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
-                if (wave < 2) {
-                    Acc re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-                    const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
-                    for (int l4 = lbeg; l4 < lend; l4 += 4) {
-                        int row = t0 + lr, col = l4 + lk;
-                        E tv = zero;
-                        if (row < g && col < g) {
-                            if (adj) {
-                                E u = tg[col + row * g];
-                                tv = El<E>::mk(u.x, -u.y);
-                            } else {
-                                tv = tg[row + col * g];
-                            }
-                        }
-                        E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
-                        q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), re, im);
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(re[i], im[i]);
-                }
-                __syncthreads();
-                // step 3: Y_rows -= V W2, row tiles wave and wave + 4
-                for (int q = wave; q < 6; q += 4) {
-                    const int r0 = 16 * q;
-                    if (r0 >= nrows) continue;
-                    Acc re, im;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        E y = Yr[slot(R0 + r0 + Q2M<E>::orow(lk, i))][lr];
-                        re[i] = y.x;
-                        im[i] = y.y;
-                    }
-                    const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-                    E a3[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        int t4 = tlo + 4 * u;
-                        E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
-                        a3[u] = El<E>::mk(-v.x, -v.y);
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        int t4 = tlo + 4 * u;
-                        if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], re, im);
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        int r = r0 + Q2M<E>::orow(lk, i);
-                        if (r < nrows) Yr[slot(R0 + r)][lr] = El<E>::mk(re[i], im[i]);
-                    }
+            for (int u = 0; u < GM / 4; ++u) {
+                const int l4 = lbeg + 4 * u;
+                if (l4 < lend) {
+                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
+                    q2_cmfma<E>(tv[u], El<E>::mk(w0.x + w1.x, w0.y + w1.y), p1, p2, p3);
                 }
             }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+            if (more) load_tv(nq);
         }
         __syncthreads();
-        if (phi >= plo) store_rows(plo, phi);
+        // step 3: Y_rows -= V W2, row tiles wave and wave + 4
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+            const int r0 = 16 * (wave + 4 * qq);
+            if (r0 >= 96 || r0 >= q.nrows) continue;
+            Acc p1, p2 = {0, 0, 0, 0}, p3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                E y = Yr[slot(q.R0 + r0 + Q2M<E>::orow(lk, i))][lr];
+                p1[i] = y.x;
+                p3[i] = y.x + y.y;
+            }
+            const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                int t4 = tlo + 4 * u;
+                if (t4 < thi) q2_cmfma<E>(a3[qq][u], W2[t4 + lk][lr], p1, p2, p3);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int r = r0 + Q2M<E>::orow(lk, i);
+                if (r < q.nrows) Yr[slot(q.R0 + r)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+            }
+        }
+        if (more) load_a3(nq);
+        si = nsi;
+        ji = nji;
+        Bi = nBi;
     }
+    __syncthreads();
+    if (phi >= plo) store_rows(plo, phi);
 }
 
 static int q2_group(int b) { return std::min(b, 32); }
@@ -733,14 +819,16 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
         hipLaunchKernelGGL((q2_tbuild_kernel<64, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     HGV_LAUNCH_CHECK();
-    // The super-block kernel keeps Y rows in LDS (fewer global round trips
-    // per group) but its larger LDS footprint allows two workgroups per CU
-    // instead of three; with more column tiles than two per CU the per-group
-    // kernel's occupancy wins.
+    // The super-block kernel keeps Y rows in LDS and loads every group's V and
+    // T operands one phase ahead of their use, which hides most of the load
+    // latency of a workgroup that is alone on its CU; its register and LDS
+    // footprint allows one workgroup per CU.  With more column tiles than CUs
+    // the per-group kernel (three workgroups per CU hide each other's
+    // latencies) wins.
     int cus = 0;
     HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     const int tiles = cdiv(m, 16);
-    const bool sb = tiles <= 2 * cus;
+    const bool sb = tiles <= cus;
     if (b <= 32) {
         if (sb)
             hipLaunchKernelGGL((q2_sb_kernel<32, Q2_KS, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J,
