@@ -55,10 +55,13 @@ __host__ __device__ inline int hb_tasks(int n, int b, int s) { return (n - 2 - s
 
 template <class E>
 __device__ inline double2 band_get(const E *AB, int ldb, int r, int c) {
-    // element (r, c) of the Hermitian band (r, c in range, |r - c| < ldb)
-    if (r >= c) return El<E>::to(AB[(r - c) + (size_t)c * ldb]);
-    double2 v = El<E>::to(AB[(c - r) + (size_t)r * ldb]);
-    return make_double2(v.x, -v.y);
+    // element (r, c) of the Hermitian band (r, c in range, |r - c| < ldb);
+    // branch-free, so that a thread's loads of a block are all in flight at once
+    const bool low = r >= c;
+    const int off = low ? r - c : c - r, col = low ? c : r;
+    double2 v = El<E>::to(AB[off + (size_t)col * ldb]);
+    v.y = low ? v.y : -v.y;
+    return v;
 }
 
 __device__ inline double wave_sum(double x) {
@@ -90,6 +93,9 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
     constexpr int TPR = 256 / BM;   // lanes per row
     constexpr int NU = BM / TPR;    // row elements per lane
     __shared__ double2 Es[BM][BM + 1];
+    // staging of E for the LDS-direct loads: column c at Et[c][0 .. BM-1], each
+    // column a contiguous 64 x 16-byte run (unused for narrower bands)
+    __shared__ E Et[BM == 64 && sizeof(E) == 16 ? BM : 1][BM];
     __shared__ double2 v[BM], vp[BM], pv[BM];
     __shared__ double2 sh_tau, sh_taup;
     __shared__ double sh_beta;
@@ -125,19 +131,62 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
             const int L = min(b, n - r0);          // rows of this task
             const int p0 = r0 - b;                 // first column of E (j > 0)
             // ---- D row into registers, E (or column s) into LDS --------------------
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                int k = q + TPR * u;
-                Dr[u] = (row < L && k < L) ? band_get(AB, ldb, r0 + row, r0 + k) : zero;
-            }
+            // Every load is issued unconditionally (out-of-block elements read the
+            // in-range diagonal element (r0, r0) and are zeroed afterwards), so a
+            // thread's 2 * NU loads are in flight together instead of one after
+            // another.
             if (j == 0) {
                 if (tid < BM) Es[tid][0] = (tid < L) ? bld((r0 + tid - s) + (size_t)s * ldb) : zero;
+            } else if constexpr (BM == 64 && sizeof(E) == 16) {
+                // LDS-direct loads (no registers, all in flight at once): wave w
+                // stages columns w, w + 4, ... of E, lane i taking row i (column c
+                // of E is contiguous in the band storage); elements outside the
+                // block read the in-range element (r0, r0) and are zeroed in the
+                // copy into Es
+#pragma unroll
+                for (int cc = 0; cc < BM / 4; ++cc) {
+                    const int c = (tid >> 6) + 4 * cc, i = lane;
+                    const bool in = i < L && c < b;
+                    const size_t idx = in ? (r0 + i - p0 - c) + (size_t)(p0 + c) * ldb : (size_t)r0 * ldb;
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(AB + idx),
+                                                     (__attribute__((address_space(3))) void *)(&Et[c][0]), 16, 0,
+                                                     0);
+                }
+                // the D block's loads go out while E's are in flight
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int k = q + TPR * u;
+                    const bool in = row < L && k < L;
+                    Dr[u] = band_get(AB, ldb, r0 + (in ? row : 0), r0 + (in ? k : 0));
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < BM * BM / 256; ++u) {
+                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                    Es[i][c] = (i < L && c < b) ? El<E>::to(Et[c][i]) : zero;
+                }
             } else {
 #pragma unroll
                 for (int t = tid; t < BM * BM; t += 256) {
                     int i = t % BM, c = t / BM;
                     Es[i][c] = (i < L && c < b) ? bld((r0 + i - p0 - c) + (size_t)(p0 + c) * ldb) : zero;
                 }
+            }
+            // (after E in the register-staged paths: the D registers are then not
+            // yet live, which leaves room for E's loads)
+            if (!(BM == 64 && sizeof(E) == 16) || j == 0) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int k = q + TPR * u;
+                    const bool in = row < L && k < L;
+                    Dr[u] = band_get(AB, ldb, r0 + (in ? row : 0), r0 + (in ? k : 0));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = q + TPR * u;
+                if (!(row < L && k < L)) Dr[u] = zero;
             }
             __syncthreads();
             if (j > 0) {
@@ -245,7 +294,9 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
             __syncthreads();
             if (tid < BM) vp[tid] = v[tid];
             if (tid == 0) sh_taup = tau;
-            __threadfence();
+            // every thread's stores have reached the L2 before the barrier; thread
+            // 0's release store then writes the L2 back once for the workgroup
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) __hip_atomic_store(&a.prog[s], j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
