@@ -26,14 +26,16 @@
 // equals the sequential one bit for bit.  Progress counters are published
 // with release stores and read with acquire loads at device (agent) scope.
 //
-// Q2 back-transformation: the reflectors H_{s,j} of b consecutive sweeps
-// s0 .. s0+b-1 at the same step j occupy a (2b-1) x b parallelogram of rows;
-// their product D = H_{s0} ... H_{s0+b-1} = I - V T V^H (compact WY).
+// Q2 back-transformation: the reflectors H_{s,j} of g = min(b, 32)
+// consecutive sweeps s0 .. s0+g-1 at the same step j occupy a (g+b-1) x g
+// parallelogram of rows; their product H_{s0} ... H_{s0+g-1} = I - V T V^H
+// (compact WY).
 // Applying Q2 = prod_s prod_j H_{s,j} to Y is the same as applying the
 // groups block by block from the last block of sweeps to the first and,
 // within a block, with j ascending: any two reflectors whose rows overlap
-// keep their relative order.  Each workgroup owns a panel of columns of Y and
-// walks the groups in that order (no synchronisation between workgroups).
+// keep their relative order.  Groups on one anti-diagonal of the (block, j)
+// grid touch disjoint rows, so each anti-diagonal is one launch over
+// (group, column tile) pairs.
 #include <algorithm>
 
 #include "hgv_internal.h"
@@ -52,17 +54,6 @@ struct HbArgs {
 };
 
 __host__ __device__ inline int hb_tasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
-
-template <class E>
-__device__ inline double2 band_get(const E *AB, int ldb, int r, int c) {
-    // element (r, c) of the Hermitian band (r, c in range, |r - c| < ldb);
-    // branch-free, so that a thread's loads of a block are all in flight at once
-    const bool low = r >= c;
-    const int off = low ? r - c : c - r, col = low ? c : r;
-    double2 v = El<E>::to(AB[off + (size_t)col * ldb]);
-    v.y = low ? v.y : -v.y;
-    return v;
-}
 
 __device__ inline double wave_sum(double x) {
 #pragma unroll
@@ -130,13 +121,31 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
             const int r0 = s + 1 + j * b;
             const int L = min(b, n - r0);          // rows of this task
             const int p0 = r0 - b;                 // first column of E (j > 0)
+            // D row of this thread, read raw from the lower band (elements above
+            // the diagonal from their mirror); bit u of the result marks Dr[u] as
+            // mirrored (to be conjugated once the loads have arrived, so that no
+            // load waits for the previous one)
+            auto load_d = [&]() {
+                unsigned up = 0;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int k = q + TPR * u;
+                    const bool in = row < L && k < L;
+                    const int rr = r0 + (in ? row : 0), kk = r0 + (in ? k : 0);
+                    const bool low = rr >= kk;
+                    up |= (low ? 0u : 1u) << u;
+                    Dr[u] = El<E>::to(AB[(low ? rr - kk : kk - rr) + (size_t)(low ? kk : rr) * ldb]);
+                }
+                return up;
+            };
+            unsigned upper = 0;
             // ---- D row into registers, E (or column s) into LDS --------------------
             // Every load is issued unconditionally (out-of-block elements read the
             // in-range diagonal element (r0, r0) and are zeroed afterwards), so a
             // thread's 2 * NU loads are in flight together instead of one after
             // another.
             if (j == 0) {
-                if (tid < BM) Es[tid][0] = (tid < L) ? bld((r0 + tid - s) + (size_t)s * ldb) : zero;
+                if (tid < BM) Es[tid][0] = zsel(tid < L, bld(tid < L ? (r0 + tid - s) + (size_t)s * ldb : (size_t)s * ldb), zero);
             } else if constexpr (BM == 64 && sizeof(E) == 16) {
                 // LDS-direct loads (no registers, all in flight at once): wave w
                 // stages columns w, w + 4, ... of E, lane i taking row i (column c
@@ -153,40 +162,37 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
                                                      0);
                 }
                 // the D block's loads go out while E's are in flight
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int k = q + TPR * u;
-                    const bool in = row < L && k < L;
-                    Dr[u] = band_get(AB, ldb, r0 + (in ? row : 0), r0 + (in ? k : 0));
-                }
+                upper = load_d();
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < BM * BM / 256; ++u) {
                     const int t = tid + 256 * u, i = t % BM, c = t / BM;
-                    Es[i][c] = (i < L && c < b) ? El<E>::to(Et[c][i]) : zero;
+                    Es[i][c] = zsel(i < L && c < b, El<E>::to(Et[c][i]), zero);
                 }
             } else {
+                // E through registers: all of a thread's E and D loads are issued
+                // before the first one is waited for
+                E ev[BM * BM / 256];
 #pragma unroll
-                for (int t = tid; t < BM * BM; t += 256) {
-                    int i = t % BM, c = t / BM;
-                    Es[i][c] = (i < L && c < b) ? bld((r0 + i - p0 - c) + (size_t)(p0 + c) * ldb) : zero;
+                for (int u = 0; u < BM * BM / 256; ++u) {
+                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                    const bool in = i < L && c < b;
+                    ev[u] = AB[in ? (r0 + i - p0 - c) + (size_t)(p0 + c) * ldb : (size_t)r0 * ldb];
+                }
+                upper = load_d();
+#pragma unroll
+                for (int u = 0; u < BM * BM / 256; ++u) {
+                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                    Es[i][c] = zsel(i < L && c < b, El<E>::to(ev[u]), zero);
                 }
             }
-            // (after E in the register-staged paths: the D registers are then not
-            // yet live, which leaves room for E's loads)
-            if (!(BM == 64 && sizeof(E) == 16) || j == 0) {
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int k = q + TPR * u;
-                    const bool in = row < L && k < L;
-                    Dr[u] = band_get(AB, ldb, r0 + (in ? row : 0), r0 + (in ? k : 0));
-                }
-            }
+            if (j == 0) upper = load_d();
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int k = q + TPR * u;
-                if (!(row < L && k < L)) Dr[u] = zero;
+                const double2 d = Dr[u];
+                Dr[u] = zsel(row < L && k < L, make_double2(d.x, ((upper >> u) & 1u) ? -d.y : d.y), zero);
             }
             __syncthreads();
             if (j > 0) {
@@ -209,7 +215,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
             }
             // ---- reflector from Es[:, 0] (wave 0) -------------------------------------
             if (tid < 64) {
-                double2 x = (lane < L) ? Es[lane][0] : zero;
+                double2 x = zsel(lane < L, Es[lane < BM ? lane : 0][0], zero);
                 double t2 = wave_sum((lane >= 1) ? zabs2(x) : 0.0);
                 double2 alpha = make_double2(__shfl(x.x, 0, 64), __shfl(x.y, 0, 64));
                 double beta;
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
                     tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
                     scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
                 }
-                if (lane < BM) v[lane] = (lane >= L) ? zero : (lane == 0 ? make_double2(1.0, 0.0) : zmul(scale, x));
+                if (lane < BM) v[lane] = zsel(lane < L, zsel(lane == 0, make_double2(1.0, 0.0), zmul(scale, x)), zero);
                 if (lane == 0) {
                     sh_beta = beta;
                     sh_tau = tau;
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
             const double2 tau = sh_tau;
             const double beta = sh_beta;
             if (j == 0) {
-                if (tid < L) bst((r0 + tid - s) + (size_t)s * ldb, (tid == 0) ? make_double2(beta, 0.0) : zero);
+                if (tid < L) bst((r0 + tid - s) + (size_t)s * ldb, zsel(tid == 0, make_double2(beta, 0.0), zero));
             } else {
                 // E[:, 1:] <- E - conj(tau) v (v^H E);  E[:, 0] = beta e_1   (column owners)
                 const int c = row;   // lane group -> column
@@ -250,8 +256,8 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
                     for (int u = 0; u < NU; ++u) {
                         int i = q + TPR * u;
                         if (i < L) {
-                            double2 val = (c == 0) ? (i == 0 ? make_double2(beta, 0.0) : zero)
-                                                   : zsub(Es[i][c], zmul(v[i], wc));
+                            double2 val = zsel(c == 0, zsel(i == 0, make_double2(beta, 0.0), zero),
+                                               zsub(Es[i][c], zmul(v[i], wc)));
                             bst((r0 + i - p0 - c) + (size_t)(p0 + c) * ldb, val);
                         }
                     }
@@ -263,10 +269,10 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
 #pragma unroll
                 for (int u = 0; u < NU; ++u) acc = zadd(acc, zmul(Dr[u], v[q + TPR * u]));
                 double2 prow = zmul(tau, group_sum<TPR>(acc));
-                if (q == 0) pv[row] = (row < L) ? prow : zero;
+                if (q == 0) pv[row] = zsel(row < L, prow, zero);
                 __syncthreads();
                 // w = p - 1/2 conj(tau) (v^H p) v   (the scalar is real; same order in every wave)
-                double2 c1 = (lane < BM) ? zcmul(v[lane], pv[lane]) : zero;
+                double2 c1 = zsel(lane < BM, zcmul(v[lane < BM ? lane : 0], pv[lane < BM ? lane : 0]), zero);
                 double vr = wave_sum(c1.x), vi = wave_sum(c1.y);
                 double half = 0.5 * zcmul(tau, make_double2(vr, vi)).x;
                 double2 wrow = zsub(prow, zscale(half, v[row]));
@@ -446,20 +452,9 @@ __global__ __launch_bounds__(256) void q2_tbuild_kernel(int n, int b, int g, int
     for (int t = tid; t < g * g; t += 256) tout[t] = El<E>::from(Ts[t % g][t / g]);   // column-major g x g
 }
 
-// Y (n x m) <- Q2 Y (or Q2^H Y) on MFMA tiles.  Workgroup = 16 columns of Y (so
-// two or three workgroups share a CU and hide each other's latencies); for
-// every group, walked from the last group of sweeps to the first with j
-// ascending for Q2 (first to last, j descending, for Q2^H):
-//   W = V^H Y_rows  (two 16x16 tiles, the k range split over the 4 waves),
-//   W <- T W        (T^H W for Q2^H; two tiles),
-//   Y_rows -= V W   (six row tiles).
-// A complex block product is three real MFMAs (3M form): v_mfma_f64_16x16x4f64
-// for double storage, v_mfma_f32_16x16x4f32 (fp32 accumulation) for float
-// storage.  V (the
-// (g+b-1) x g parallelogram, column t non-zero on rows t .. t+b-1) and T are
-// read from memory straight into operand registers (they are shared by all
-// workgroups and stay in L2); only the Y rows and W live in LDS.  k-steps of
-// tiles that are entirely zero are skipped.
+// Y (n x m) <- Q2 Y (or Q2^H Y) on MFMA tiles.  A complex block product is
+// three real MFMAs (3M form): v_mfma_f64_16x16x4f64 for double storage,
+// v_mfma_f32_16x16x4f32 (fp32 accumulation) for float storage.
 typedef double q2v4d __attribute__((ext_vector_type(4)));
 typedef float q2v4f __attribute__((ext_vector_type(4)));
 
@@ -491,369 +486,170 @@ __device__ inline void q2_cmfma(E a, E b, typename Q2M<E>::Acc &p1, typename Q2M
     p3 = Q2M<E>::mfma(a.x + a.y, b.x + b.y, p3);
 }
 
+// Wavefront schedule.  Group (B, j) overlaps groups of later blocks only at
+// j' <= j and groups of earlier blocks only at j' >= j, and (B, j') for
+// |j' - j| = 1; so the groups with (ngrp - 1 - B) + j = w (one anti-diagonal
+// of the (B, j) grid) touch pairwise disjoint rows, and applying the
+// anti-diagonals w = 0, 1, ... in turn (every group of one of them in
+// parallel) keeps every overlapping pair in the order of Q2; Q2^H runs the
+// anti-diagonals in reverse.  One launch per anti-diagonal; a workgroup applies
+// one group to 32 columns of Y:
+//   Y_rows (g+b-1 rows) -> LDS,
+//   W  = V^H Y_rows   (four 16x16 tiles, one per wave, whole k range),
+//   W2 = T W          (T^H W for Q2^H; T read into registers up front),
+//   Y_rows -= V W2    (twelve 16x16 tiles, three per wave, results to LDS),
+//   Y_rows -> Y       (column-contiguous stores).
+// V and T are read straight into MFMA operand registers from memory that the
+// column tiles of the group share; the tiles of one group are given
+// consecutive workgroup slots of one XCD, so they share that XCD's L2.  All
+// operand loads are unconditional (clamped address, zeroed after), so a
+// wave's loads are in flight together.
+constexpr int Q2WF_NC = 32;
+
 template <int BMAX, class E>
-__global__ __launch_bounds__(256) void q2_mfma_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
-                                                       const E *V2, const E *T2, E *Y, int ldy) {
+__global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int g, int J, int Bt, int jlo, int ngs,
+                                                        int adj, const E *V2, const E *T2, E *Y, int ldy) {
     typedef typename Q2M<E>::Acc Acc;
-    constexpr int NC = 16, GM = 32, RM = 96;
-    constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
+    constexpr int NC = Q2WF_NC, GM = 32, RM = 96;
+    constexpr int K1 = (BMAX + 15 + 3) / 4;   // k-steps of a W tile
     __shared__ E Ys[RM][NC + 1];
-    __shared__ E Wp[2][GM][NC + 1];           // partial W over the two k halves
-    __shared__ E W2[GM][NC + 1];
+    __shared__ E Ws[GM][NC + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int c0 = blockIdx.x * NC;
+    const int ct = (m + NC - 1) / NC;
+    const int items = ngs * ct;
+    // item p = (group, column tile); the 8 XCDs take contiguous ranges of p
+    const int per = (items + 7) / 8;
+    const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (p >= items) return;
+    const int j = jlo + p / ct, c0 = (p % ct) * NC;
     const int nc = min(NC, m - c0);
+    const int B = Bt + j, s0 = B * g;
+    const int R0 = s0 + 1 + j * b;
+    const int nrows = min(g + b - 1, n - R0);
+    const E *tg = T2 + ((size_t)B * J + j) * g * g;
     const E zero = El<E>::mk(0.0, 0.0);
-    for (int Bi = 0; Bi < ngrp; ++Bi) {
-        const int B = adj ? Bi : ngrp - 1 - Bi;
-        const int s0 = B * g;
-        // rows start at s0 + 1 + j b; the last step with rows left is j = jn - 1
-        const int jn = min(J, (n - 2 - s0) / b + 1);
-        for (int ji = 0; ji < jn; ++ji) {
-            const int j = adj ? jn - 1 - ji : ji;
-            const int R0 = s0 + 1 + j * b;
-            const int nrows = min(g + b - 1, n - R0);
-            const E *tg = T2 + ((size_t)B * J + j) * g * g;
-            // element (r, t) of the parallelogram V
-            auto vget = [&](int r, int t) -> E {
-                int i = r - t, s = s0 + t;
-                return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, j)[i] : zero;
-            };
-            __syncthreads();
-            for (int t = tid; t < RM * NC; t += 256) {
-                int r = t % RM, c = t / RM;
-                Ys[r][c] = (r < nrows && c < nc) ? Y[R0 + r + (size_t)(c0 + c) * ldy] : zero;
-            }
-            // step-1 operands: wave -> (t tile, k half)
-            const int t0 = 16 * (wave & 1), kh = wave >> 1;
-            const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
-            const int ka = (nks + 1) / 2;
-            const int kbeg = kh ? ka : 0, kend = kh ? nks : ka;
-            E a1[K1];
-#pragma unroll
-            for (int q = 0; q < K1; ++q) {
-                int kq = kbeg + q;
-                E v = (kq < kend) ? vget(t0 + 4 * kq + lk, t0 + lr) : zero;
-                a1[q] = El<E>::mk(v.x, -v.y);   // conj(V)
-            }
-            __syncthreads();
-            {
-                Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
-#pragma unroll
-                for (int q = 0; q < K1; ++q) {
-                    int kq = kbeg + q;
-                    if (kq < kend) q2_cmfma<E>(a1[q], Ys[t0 + 4 * kq + lk][lr], p1, p2, p3);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
-            }
-            __syncthreads();
-            // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
-            // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
-            if (wave < 2) {
-                Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
-                const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
-                for (int l4 = lbeg; l4 < lend; l4 += 4) {
-                    int row = t0 + lr, col = l4 + lk;
-                    E tv = zero;
-                    if (row < g && col < g) {
-                        if (adj) {
-                            E u = tg[col + row * g];
-                            tv = El<E>::mk(u.x, -u.y);
-                        } else {
-                            tv = tg[row + col * g];
-                        }
-                    }
-                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
-                    q2_cmfma<E>(tv, El<E>::mk(w0.x + w1.x, w0.y + w1.y), p1, p2, p3);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
-            }
-            __syncthreads();
-            // step 3: Y_rows -= V W2, row tiles wave and wave + 4
-            for (int q = wave; q < 6; q += 4) {
-                const int r0 = 16 * q;
-                if (r0 >= nrows) continue;
-                Acc p1, p2 = {0, 0, 0, 0}, p3;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    E y = Ys[r0 + Q2M<E>::orow(lk, i)][lr];
-                    p1[i] = y.x;
-                    p3[i] = y.x + y.y;
-                }
-                const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-                E a3[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int t4 = tlo + 4 * u;
-                    E v = (t4 < thi) ? vget(r0 + lr, t4 + lk) : zero;
-                    a3[u] = El<E>::mk(-v.x, -v.y);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int t4 = tlo + 4 * u;
-                    if (t4 < thi) q2_cmfma<E>(a3[u], W2[t4 + lk][lr], p1, p2, p3);
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    int r = r0 + Q2M<E>::orow(lk, i);
-                    if (r < nrows && lr < nc) Y[R0 + r + (size_t)(c0 + lr) * ldy] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
-                }
-            }
+    const int sblk = s0 / b, soff = s0 % b;
+    // V(r, t): row r of the group's parallelogram, reflector t (sweep s0 + t)
+    // (a ternary on the vector type would be compiled as a select of addresses
+    // through scratch memory, so values are selected per component)
+    auto keep = [](bool in, E v) -> E { return El<E>::mk(in ? v.x : 0.0, in ? v.y : 0.0); };
+    auto vld = [&](bool ok, int r, int t) -> E {
+        const int i = r - t;
+        int sb = soff + t, blk = sblk;
+        if (sb >= b) {
+            sb -= b;
+            ++blk;
         }
-    }
-}
-
-// Super-blocks: the groups B = KS*SB .. KS*SB + KS - 1 of one step j touch the
-// rows [KS*SB*g + 1 + j b, (KS*SB + KS) g + j b + b - 1].  Applying, for j
-// ascending, these KS groups (B descending) before moving on keeps every pair
-// of overlapping groups in the order of Q2 (a group (B, j) overlaps (B - 1, j')
-// only for j' >= j, and (B + 1, j') only for j' <= j), so a workgroup keeps the
-// window of Y rows of one super-block in an LDS ring buffer: each step stores
-// the b rows that leave the window and loads the b rows that enter it, and Y
-// crosses HBM twice per super-block instead of twice per group.  Q2^H runs the
-// exact reverse order (super-blocks ascending, j descending, B ascending).
-template <int BMAX, int KS, class E>
-__global__ __launch_bounds__(256) void q2_sb_kernel(int n, int m, int b, int g, int J, int ngrp, int adj,
-                                                     const E *V2, const E *T2, E *Y, int ldy) {
-    typedef typename Q2M<E>::Acc Acc;
-    constexpr int NC = 16, GM = 32, RM = 96;
-    constexpr int HR = KS * GM + BMAX;        // ring rows (>= window height KS g + b - 1)
-    constexpr int K1 = (BMAX + 16 + 7) / 8;   // k-steps of one half of a W tile's k range
-    __shared__ E Yr[HR][NC + 1];
-    __shared__ E Wp[2][GM][NC + 1];           // partial W over the two k halves
-    __shared__ E W2[GM][NC + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int c0 = blockIdx.x * NC;
-    const int nc = min(NC, m - c0);
-    const E zero = El<E>::mk(0.0, 0.0);
-    auto slot = [&](int row) { return row % HR; };
-    for (int t = tid; t < HR * (NC + 1); t += 256) Yr[t / (NC + 1)][t % (NC + 1)] = zero;
-    // rows [lo, hi] between the ring and Y
-    auto store_rows = [&](int lo, int hi) {
-        const int len = hi - lo + 1;
-        for (int t = tid; t < len * NC; t += 256) {
-            int r = t % len, c = t / len;
-            if (c < nc) Y[lo + r + (size_t)(c0 + c) * ldy] = Yr[slot(lo + r)][c];
-        }
+        const bool in = ok && t < g && i >= 0 && i < b && s0 + t <= n - 2;
+        return keep(in, V2[in ? (((size_t)blk * J + j) * b + sb) * b + i : 0]);
     };
-    auto load_rows = [&](int lo, int hi) {
-        const int len = hi - lo + 1;
-        for (int t = tid; t < len * NC; t += 256) {
-            int r = t % len, c = t / len;
-            Yr[slot(lo + r)][c] = (c < nc) ? Y[lo + r + (size_t)(c0 + c) * ldy] : zero;
-        }
+    auto tld = [&](bool ok, int row, int col) -> E {
+        const bool in = ok && row < g && col < g;
+        const E v = keep(in, tg[in ? (adj ? col + (size_t)row * g : row + (size_t)col * g) : 0]);
+        return El<E>::mk(v.x, adj ? -v.y : v.y);
     };
-    const int nsb = (ngrp + KS - 1) / KS;
-    // ---- the sequence of groups: super-block si, step ji, group Bi within the block
-    struct Blk {
-        int Blo, Bhi, S0, jn;
-    };
-    auto block = [&](int si) {
-        Blk k;
-        const int SB = adj ? si : nsb - 1 - si;
-        k.Blo = SB * KS;
-        k.Bhi = min(ngrp, k.Blo + KS) - 1;
-        k.S0 = k.Blo * g;
-        k.jn = min(J, (n - 2 - k.S0) / b + 1);   // the lowest group of the block has the most steps
-        return k;
-    };
-    struct Grp {
-        int B, j, s0, R0, nrows;
-    };
-    auto group = [&](int si, int ji, int Bi) {
-        const Blk k = block(si);
-        Grp q;
-        q.j = adj ? k.jn - 1 - ji : ji;
-        q.B = adj ? k.Blo + Bi : k.Bhi - Bi;
-        q.s0 = q.B * g;
-        q.R0 = q.s0 + 1 + q.j * b;
-        q.nrows = min(g + b - 1, n - q.R0);
-        return q;
-    };
-    // next group in application order whose rows start inside the matrix
-    auto advance = [&](int &si, int &ji, int &Bi) {
-        for (;;) {
-            ++Bi;
-            if (si >= nsb) return;
-            const Blk k = block(si);
-            if (Bi > k.Bhi - k.Blo) {
-                Bi = 0;
-                if (++ji >= k.jn) {
-                    ji = 0;
-                    if (++si >= nsb) return;
-                }
-            }
-            if (group(si, ji, Bi).R0 <= n - 1) return;
-        }
-    };
-    // ---- operand registers of one group (loaded one phase ahead of their use)
-    const int t0 = 16 * (wave & 1), kh = wave >> 1;
-    auto vget = [&](const Grp &q, int r, int t) -> E {
-        int i = r - t, s = q.s0 + t;
-        return (t < g && i >= 0 && i < b && s <= n - 2) ? v2_ptr(V2, b, J, s, q.j)[i] : zero;
-    };
-    E a1[K1], tv[GM / 4], a3[2][8];
-    int kbeg = 0, kend = 0;
-    auto load_a1 = [&](const Grp &q) {
-        // step-1 operands: wave -> (t tile, k half), conj(V)
-        const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
-        const int ka = (nks + 1) / 2;
-        kbeg = kh ? ka : 0;
-        kend = kh ? nks : ka;
-#pragma unroll
-        for (int u = 0; u < K1; ++u) {
-            int kq = kbeg + u;
-            E v = (kq < kend) ? vget(q, t0 + 4 * kq + lk, t0 + lr) : zero;
-            a1[u] = El<E>::mk(v.x, -v.y);
-        }
-    };
+    // wave -> (t tile, column tile) of W and W2
+    const int t0 = 16 * (wave & 1), cc = 16 * (wave >> 1);
+    // step-2 operands, loaded first
     const int lbeg = adj ? 0 : t0, lend = adj ? t0 + 16 : GM;
-    auto load_tv = [&](const Grp &q) {
-        if (wave >= 2) return;
-        const E *tg = T2 + ((size_t)q.B * J + q.j) * g * g;
+    E tv[8];
 #pragma unroll
-        for (int u = 0; u < GM / 4; ++u) {
-            const int l4 = lbeg + 4 * u;
-            const int row = t0 + lr, col = l4 + lk;
-            E v = zero;
-            if (l4 < lend && row < g && col < g) {
-                if (adj) {
-                    E w = tg[col + row * g];
-                    v = El<E>::mk(w.x, -w.y);
-                } else {
-                    v = tg[row + col * g];
-                }
-            }
-            tv[u] = v;
-        }
-    };
-    auto load_a3 = [&](const Grp &q) {
+    for (int u = 0; u < 8; ++u) tv[u] = tld(lbeg + 4 * u < lend, t0 + lr, lbeg + 4 * u + lk);
+    // step-1 operands conj(V)
+    const int nks = (min(RM, t0 + 15 + b) - t0 + 3) / 4;
+    E a1[K1];
 #pragma unroll
-        for (int qq = 0; qq < 2; ++qq) {
-            const int r0 = 16 * (wave + 4 * qq);
-            const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t4 = tlo + 4 * u;
-                E v = (r0 < 96 && r0 < q.nrows && t4 < thi) ? vget(q, r0 + lr, t4 + lk) : zero;
-                a3[qq][u] = El<E>::mk(-v.x, -v.y);
-            }
-        }
-    };
-
-    int si = 0, ji = 0, Bi = -1;
-    advance(si, ji, Bi);
-    int csi = -1, cji = -1;                    // step whose window the ring holds
-    int plo = 0, phi = -1;
-    if (si < nsb) {
-        const Grp q = group(si, ji, Bi);
-        load_a1(q);
-        load_tv(q);
-        load_a3(q);
+    for (int q = 0; q < K1; ++q) {
+        const E v = vld(q < nks, t0 + 4 * q + lk, t0 + lr);
+        a1[q] = El<E>::mk(v.x, -v.y);
     }
-    while (si < nsb) {
-        const Grp q = group(si, ji, Bi);
-        if (si != csi || ji != cji) {
-            // new step: move the ring window (store the rows that leave, load
-            // the rows that enter); a new super-block starts from an empty ring
-            const Blk k = block(si);
-            const int lo = k.S0 + 1 + q.j * b;
-            const int hi = min(n - 1, (k.Bhi + 1) * g + q.j * b + b - 1);
-            __syncthreads();
-            if (si != csi) {
-                if (phi >= plo) store_rows(plo, phi);
-                plo = 0;
-                phi = -1;
-            } else {
-                if (lo - 1 >= plo) store_rows(plo, min(phi, lo - 1));
-                if (phi >= hi + 1) store_rows(max(plo, hi + 1), phi);
-            }
-            __syncthreads();
-            if (phi < plo) {
-                load_rows(lo, hi);
-            } else {
-                if (plo - 1 >= lo) load_rows(lo, min(hi, plo - 1));
-                if (hi >= phi + 1) load_rows(max(lo, phi + 1), hi);
-            }
-            plo = lo;
-            phi = hi;
-            csi = si;
-            cji = ji;
+    // Y rows -> LDS
+    {
+        E yv[RM * NC / 256];
+#pragma unroll
+        for (int u = 0; u < RM * NC / 256; ++u) {
+            const int t = tid + 256 * u, r = t % RM, c = t / RM;
+            const bool in = r < nrows && c < nc;
+            yv[u] = keep(in, Y[in ? R0 + r + (size_t)(c0 + c) * ldy : (size_t)R0 + (size_t)c0 * ldy]);
         }
-        int nsi = si, nji = ji, nBi = Bi;
-        advance(nsi, nji, nBi);
-        const bool more = nsi < nsb;
-        const Grp nq = more ? group(nsi, nji, nBi) : q;
-        __syncthreads();
-        // step 1: W partials = V^H Y_rows (this wave's t tile and k half)
-        {
-            Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < K1; ++u) {
-                int kq = kbeg + u;
-                if (kq < kend) q2_cmfma<E>(a1[u], Yr[slot(q.R0 + t0 + 4 * kq + lk)][lr], p1, p2, p3);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Wp[kh][t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+        for (int u = 0; u < RM * NC / 256; ++u) {
+            const int t = tid + 256 * u;
+            Ys[t % RM][t / RM] = yv[u];
         }
-        if (more) load_a1(nq);
-        __syncthreads();
-        // step 2 (waves 0, 1): W2 = T (Wp[0] + Wp[1]), T upper triangular;
-        // for Q2^H W2 = T^H (Wp[0] + Wp[1]), T^H lower triangular
-        if (wave < 2) {
-            Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+    }
+    __syncthreads();
+    // step 1: W tile (t0, cc) = V(:, t0..t0+15)^H Y_rows(:, cc..cc+15)
+    {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < GM / 4; ++u) {
-                const int l4 = lbeg + 4 * u;
-                if (l4 < lend) {
-                    E w0 = Wp[0][l4 + lk][lr], w1 = Wp[1][l4 + lk][lr];
-                    q2_cmfma<E>(tv[u], El<E>::mk(w0.x + w1.x, w0.y + w1.y), p1, p2, p3);
-                }
-            }
+        for (int q = 0; q < K1; ++q)
+            if (q < nks) q2_cmfma<E>(a1[q], Ys[t0 + 4 * q + lk][cc + lr], p1, p2, p3);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) W2[t0 + Q2M<E>::orow(lk, i)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
-            if (more) load_tv(nq);
+        for (int i = 0; i < 4; ++i) Ws[t0 + Q2M<E>::orow(lk, i)][cc + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+    }
+    // step-3 operands of this wave's first row tile
+    const int c3 = 16 * (wave & 1), q3 = wave >> 1;
+    struct Ops8 {
+        E v[8];
+    };
+    auto load3 = [&](int r0) {
+        Ops8 a;
+        const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t4 = tlo + 4 * u;
+            const E v = vld(t4 < thi && r0 < nrows, r0 + lr, t4 + lk);
+            a.v[u] = El<E>::mk(-v.x, -v.y);
         }
-        __syncthreads();
-        // step 3: Y_rows -= V W2, row tiles wave and wave + 4
+        return a;
+    };
+    Ops8 a3 = load3(16 * q3);
+    __syncthreads();
+    // step 2: W2 tile (t0, cc) = T(t0.., :) W(:, cc..)  (T upper triangular; T^H lower)
+    {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
 #pragma unroll
-        for (int qq = 0; qq < 2; ++qq) {
-            const int r0 = 16 * (wave + 4 * qq);
-            if (r0 >= 96 || r0 >= q.nrows) continue;
+        for (int u = 0; u < 8; ++u)
+            if (lbeg + 4 * u < lend) q2_cmfma<E>(tv[u], Ws[lbeg + 4 * u + lk][cc + lr], p1, p2, p3);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Ws[t0 + Q2M<E>::orow(lk, i)][cc + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+    }
+    __syncthreads();
+    // step 3: row tiles q3, q3 + 2, q3 + 4 of column tile c3
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        const int r0 = 16 * (q3 + 2 * u);
+        const Ops8 a3n = load3(u < 2 ? r0 + 32 : 1 << 20);
+        if (r0 < nrows) {
             Acc p1, p2 = {0, 0, 0, 0}, p3;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                E y = Yr[slot(q.R0 + r0 + Q2M<E>::orow(lk, i))][lr];
+                const E y = Ys[r0 + Q2M<E>::orow(lk, i)][c3 + lr];
                 p1[i] = y.x;
                 p3[i] = y.x + y.y;
             }
             const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                int t4 = tlo + 4 * u;
-                if (t4 < thi) q2_cmfma<E>(a3[qq][u], W2[t4 + lk][lr], p1, p2, p3);
-            }
+            for (int v = 0; v < 8; ++v)
+                if (tlo + 4 * v < thi) q2_cmfma<E>(a3.v[v], Ws[tlo + 4 * v + lk][c3 + lr], p1, p2, p3);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int r = r0 + Q2M<E>::orow(lk, i);
-                if (r < q.nrows) Yr[slot(q.R0 + r)][lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
-            }
+            for (int i = 0; i < 4; ++i)
+                Ys[r0 + Q2M<E>::orow(lk, i)][c3 + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
         }
-        if (more) load_a3(nq);
-        si = nsi;
-        ji = nji;
-        Bi = nBi;
+        a3 = a3n;
     }
     __syncthreads();
-    if (phi >= plo) store_rows(plo, phi);
+    for (int t = tid; t < nrows * NC; t += 256) {
+        const int r = t % nrows, c = t / nrows;
+        if (c < nc) Y[R0 + r + (size_t)(c0 + c) * ldy] = Ys[r][c];
+    }
 }
 
+// reflectors per group (sweeps s0 .. s0 + g - 1 at one step j)
 static int q2_group(int b) { return std::min(b, 32); }
-constexpr int Q2_KS = 4;   // groups per super-block
 
 template <class E>
 void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
@@ -870,32 +666,30 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
         hipLaunchKernelGGL((q2_tbuild_kernel<64, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     HGV_LAUNCH_CHECK();
-    // The super-block kernel keeps Y rows in LDS and loads every group's V and
-    // T operands one phase ahead of their use, which hides most of the load
-    // latency of a workgroup that is alone on its CU; its register and LDS
-    // footprint allows one workgroup per CU.  With more column tiles than CUs
-    // the per-group kernel (three workgroups per CU hide each other's
-    // latencies) wins.
-    int cus = 0;
-    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    const int tiles = cdiv(m, 16);
-    const bool sb = tiles <= cus;
-    if (b <= 32) {
-        if (sb)
-            hipLaunchKernelGGL((q2_sb_kernel<32, Q2_KS, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J,
-                               ngrp, (int)adj, V2, T2, Y, ldy);
+    // anti-diagonal w holds the groups B = ngrp - 1 - w + j with j in
+    // [max(0, w - ngrp + 1), min(w, J - 1)] and j < jn(B); the valid j form a prefix
+    const int nw = ngrp + J - 1, ct = cdiv(m, Q2WF_NC);
+    for (int wi = 0; wi < nw; ++wi) {
+        const int w = adj ? nw - 1 - wi : wi;
+        const int Bt = ngrp - 1 - w;
+        const int jlo = std::max(0, -Bt);
+        int jhi = std::min(w, J - 1);
+        while (jhi >= jlo) {
+            const int s0 = (Bt + jhi) * g;
+            if (s0 <= n - 2 && jhi <= (n - 2 - s0) / b) break;
+            --jhi;
+        }
+        if (jhi < jlo) continue;
+        const int ngs = jhi - jlo + 1;
+        const int grid = 8 * cdiv(ngs * ct, 8);
+        if (b <= 32)
+            hipLaunchKernelGGL((q2_wf_kernel<32, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                               jlo, ngs, (int)adj, V2, T2, Y, ldy);
         else
-            hipLaunchKernelGGL((q2_mfma_kernel<32, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
-                               (int)adj, V2, T2, Y, ldy);
-    } else {
-        if (sb)
-            hipLaunchKernelGGL((q2_sb_kernel<64, Q2_KS, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J,
-                               ngrp, (int)adj, V2, T2, Y, ldy);
-        else
-            hipLaunchKernelGGL((q2_mfma_kernel<64, E>), dim3(tiles), dim3(256), 0, ctx->stream, n, m, b, g, J, ngrp,
-                               (int)adj, V2, T2, Y, ldy);
+            hipLaunchKernelGGL((q2_wf_kernel<64, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                               jlo, ngs, (int)adj, V2, T2, Y, ldy);
+        HGV_LAUNCH_CHECK();
     }
-    HGV_LAUNCH_CHECK();
 }
 
 template void unmtr_q2_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, const double2 *, double2 *, int, bool,

@@ -79,6 +79,11 @@ struct Arena {
 
 // ---- device complex helpers ---------------------------------------------------
 __host__ __device__ inline double2 zmk(double r, double i) { return make_double2(r, i); }
+// c ? a : b per component (a ternary on the vector type itself may be compiled
+// as a select between two addresses and a load through scratch memory)
+__host__ __device__ inline double2 zsel(bool c, double2 a, double2 b) {
+    return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 __host__ __device__ inline double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __host__ __device__ inline double2 zmul(double2 a, double2 b) {
