@@ -96,43 +96,62 @@ __device__ inline int remap_xcd(int bid, int total) {
     return bid;
 }
 
+// Fix-ups of a loaded element, applied when it is stored to LDS: bit 0 in
+// range (else zero), bit 1 conjugate, bit 2 real part only (the diagonal of a
+// Hermitian operand).  Keeping them as flag bits leaves the loads themselves
+// unconditional (clamped to an in-range address), so that a thread's loads of a
+// tile are all in flight together and none waits for the previous one.
+template <class T>
+__device__ inline typename T::E fix_elem(typename T::E v, unsigned f);
+template <>
+__device__ inline double2 fix_elem<TZ>(double2 v, unsigned f) {
+    const bool in = f & 1u, cj = f & 2u, re = f & 4u;
+    return make_double2(in ? v.x : 0.0, (in && !re) ? (cj ? -v.y : v.y) : 0.0);
+}
+template <>
+__device__ inline float2 fix_elem<TC>(float2 v, unsigned f) {
+    const bool in = f & 1u, cj = f & 2u, re = f & 4u;
+    return make_float2(in ? v.x : 0.0f, (in && !re) ? (cj ? -v.y : v.y) : 0.0f);
+}
+template <>
+__device__ inline double fix_elem<TD>(double v, unsigned f) { return (f & 1u) ? v : 0.0; }
+
 // Load the BM x BK tile of op(A) (rows m0.., cols k0..) into registers; idx
-// receives the LDS slot of every element.  op: 0 N, 1 T, 2 C, 3 H.
+// receives the LDS slot of every element, fl its fix-up bits (3 per element).
+// op: 0 N, 1 T, 2 C, 3 H (Hermitian, lower triangle stored).
 template <class T, int BM>
 __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int op, int M, int K,
                               int m0, int k0, int tid, typename T::E (&r)[BM * BK / 256],
-                              int (&idx)[BM * BK / 256]) {
-    typedef typename T::E E;
+                              int (&idx)[BM * BK / 256], unsigned &fl) {
     constexpr int NE = BM * BK / 256;
-    bool mirrored = (op == 1 || op == 2) || (op == 3 && m0 + BM - 1 < k0);
+    const bool mirrored = (op == 1 || op == 2) || (op == 3 && m0 + BM - 1 < k0);
+    fl = 0;
     if (!mirrored) {
+        const bool herm = op == 3;
+        const size_t safe = m0 + (size_t)k0 * lda;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            int e = tid + t * 256;
-            int mm = e % BM, kk = e / BM;
-            int gm = m0 + mm, gk = k0 + kk;
-            E v = T::zero();
-            if (gm < M && gk < K) {
-                if (op == 0 || gm > gk) v = A[gm + (size_t)gk * lda];
-                else if (gm == gk) v = T::realpart(A[gm + (size_t)gm * lda]);
-                else v = T::conj(A[gk + (size_t)gm * lda]);
-            }
-            r[t] = v;
+            const int e = tid + t * 256;
+            const int mm = e % BM, kk = e / BM;
+            const int gm = m0 + mm, gk = k0 + kk;
+            const bool in = gm < M && gk < K;
+            const bool up = herm && gm < gk;   // above the diagonal: the mirrored element, conjugated
+            const size_t off = up ? gk + (size_t)gm * lda : gm + (size_t)gk * lda;
+            r[t] = A[in ? off : safe];
+            fl |= ((in ? 1u : 0u) | (up ? 2u : 0u) | ((herm && gm == gk) ? 4u : 0u)) << (3 * t);
             idx[t] = kk * (BM + PAD) + mm;
         }
     } else {
-        bool cj = (op == 2 || op == 3);
+        const unsigned cj = (op == 2 || op == 3) ? 2u : 0u;
+        const size_t safe = k0 + (size_t)m0 * lda;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            int e = tid + t * 256;
-            int kk = e % BK, mm = e / BK;
-            int gm = m0 + mm, gk = k0 + kk;
-            E v = T::zero();
-            if (gm < M && gk < K) {
-                v = A[gk + (size_t)gm * lda];
-                if (cj) v = T::conj(v);
-            }
-            r[t] = v;
+            const int e = tid + t * 256;
+            const int kk = e % BK, mm = e / BK;
+            const int gm = m0 + mm, gk = k0 + kk;
+            const bool in = gm < M && gk < K;
+            r[t] = A[in ? gk + (size_t)gm * lda : safe];
+            fl |= ((in ? 1u : 0u) | cj) << (3 * t);
             idx[t] = kk * (BM + PAD) + mm;
         }
     }
@@ -142,33 +161,32 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
 template <class T, int BN>
 __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int op, int K, int N,
                               int k0, int n0, int tid, typename T::E (&r)[BN * BK / 256],
-                              int (&idx)[BN * BK / 256]) {
-    typedef typename T::E E;
+                              int (&idx)[BN * BK / 256], unsigned &fl) {
     constexpr int NE = BN * BK / 256;
+    fl = 0;
     if (op == 0) {
+        const size_t safe = k0 + (size_t)n0 * ldb;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            int e = tid + t * 256;
-            int kk = e % BK, nn = e / BK;
-            int gk = k0 + kk, gn = n0 + nn;
-            E v = T::zero();
-            if (gk < K && gn < N) v = B[gk + (size_t)gn * ldb];
-            r[t] = v;
+            const int e = tid + t * 256;
+            const int kk = e % BK, nn = e / BK;
+            const int gk = k0 + kk, gn = n0 + nn;
+            const bool in = gk < K && gn < N;
+            r[t] = B[in ? gk + (size_t)gn * ldb : safe];
+            fl |= (in ? 1u : 0u) << (3 * t);
             idx[t] = kk * (BN + PAD) + nn;
         }
     } else {
-        bool cj = (op == 2);
+        const unsigned cj = (op == 2) ? 2u : 0u;
+        const size_t safe = n0 + (size_t)k0 * ldb;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            int e = tid + t * 256;
-            int nn = e % BN, kk = e / BN;
-            int gk = k0 + kk, gn = n0 + nn;
-            E v = T::zero();
-            if (gk < K && gn < N) {
-                v = B[gn + (size_t)gk * ldb];
-                if (cj) v = T::conj(v);
-            }
-            r[t] = v;
+            const int e = tid + t * 256;
+            const int nn = e % BN, kk = e / BN;
+            const int gk = k0 + kk, gn = n0 + nn;
+            const bool in = gk < K && gn < N;
+            r[t] = B[in ? gn + (size_t)gk * ldb : safe];
+            fl |= ((in ? 1u : 0u) | cj) << (3 * t);
             idx[t] = kk * (BN + PAD) + nn;
         }
     }
@@ -295,15 +313,16 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
 
     E ra[NA], rb[NB];
     int ia[NA], ib[NB];
+    unsigned fa = 0, fb = 0;
     auto fetch = [&](int c) {
         int seg = c / cps;
         int k0 = (c % cps) * BK;
         if (seg == 0) {
-            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, ia);
-            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ib);
+            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, ia, fa);
+            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ib, fb);
         } else {
-            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, ia);
-            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ib);
+            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, ia, fa);
+            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ib, fb);
         }
     };
 
@@ -311,9 +330,9 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
     for (int c = c_beg; c < c_end; ++c) {
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < NA; ++t) As[ia[t]] = ra[t];
+        for (int t = 0; t < NA; ++t) As[ia[t]] = fix_elem<T>(ra[t], (fa >> (3 * t)) & 7u);
 #pragma unroll
-        for (int t = 0; t < NB; ++t) Bs[ib[t]] = rb[t];
+        for (int t = 0; t < NB; ++t) Bs[ib[t]] = fix_elem<T>(rb[t], (fb >> (3 * t)) & 7u);
         __syncthreads();
         if (c + 1 < c_end) fetch(c + 1);
 #pragma unroll
@@ -333,9 +352,24 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
         }
     }
 
-    // epilogue: each lane holds four rows (T::out_row) of column lane%16 of each block
+    // epilogue: each lane holds four rows (T::out_row) of column lane%16 of each
+    // block; for beta != 0 the C elements of one block row are loaded together
+    // (clamped addresses) before any of them is used
+    const bool need_c = g.splits == 1 && !g.beta_zero;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int i = 0; i < FM; ++i) {
+        E cv[FN][4];
+        if (need_c) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * WM + i * 16 + T::out_row(lane, r);
+                    const int col = n0 + wn * WN + j * 16 + (lane & 15);
+                    const bool in = row < g.m && col < g.n;
+                    cv[j][r] = g.C[in ? row + (size_t)col * g.ldc : m0 + (size_t)n0 * g.ldc];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -352,10 +386,11 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
                     g.P[(size_t)z * g.m * g.n + row + (size_t)col * g.m] = v;
                 } else {
                     E o = e_mul(g.alpha, v);
-                    if (!g.beta_zero) o = e_add(o, e_mul(g.beta, g.C[row + (size_t)col * g.ldc]));
+                    if (need_c) o = e_add(o, e_mul(g.beta, cv[j][r]));
                     g.C[row + (size_t)col * g.ldc] = o;
                 }
             }
+    }
 }
 
 // C = alpha * sum_z P[z] + beta * C  (fixed summation order)

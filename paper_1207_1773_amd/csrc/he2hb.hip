@@ -82,10 +82,26 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
     const double2 *row_in = a.rowb + ib * PNB;
     double2 *row_out = a.rowb + ob * PNB;
 
-    // load the chunk's columns c0..jb-1
-    for (int t = tid; t < PCH * ncol; t += 256) {
-        int r = t % PCH, c = c0 + t / PCH;
-        if (r < rows) Ps[r][c] = a.P[row0 + r + (size_t)c * a.ldp];
+    // load the chunk's columns c0..jb-1 through registers: every load is issued
+    // (elements outside the chunk read its in-range element (row0, c0)) before
+    // the first one is waited for
+    {
+        constexpr int NLD = PCH * PNB / 256;
+        E pv[NLD];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int t = tid + 256 * u, r = t % PCH, c = c0 + t / PCH;
+            const bool in = r < rows && c < a.jb;
+            pv[u] = a.P[in ? row0 + r + (size_t)c * a.ldp : row0 + (size_t)c0 * a.ldp];
+        }
+        // unconditional stores (a conditional one would let the compiler sink its
+        // load into the branch): rows past the chunk are never read, columns past
+        // the panel go to the padding column PNB
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int t = tid + 256 * u, r = t % PCH, c = c0 + t / PCH;
+            Ps[r][c < a.jb ? c : PNB] = pv[u];
+        }
     }
     auto ld = [&](int r, int c) -> double2 { return El<E>::to(Ps[r][c]); };
     if (j >= 0) {
@@ -96,9 +112,18 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
         const int c = tid & 63, qq = tid >> 6;
         double2 acc = make_double2(0.0, 0.0);
         if (c < ncol) {
+            // partials q = qq, qq + 4, ... in ascending order, eight loads in flight
             const double2 *src = part_in + j + c;
-#pragma unroll 8
-            for (int q = qq; q < a.G; q += 4) acc = zadd(acc, src[(size_t)q * PNB]);
+            for (int q0 = qq; q0 < a.G; q0 += 32) {
+                double2 pq[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = q0 + 4 * u;
+                    pq[u] = zsel(q < a.G, src[(size_t)(q < a.G ? q : qq) * PNB], make_double2(0.0, 0.0));
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc = zadd(acc, pq[u]);
+            }
         }
         red[qq][c] = acc;
         if (tid < ncol) r0v[tid] = row_in[j + tid];
