@@ -651,14 +651,18 @@ __global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int 
 // reflectors per group (sweeps s0 .. s0 + g - 1 at one step j)
 static int q2_group(int b) { return std::min(b, 32); }
 
+size_t q2_t_elems(int n, int nb) {
+    const int g = q2_group(nb);
+    const int ngrp = n >= 2 ? cdiv(n - 1, g) : 0;
+    return std::max<size_t>((size_t)ngrp * hb_J(n, nb) * g * g, 1);
+}
+
 template <class E>
-void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
-                Arena &ar) {
+void q2_build_t(hgv_ctx_s *ctx, int n, int nb, const E *V2, const E *tau2, E *T2) {
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    if (n < 2) return;
     const int b = nb, g = q2_group(b);
-    const int J = hb_J(n, b), ngrp = n >= 2 ? cdiv(n - 1, g) : 0;
-    E *T2 = ar.take<E>(std::max<size_t>((size_t)ngrp * J * g * g, 1));
-    if (ar.measuring() || n < 2 || m == 0) return;
+    const int J = hb_J(n, b), ngrp = cdiv(n - 1, g);
     if (b <= 32)
         hipLaunchKernelGGL((q2_tbuild_kernel<32, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
@@ -666,6 +670,14 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
         hipLaunchKernelGGL((q2_tbuild_kernel<64, 32, E>), dim3(ngrp * J), dim3(256), 0, ctx->stream, n, b, g, J, V2,
                            tau2, T2);
     HGV_LAUNCH_CHECK();
+}
+
+template <class E>
+void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, E *Y, int ldy, bool adj) {
+    if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    if (n < 2 || m == 0) return;
+    const int b = nb, g = q2_group(b);
+    const int J = hb_J(n, b), ngrp = cdiv(n - 1, g);
     // anti-diagonal w holds the groups B = ngrp - 1 - w + j with j in
     // [max(0, w - ngrp + 1), min(w, J - 1)] and j < jn(B); the valid j form a prefix
     const int nw = ngrp + J - 1, ct = cdiv(m, Q2WF_NC);
@@ -692,9 +704,21 @@ void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2
     }
 }
 
+template <class E>
+void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
+                Arena &ar) {
+    if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    E *T2 = ar.take<E>(q2_t_elems(n, nb));
+    if (ar.measuring() || n < 2 || m == 0) return;
+    q2_build_t<E>(ctx, n, nb, V2, tau2, T2);
+    q2_apply_t<E>(ctx, n, nb, m, V2, T2, Y, ldy, adj);
+}
+
 template void unmtr_q2_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, const double2 *, double2 *, int, bool,
                                   Arena &);
 template void unmtr_q2_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, const float2 *, float2 *, int, bool,
                                  Arena &);
+template void q2_build_t<float2>(hgv_ctx_s *, int, int, const float2 *, const float2 *, float2 *);
+template void q2_apply_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, const float2 *, float2 *, int, bool);
 
 }  // namespace hgv

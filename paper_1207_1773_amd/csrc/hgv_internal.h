@@ -209,6 +209,14 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
 template <class E>
 void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
                 Arena &ar);
+// the two halves of unmtr_q2_t, for callers that apply the same Q2 repeatedly:
+// the T factors of every reflector group (q2_t_elems(n, nb) elements), then
+// their application
+size_t q2_t_elems(int n, int nb);
+template <class E>
+void q2_build_t(hgv_ctx_s *ctx, int n, int nb, const E *V2, const E *tau2, E *T2);
+template <class E>
+void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, E *Y, int ldy, bool adj);
 inline void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar) {
     he2hb_t<double2>(ctx, n, nb, A, lda, T1, ar);
 }

@@ -1,14 +1,12 @@
 // refine.hip -- mixed-precision standard eigensolve: the band reduction, the
 // bulge chasing and both back-transforms run on complex64 data (FP32 MFMA,
 // reflector norms and scalars in FP64), the tridiagonal solve in FP64, and the
-// eigenpairs are then refined in FP64:
+// eigenpairs are then refined in FP64.  The working subspace is the wanted
+// pairs il..iu widened by up to kGuard pairs on each side.
 //
-//   1. Rayleigh-Ritz on the working subspace (the wanted pairs il..iu widened
-//      by up to kGuard pairs on each side): Cholesky QR of Y, H = Y^H A' Y,
-//      H = U Theta U^H by the FP64 standard solver, Y <- Y U.
-//   2. R = A' Y - Y Theta in FP64 (the one unavoidable FP64 pass over A');
-//      rho = max_i ||r_i||_2 / ||A'||_2.  Stop when rho <= tol.
-//   3. Newton-type correction through the complex64 factorisation
+//   1. Subspace residual: Cholesky QR of Y, H = Y^H A' Y, theta_i = H_ii,
+//      R = A' Y - Y H (FP64; the part of A' Y outside span(Y)).
+//   2. Newton-type correction through the complex64 factorisation
 //      A' ~ Q T Q^H (Q = Q1 Q2, T tridiagonal):  for every column
 //        y_i <- y_i - Q P (T - theta_i I)^-1 P Q^H r_i,
 //      P = I - Z Z^T the projector onto the complement of the working
@@ -16,9 +14,16 @@
 //      The complex64 back-transform kernels apply Q^H and Q; the shifted
 //      tridiagonal systems are solved in FP64 by Gaussian elimination with
 //      partial pivoting, one column per thread.
-// Each correction multiplies the error outside the working subspace by about
-// ||A' - Q T Q^H|| / (distance of theta_i to the eigenvalues outside it), so
-// the guard pairs keep the wanted pairs away from the slow boundary.
+//   3. Rayleigh-Ritz: Cholesky QR of Y, H = Y^H A' Y, H = U Theta U^H by the
+//      FP64 standard solver, Y <- Y U, R = A' Y - Y Theta,
+//      rho = max_i ||r_i||_2 / ||A'||_2.  Done when rho <= tol.
+// Steps 1-2 run twice (a correction only changes Y outside its span, so the
+// rotation inside the subspace is left to the one Rayleigh-Ritz step that
+// follows); each further round is a correction from the Rayleigh-Ritz
+// residual and another Rayleigh-Ritz step.  Each correction multiplies the
+// error outside the working subspace by about ||A' - Q T Q^H|| / (distance of
+// theta_i to the eigenvalues outside it), so the guard pairs keep the wanted
+// pairs away from the slow boundary.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -180,6 +185,12 @@ __global__ __launch_bounds__(64) void tri_solve_kernel(int n, int m, const doubl
     }
 }
 
+// theta_i = Re H_ii
+__global__ void diag_re_kernel(int m, const double2 *H, int ldh, double *theta) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < m) theta[i] = H[i + (size_t)i * ldh].x;
+}
+
 __global__ void copy_vals_kernel(int m, const double *a, double *b) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i < m) b[i] = a[i];
@@ -224,6 +235,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
     double *Ut = ar.take<double>(3 * (size_t)n * mw);
     const size_t wsb = zgemm_splitk_bytes(n);
     double2 *ws = ar.take<double2>(wsb / sizeof(double2));
+    float2 *T2c = ar.take<float2>(q2_t_elems(n, nb));   // Q2's T factors, built once
     const size_t mk1 = ar.mark();
 
     auto gemm = [&](char opa, char opb, int gm, int gn, int gk, const double2 *a, int la, const double2 *b, int lb,
@@ -265,8 +277,10 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
     if (tm) tm->end(HGV_ST_STEDC, 4.0 / 3.0 * N * N * N);
 
     if (tm) tm->begin(HGV_ST_Q2);
-    unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, false, ar);
-    ar.release(mk1);
+    if (run) {
+        q2_build_t<float2>(ctx, n, nb, V2c, tau2c, T2c);
+        q2_apply_t<float2>(ctx, n, nb, mw, V2c, T2c, Yc, n, false);
+    }
     if (tm) tm->end(HGV_ST_Q2, 8.0 * N * N * MW);
 
     if (tm) tm->begin(HGV_ST_Q1);
@@ -304,6 +318,21 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
             HGV_LAUNCH_CHECK();
         }
     };
+    auto subspace_residual = [&]() {
+        gemm('C', 'N', mw, mw, n, Y, n, Y, n, S, mw, one, zero, 1);
+        potrf_run(ctx, mw, S, mw, ar, info2, 0);
+        ar.release(mk1);
+        trsm_right_lc(ctx, n, mw, S, mw, Y, n, ar);
+        ar.release(mk1);
+        gemm('H', 'N', n, mw, n, A, lda, Y, n, AY, n, one, zero, 0);
+        gemm('C', 'N', mw, mw, n, Y, n, AY, n, S, mw, one, zero, 0);
+        if (run) {
+            hipLaunchKernelGGL(diag_re_kernel, dim3(cdiv(mw, 256)), dim3(256), 0, ctx->stream, mw, S, mw, theta);
+            HGV_LAUNCH_CHECK();
+            copy_matrix(ctx, n, mw, AY, n, R, n);
+        }
+        gemm('N', 'N', n, mw, mw, Y, n, S, mw, R, n, mone, one, 0);
+    };
     auto correct = [&]() {
         // P = Q^H R in complex64 (Q1^H first, then Q2^H)
         if (run) {
@@ -312,8 +341,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
         }
         unmtr_q1_t<float2>(ctx, n, nb, mw, Ac, n, T1c, Yc, n, true, ar);
         ar.release(mk1);
-        unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, true, ar);
-        ar.release(mk1);
+        if (run) q2_apply_t<float2>(ctx, n, nb, mw, V2c, T2c, Yc, n, true);
         if (run) {
             hipLaunchKernelGGL(to_c128_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, Yc, n, R, n);
             HGV_LAUNCH_CHECK();
@@ -333,8 +361,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
             hipLaunchKernelGGL(to_c64_kernel, grid2(n, mw), dim3(256), 0, ctx->stream, n, mw, R, n, Yc, n);
             HGV_LAUNCH_CHECK();
         }
-        unmtr_q2_t<float2>(ctx, n, nb, mw, V2c, tau2c, Yc, n, false, ar);
-        ar.release(mk1);
+        if (run) q2_apply_t<float2>(ctx, n, nb, mw, V2c, T2c, Yc, n, false);
         unmtr_q1_t<float2>(ctx, n, nb, mw, Ac, n, T1c, Yc, n, false, ar);
         ar.release(mk1);
         if (run) {
@@ -345,11 +372,19 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
 
     if (tm) tm->begin(HGV_ST_REFINE);
     bool converged = false;
-    int iters = 0;
+    int iters = 0, rr = 0;
     double rho = 0.0;
-    for (int it = 0;; ++it) {
+    // a working subspace that is the whole space is exact after Rayleigh-Ritz
+    const int k0 = (mw == n) ? 0 : std::min(2, std::max(max_iters, 0));
+    for (int c = 0; c < k0; ++c) {
+        subspace_residual();
+        correct();
+        ++iters;
+    }
+    for (;;) {
         rayleigh_ritz();
-        const bool last = it >= max_iters;
+        ++rr;
+        const bool last = iters >= max_iters;
         if (run) {
             int code = (fixed_iters && last) ? 2 * n + 1 : 0;
             hipLaunchKernelGGL(rho_kernel, dim3(1), dim3(256), 0, ctx->stream, mw, colres, lam, n, rho_d, tol,
@@ -378,7 +413,8 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
         HGV_LAUNCH_CHECK();
         copy_matrix(ctx, n, m, Y + (size_t)off * n, n, X, ldx);
     }
-    if (tm) tm->end(HGV_ST_REFINE, iters * (8.0 * N * N * MW + 32.0 * N * N * MW) + (iters + 1) * 8.0 * N * N * MW);
+    // the products with A' (one per residual) and the four complex64 back-transforms per correction
+    if (tm) tm->end(HGV_ST_REFINE, (std::min(iters, k0) + rr) * 8.0 * N * N * MW + iters * 32.0 * N * N * MW);
     if (res) {
         res->iters = iters;
         res->rho = rho;

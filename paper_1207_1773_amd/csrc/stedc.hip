@@ -265,16 +265,50 @@ __global__ void dc_m2_kernel(DcArgs A) {
 // a bracket [lo, hi] with f(lo) < 0 < f(hi) is kept, and the step falls back
 // to bisection when the model root leaves it or every fourth iteration.  The
 // iteration stops when |f| is below its rounding-error bound.
+// A group of M3G consecutive lanes works on one root: lane `sub` of the group
+// sums the terms i = sub, sub + M3G, ... (four loads in flight), and an xor
+// butterfly over the group adds the partial sums.  Floating-point addition is
+// commutative, so every lane of the group ends with the same sums bit for bit
+// and takes the same branches of the iteration.
+constexpr int M3G = 16;
+
+__device__ inline double group_add(double x) {
+#pragma unroll
+    for (int o = 1; o < M3G; o <<= 1) x += __shfl_xor(x, o, M3G);
+    return x;
+}
+
 __device__ inline void secular_eval(const double *dK, const double *zK, int kp, double dorg, double rho, double t,
-                                    int split, double &f, double &dl, double &dr, double &err) {
+                                    int split, int sub, double &f, double &dl, double &dr, double &err) {
     double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0;
-    for (int i = 0; i < kp; ++i) {
-        double del = (dK[i] - dorg) - t;
-        double q = zK[i] / del;
-        double term = zK[i] * q, dterm = q * q;
-        if (i <= split) { psi += term; dpsi += dterm; }
-        else { phi += term; dphi += dterm; }
+    for (int i0 = sub; i0 < kp; i0 += 4 * M3G) {
+        double dv[4], zv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * M3G;
+            dv[u] = dK[i < kp ? i : 0];
+            zv[u] = zK[i < kp ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * M3G;
+            const double z = (i < kp) ? zv[u] : 0.0;
+            const double del = (dv[u] - dorg) - t;
+            const double q = z / del;
+            const double term = z * q, dterm = q * q;
+            if (i <= split) {
+                psi += term;
+                dpsi += dterm;
+            } else {
+                phi += term;
+                dphi += dterm;
+            }
+        }
     }
+    psi = group_add(psi);
+    phi = group_add(phi);
+    dpsi = group_add(dpsi);
+    dphi = group_add(dphi);
     f = 1.0 + rho * (psi + phi);
     dl = rho * dpsi;
     dr = rho * dphi;
@@ -282,12 +316,14 @@ __device__ inline void secular_eval(const double *dK, const double *zK, int kp, 
 }
 
 __global__ void dc_m3_kernel(DcArgs A) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= A.n) return;
-    int p = g / (2 * A.L);
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int root = g / M3G, sub = g % M3G;
+    // every exit below is taken by whole lane groups (it depends on root only)
+    if (root >= A.n) return;
+    int p = root / (2 * A.L);
     MergeGeom m = merge_geom(A.n, A.L, p);
     if (m.n2 <= 0) return;
-    int j = g - m.a;
+    int j = root - m.a;
     int kp = A.kcnt[p];
     if (j >= kp) return;
     const double *dK = A.dK + m.a, *zK = A.zK + m.a;
@@ -296,14 +332,15 @@ __global__ void dc_m3_kernel(DcArgs A) {
     double lo, hi;
     if (j < kp - 1) {
         double mid = 0.5 * (dK[j + 1] - dK[j]);
-        double f = 1.0;
-        for (int i = 0; i < kp; ++i) f += rho * zK[i] * zK[i] / ((dK[i] - dK[j]) - mid);
+        double fs = 0.0;
+        for (int i = sub; i < kp; i += M3G) fs += zK[i] * zK[i] / ((dK[i] - dK[j]) - mid);
+        double f = 1.0 + rho * group_add(fs);
         if (f >= 0.0) { org = j; lo = 0.0; hi = mid; }
         else { org = j + 1; lo = -mid; hi = 0.0; }
     } else {
         double s2 = 0.0;
-        for (int i = 0; i < kp; ++i) s2 += zK[i] * zK[i];
-        org = j; lo = 0.0; hi = rho * s2;
+        for (int i = sub; i < kp; i += M3G) s2 += zK[i] * zK[i];
+        org = j; lo = 0.0; hi = rho * group_add(s2);
     }
     const double dorg = dK[org];
     const bool last = (j == kp - 1);
@@ -312,7 +349,7 @@ __global__ void dc_m3_kernel(DcArgs A) {
     double t = 0.5 * (lo + hi);
     for (int it = 0; it < 200; ++it) {
         double f, sl, sr, err;
-        secular_eval(dK, zK, kp, dorg, rho, t, j, f, sl, sr, err);
+        secular_eval(dK, zK, kp, dorg, rho, t, j, sub, f, sl, sr, err);
         if (fabs(f) <= err) break;
         if (f < 0.0) lo = t;
         else hi = t;
@@ -351,8 +388,10 @@ __global__ void dc_m3_kernel(DcArgs A) {
         if (tn == t) break;
         t = tn;
     }
-    A.org[m.a + j] = org;
-    A.tau[m.a + j] = t;
+    if (sub == 0) {
+        A.org[m.a + j] = org;
+        A.tau[m.a + j] = t;
+    }
 }
 
 // M4: Gu-Eisenstat recomputation of u from the computed roots.
@@ -565,7 +604,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m2_kernel, dim3(P), dim3(64), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dc_m3_kernel, gN, dim3(256), 0, ctx->stream, A);
+        hipLaunchKernelGGL(dc_m3_kernel, dim3(cdiv(n * M3G, 256)), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m4_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
