@@ -152,15 +152,21 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
             vrow[tid] = v;
         }
         __syncthreads();
-        // apply H^H to columns j+1.., store v below the diagonal and beta on it
-        for (int t = tid; t < PCH * ncol; t += 256) {
-            int r = t % PCH, cc = t / PCH, c = j + cc;
-            int gr = row0 + r;
-            if (r >= rows || gr < j) continue;
-            if (cc == 0) {
-                Ps[r][c] = El<E>::from((gr == j) ? make_double2(beta, 0.0) : vrow[r]);
-            } else {
-                Ps[r][c] = El<E>::from(zsub(ld(r, c), zmul(vrow[r], w[cc])));
+        // apply H^H to columns j+1.., store v below the diagonal and beta on it;
+        // thread -> row tid % PCH and columns cc = tid / PCH, tid / PCH + 2, ...
+        // (a fixed-count loop, so that its LDS accesses overlap)
+        {
+            const int r = tid & (PCH - 1), gr = row0 + r;
+            const bool rok = r < rows && gr >= j;
+            const double2 vr = vrow[r];
+#pragma unroll
+            for (int u = 0; u < PNB / 2; ++u) {
+                const int cc = 2 * u + (tid >> 7);
+                if (cc < ncol && rok) {
+                    const int c = j + cc;
+                    Ps[r][c] = El<E>::from(cc == 0 ? zsel(gr == j, make_double2(beta, 0.0), vr)
+                                                   : zsub(ld(r, c), zmul(vr, w[cc])));
+                }
             }
         }
         if (g == 0 && tid == 0) a.tau[j] = tau;
@@ -174,14 +180,15 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
         const int c = tid & (PNB - 1), grp = tid >> 6;
         double2 acc = make_double2(0.0, 0.0);
         if (c >= jn && c < a.jb) {
-            for (int r = grp * 32; r < grp * 32 + 32 && r < rows; ++r) {
-                int gr = row0 + r;
-                if (gr < jn) continue;
-                if (c == jn) {
-                    if (gr > jn) acc.x += zabs2(ld(r, jn));
-                } else {
-                    acc = zadd(acc, zcmul(ld(r, jn), ld(r, c)));
-                }
+            // fixed count and no branches, so that the LDS reads overlap; rows
+            // outside the chunk or above the diagonal contribute zero (for
+            // c == jn the diagonal row too: conj(x) x is |x|^2 with a zero
+            // imaginary part)
+#pragma unroll 8
+            for (int rr = 0; rr < PCH / 4; ++rr) {
+                const int r = grp * (PCH / 4) + rr, gr = row0 + r;
+                const bool ok = r < rows && (c == jn ? gr > jn : gr >= jn);
+                acc = zadd(acc, zsel(ok, zcmul(ld(r, jn), ld(r, c)), make_double2(0.0, 0.0)));
             }
         }
         red[grp][c] = acc;
