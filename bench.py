@@ -43,7 +43,7 @@ def main():
     ap.add_argument("--mixed-fractions", type=str, default="0.1,0.25,1.0",
                     help="fractions also solved in mixed precision (side by side with FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=2048)
+    ap.add_argument("--cpu-n", type=int, default=2560)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this size 5 times and exit (HBM counter calibration)")
     args = ap.parse_args()

@@ -87,7 +87,12 @@ struct GemmDev {
     int tiles_m, tiles_n;
 };
 
-constexpr int BK = 16;
+// k depth of a staged tile (a depth of 32 for the real 128 x 128 tile runs out
+// of architectural registers and is slower)
+template <class T>
+struct KDepth {
+    static constexpr int v = 16;
+};
 constexpr int PAD = 1;
 
 __device__ inline int remap_xcd(int bid, int total) {
@@ -116,19 +121,24 @@ __device__ inline float2 fix_elem<TC>(float2 v, unsigned f) {
 template <>
 __device__ inline double fix_elem<TD>(double v, unsigned f) { return (f & 1u) ? v : 0.0; }
 
-// Load the BM x BK tile of op(A) (rows m0.., cols k0..) into registers; idx
-// receives the LDS slot of every element, fl its fix-up bits (3 per element).
-// op: 0 N, 1 T, 2 C, 3 H (Hermitian, lower triangle stored).
+// Load the BM x BK tile of op(A) (rows m0.., cols k0..) into registers.  The
+// LDS slot of element t is ibase + t * istep (the element-to-slot map is
+// affine in t for both access orders); fl receives the fix-up bits (3 per
+// element, at most 21 elements).  op: 0 N, 1 T, 2 C, 3 H (Hermitian, lower
+// triangle stored).
 template <class T, int BM>
 __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int op, int M, int K,
-                              int m0, int k0, int tid, typename T::E (&r)[BM * BK / 256],
-                              int (&idx)[BM * BK / 256], unsigned &fl) {
+                              int m0, int k0, int tid, typename T::E (&r)[BM * KDepth<T>::v / 256],
+                              int &ibase, int &istep, unsigned long long &fl) {
+    constexpr int BK = KDepth<T>::v;
     constexpr int NE = BM * BK / 256;
     const bool mirrored = (op == 1 || op == 2) || (op == 3 && m0 + BM - 1 < k0);
     fl = 0;
     if (!mirrored) {
         const bool herm = op == 3;
         const size_t safe = m0 + (size_t)k0 * lda;
+        ibase = (tid / BM) * (BM + PAD) + tid % BM;
+        istep = (256 / BM) * (BM + PAD);
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
             const int e = tid + t * 256;
@@ -138,12 +148,13 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
             const bool up = herm && gm < gk;   // above the diagonal: the mirrored element, conjugated
             const size_t off = up ? gk + (size_t)gm * lda : gm + (size_t)gk * lda;
             r[t] = A[in ? off : safe];
-            fl |= ((in ? 1u : 0u) | (up ? 2u : 0u) | ((herm && gm == gk) ? 4u : 0u)) << (3 * t);
-            idx[t] = kk * (BM + PAD) + mm;
+            fl |= (unsigned long long)((in ? 1u : 0u) | (up ? 2u : 0u) | ((herm && gm == gk) ? 4u : 0u)) << (3 * t);
         }
     } else {
         const unsigned cj = (op == 2 || op == 3) ? 2u : 0u;
         const size_t safe = k0 + (size_t)m0 * lda;
+        ibase = (tid % BK) * (BM + PAD) + tid / BK;
+        istep = 256 / BK;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
             const int e = tid + t * 256;
@@ -151,8 +162,7 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
             const int gm = m0 + mm, gk = k0 + kk;
             const bool in = gm < M && gk < K;
             r[t] = A[in ? gk + (size_t)gm * lda : safe];
-            fl |= ((in ? 1u : 0u) | cj) << (3 * t);
-            idx[t] = kk * (BM + PAD) + mm;
+            fl |= (unsigned long long)((in ? 1u : 0u) | cj) << (3 * t);
         }
     }
 }
@@ -160,12 +170,15 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
 // Load the BK x BN tile of op(B) (rows k0.., cols n0..).  op: 0 N, 1 T, 2 C.
 template <class T, int BN>
 __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int op, int K, int N,
-                              int k0, int n0, int tid, typename T::E (&r)[BN * BK / 256],
-                              int (&idx)[BN * BK / 256], unsigned &fl) {
+                              int k0, int n0, int tid, typename T::E (&r)[BN * KDepth<T>::v / 256],
+                              int &ibase, int &istep, unsigned long long &fl) {
+    constexpr int BK = KDepth<T>::v;
     constexpr int NE = BN * BK / 256;
     fl = 0;
     if (op == 0) {
         const size_t safe = k0 + (size_t)n0 * ldb;
+        ibase = (tid % BK) * (BN + PAD) + tid / BK;
+        istep = 256 / BK;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
             const int e = tid + t * 256;
@@ -173,12 +186,13 @@ __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int 
             const int gk = k0 + kk, gn = n0 + nn;
             const bool in = gk < K && gn < N;
             r[t] = B[in ? gk + (size_t)gn * ldb : safe];
-            fl |= (in ? 1u : 0u) << (3 * t);
-            idx[t] = kk * (BN + PAD) + nn;
+            fl |= (unsigned long long)(in ? 1u : 0u) << (3 * t);
         }
     } else {
         const unsigned cj = (op == 2) ? 2u : 0u;
         const size_t safe = n0 + (size_t)k0 * ldb;
+        ibase = (tid / BN) * (BN + PAD) + tid % BN;
+        istep = (256 / BN) * (BN + PAD);
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
             const int e = tid + t * 256;
@@ -186,8 +200,7 @@ __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int 
             const int gk = k0 + kk, gn = n0 + nn;
             const bool in = gk < K && gn < N;
             r[t] = B[in ? gn + (size_t)gk * ldb : safe];
-            fl |= ((in ? 1u : 0u) | cj) << (3 * t);
-            idx[t] = kk * (BN + PAD) + nn;
+            fl |= (unsigned long long)((in ? 1u : 0u) | cj) << (3 * t);
         }
     }
 }
@@ -242,6 +255,7 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
     typedef typename T::Acc Acc;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int BK = KDepth<T>::v;
     constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
     __shared__ E As[BK * (BM + PAD)];
     __shared__ E Bs[BK * (BN + PAD)];
@@ -312,17 +326,17 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
         }
 
     E ra[NA], rb[NB];
-    int ia[NA], ib[NB];
-    unsigned fa = 0, fb = 0;
+    int iab = 0, ias = 0, ibb = 0, ibs = 0;
+    unsigned long long fa = 0, fb = 0;
     auto fetch = [&](int c) {
         int seg = c / cps;
         int k0 = (c % cps) * BK;
         if (seg == 0) {
-            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, ia, fa);
-            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ib, fb);
+            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
+            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
         } else {
-            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, ia, fa);
-            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ib, fb);
+            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
+            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
         }
     };
 
@@ -330,9 +344,9 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
     for (int c = c_beg; c < c_end; ++c) {
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < NA; ++t) As[ia[t]] = fix_elem<T>(ra[t], (fa >> (3 * t)) & 7u);
+        for (int t = 0; t < NA; ++t) As[iab + t * ias] = fix_elem<T>(ra[t], (unsigned)(fa >> (3 * t)) & 7u);
 #pragma unroll
-        for (int t = 0; t < NB; ++t) Bs[ib[t]] = fix_elem<T>(rb[t], (fb >> (3 * t)) & 7u);
+        for (int t = 0; t < NB; ++t) Bs[ibb + t * ibs] = fix_elem<T>(rb[t], (unsigned)(fb >> (3 * t)) & 7u);
         __syncthreads();
         if (c + 1 < c_end) fetch(c + 1);
 #pragma unroll
@@ -462,11 +476,11 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         tiles = K * (K + 1) / 2 + (g.tiles_m - K) * g.tiles_n;
         g.lower_tiles = 1;
     }
-    int chunks = cdiv(std::max(a.k, 0), BK) * g.nseg;
+    int chunks = cdiv(std::max(a.k, 0), KDepth<T>::v) * g.nseg;
     int splits = 1;
     // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
-    // (every split keeps at least 8 chunks of depth BK)
-    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 8) splits *= 2;
+    // (every split keeps at least 4 chunks)
+    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 4) splits *= 2;
     size_t need = (size_t)splits * a.m * a.n * sizeof(E);
     while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
         splits /= 2;
