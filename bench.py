@@ -31,6 +31,24 @@ def solve_flops(n, m):
     return (4.0 / 3.0 + 4.0 + 16.0 / 3.0) * n ** 3 + 20.0 * n * n * m
 
 
+def gemm_traffic():
+    """HBM bytes per launch of the complex-double GEMM tile kernel, from the committed counter
+    summary, or None when the kernel source has changed since the counters were taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", "gemm_tz_hbm_traffic_fp64_n10000.md")).read()
+        src = open(os.path.join(root, "paper_1207_1773_amd", "csrc", "gemm.hip"), "rb").read()
+    except OSError:
+        return None
+    import hashlib
+    import re
+    mb = re.search(r"^hbm_bytes_per_launch: (\d+)$", text, re.M)
+    mh = re.search(r"^gemm\.hip sha256: ([0-9a-f]{64})$", text, re.M)
+    if not mb or not mh or hashlib.sha256(src).hexdigest() != mh.group(1):
+        return None
+    return int(mb.group(1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,7 +244,8 @@ def main():
         "fractions": extra,
         "mixed": mixed,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": None,
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": gemm_traffic(),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE / WRITE_SIZE counters, copy-calibrated)",
                      "kernel": "hgv::gemm_kernel<hgv::TZ, 64, 64> (complex-double MFMA GEMM tiles, every launch "
                                "of a step; split-K reductions excluded)",
                      "launches_per_step": gemm_launches / args.steps,
