@@ -580,14 +580,23 @@ __global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int 
         }
     }
     __syncthreads();
-    // step 1: W tile (t0, cc) = V(:, t0..t0+15)^H Y_rows(:, cc..cc+15)
+    // step 1: W tile (t0, cc) = V(:, t0..t0+15)^H Y_rows(:, cc..cc+15); even and odd
+    // k-steps go to two sets of accumulators (six independent MFMA chains), added
+    // at the end
     {
-        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+        Acc p[2][3];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) p[h][c] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int q = 0; q < K1; ++q)
-            if (q < nks) q2_cmfma<E>(a1[q], Ys[t0 + 4 * q + lk][cc + lr], p1, p2, p3);
+            if (q < nks) q2_cmfma<E>(a1[q], Ys[t0 + 4 * q + lk][cc + lr], p[q & 1][0], p[q & 1][1], p[q & 1][2]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Ws[t0 + Q2M<E>::orow(lk, i)][cc + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+        for (int i = 0; i < 4; ++i) {
+            const auto p1 = p[0][0][i] + p[1][0][i], p2 = p[0][1][i] + p[1][1][i], p3 = p[0][2][i] + p[1][2][i];
+            Ws[t0 + Q2M<E>::orow(lk, i)][cc + lr] = El<E>::mk(p1 - p2, p3 - p1 - p2);
+        }
     }
     // step-3 operands of this wave's first row tile
     const int c3 = 16 * (wave & 1), q3 = wave >> 1;
@@ -605,7 +614,10 @@ __global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int 
         }
         return a;
     };
-    Ops8 a3 = load3(16 * q3);
+    // all three row tiles' operands, loaded together
+    Ops8 a3[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) a3[u] = load3(16 * (q3 + 2 * u));
     __syncthreads();
     // step 2: W2 tile (t0, cc) = T(t0.., :) W(:, cc..)  (T upper triangular; T^H lower)
     {
@@ -618,28 +630,41 @@ __global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int 
         for (int i = 0; i < 4; ++i) Ws[t0 + Q2M<E>::orow(lk, i)][cc + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
     }
     __syncthreads();
-    // step 3: row tiles q3, q3 + 2, q3 + 4 of column tile c3
+    // step 3: row tiles q3, q3 + 2, q3 + 4 of column tile c3, interleaved (nine
+    // independent MFMA chains)
+    {
+        Acc p[3][3];
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        const int r0 = 16 * (q3 + 2 * u);
-        const Ops8 a3n = load3(u < 2 ? r0 + 32 : 1 << 20);
-        if (r0 < nrows) {
-            Acc p1, p2 = {0, 0, 0, 0}, p3;
+        for (int u = 0; u < 3; ++u) {
+            const int r0 = 16 * (q3 + 2 * u);
+            p[u][1] = Acc{0, 0, 0, 0};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const E y = Ys[r0 + Q2M<E>::orow(lk, i)][c3 + lr];
-                p1[i] = y.x;
-                p3[i] = y.x + y.y;
+                p[u][0][i] = y.x;
+                p[u][2][i] = y.x + y.y;
             }
-            const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
-#pragma unroll
-            for (int v = 0; v < 8; ++v)
-                if (tlo + 4 * v < thi) q2_cmfma<E>(a3.v[v], Ws[tlo + 4 * v + lk][c3 + lr], p1, p2, p3);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                Ys[r0 + Q2M<E>::orow(lk, i)][c3 + lr] = El<E>::mk(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
         }
-        a3 = a3n;
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int r0 = 16 * (q3 + 2 * u);
+                const int tlo = max(0, r0 - b + 1) & ~3, thi = min(GM, r0 + 16);
+                if (r0 < nrows && tlo + 4 * v < thi)
+                    q2_cmfma<E>(a3[u].v[v], Ws[tlo + 4 * v + lk][c3 + lr], p[u][0], p[u][1], p[u][2]);
+            }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int r0 = 16 * (q3 + 2 * u);
+            if (r0 < nrows) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const auto p1 = p[u][0][i], p2 = p[u][1][i], p3 = p[u][2][i];
+                    Ys[r0 + Q2M<E>::orow(lk, i)][c3 + lr] = El<E>::mk(p1 - p2, p3 - p1 - p2);
+                }
+            }
+        }
     }
     __syncthreads();
     for (int t = tid; t < nrows * NC; t += 256) {
