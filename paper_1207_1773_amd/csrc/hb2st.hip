@@ -37,6 +37,7 @@
 // grid touch disjoint rows, so each anti-diagonal is one launch over
 // (group, column tile) pairs.
 #include <algorithm>
+#include <type_traits>
 
 #include "hgv_internal.h"
 
@@ -673,6 +674,148 @@ __global__ __launch_bounds__(256, 2) void q2_wf_kernel(int n, int m, int b, int 
     }
 }
 
+// Register-resident variant for complex double.  For v_mfma_f64_16x16x4f64
+// the accumulator layout (lane (lk, lr), register i -> row lk + 4 i, column lr)
+// is the B-operand layout of k-step i (row 4 i + lk, column lr), so one wave
+// keeps its 16 columns of Y_rows, of W = V^H Y_rows and of W2 = T W in
+// registers from one step to the next: Y_rows is the B operand of step 1 and
+// the accumulator of step 3, W is the B operand of step 2, W2 that of step 3.
+// The four waves of a workgroup take 64 consecutive columns and share the
+// group's V (reflector-major, Vc[t * b + i] = entry i of reflector t) and T
+// (column-major), copied into LDS by LDS-direct loads (no registers, all in
+// flight with the Y loads); operand reads mask what lies outside the
+// parallelogram.  With pitch b the two V operand patterns of a 16-lane group
+// hit 16 distinct bank groups.
+constexpr int Q2R_NC = 64;
+
+template <int BMAX>
+__global__ __launch_bounds__(256, 2) void q2_reg_kernel(int n, int m, int b, int g, int J, int Bt, int jlo, int ngs,
+                                                         int adj, const double2 *V2, const double2 *T2, double2 *Y,
+                                                         int ldy) {
+    typedef q2v4d Acc;
+    constexpr int GM = 32;
+    constexpr int RQ = (GM + BMAX - 1 + 3) / 4;   // k-steps (4 rows each) covering the group's rows
+    __shared__ double2 Vc[GM * BMAX];
+    __shared__ double2 Tc[GM * GM];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ct = (m + Q2R_NC - 1) / Q2R_NC;
+    const int items = ngs * ct;
+    const int per = (items + 7) / 8;
+    const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (p >= items) return;
+    const int j = jlo + p / ct, c0 = (p % ct) * Q2R_NC;
+    const int cw = c0 + 16 * wave + lr;           // this lane's column
+    const bool colok = cw < m;
+    const int B = Bt + j, s0 = B * g;
+    const int R0 = s0 + 1 + j * b;
+    const int nrows = min(g + b - 1, n - R0);
+    const int tmax = min(g, n - 1 - s0);          // reflectors of the group that exist
+    const double2 *tg = T2 + ((size_t)B * J + j) * g * g;
+    const int sblk = s0 / b, soff = s0 % b;
+    auto keep = [](bool in, double2 v) { return make_double2(in ? v.x : 0.0, in ? v.y : 0.0); };
+    // V and T into LDS (element e of the copy: lane e % 64 of instruction e / 64)
+#pragma unroll
+    for (int u = 0; u < GM * BMAX / 256; ++u) {
+        const int e = 256 * u + 64 * wave + lane, t = e / b, i = e % b;
+        int sb = soff + t, blk = sblk;
+        if (sb >= b) {
+            sb -= b;
+            ++blk;
+        }
+        const bool in = e < g * b && t < tmax;
+        const double2 *src = V2 + (in ? (((size_t)blk * J + j) * b + sb) * b + i : 0);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)(&Vc[256 * u + 64 * wave]), 16, 0,
+                                         0);
+    }
+#pragma unroll
+    for (int u = 0; u < GM * GM / 256; ++u) {
+        const int e = 256 * u + 64 * wave + lane;
+        const double2 *src = tg + (e < g * g ? e : 0);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)(&Tc[256 * u + 64 * wave]), 16, 0,
+                                         0);
+    }
+    // Y rows of this lane (B-operand layout): y[q] = Y(R0 + 4q + lk, cw)
+    double2 y[RQ];
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int r = 4 * q + lk;
+        const bool in = colok && r < nrows;
+        y[q] = keep(in, Y[in ? R0 + r + (size_t)cw * ldy : (size_t)R0 + (size_t)c0 * ldy]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    // V(r, t) (zero outside the parallelogram and past the last reflector)
+    auto vget = [&](int r, int t) {
+        const int i = r - t;
+        const bool in = i >= 0 && i < b && t < tmax;
+        return keep(in, Vc[in ? t * b + i : 0]);
+    };
+    // T(row, col), or T^H for Q2^H (zero outside g x g)
+    auto tget = [&](int row, int col) {
+        const bool in = row < g && col < g;
+        const double2 v = keep(in, Tc[in ? (adj ? col + row * g : row + col * g) : 0]);
+        return make_double2(v.x, adj ? -v.y : v.y);
+    };
+    auto combine = [](const Acc &p1, const Acc &p2, const Acc &p3, int i) {
+        return make_double2(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+    };
+    // step 1: W (32 x 16) = V^H Y_rows, one t tile after the other
+    double2 w[2][4];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+        constexpr int QS = (15 + BMAX + 3) / 4;   // k-steps of one t tile
+#pragma unroll
+        for (int q = 0; q < RQ; ++q)
+            if (q >= 4 * tt && q < 4 * tt + QS) {
+                const double2 v = vget(4 * q + lk, 16 * tt + lr);
+                q2_cmfma<double2>(make_double2(v.x, -v.y), y[q], p1, p2, p3);
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[tt][i] = combine(p1, p2, p3, i);
+    }
+    // step 2: W2 = T W (T upper triangular; T^H lower for Q2^H)
+    double2 w2[2][4];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq)
+            if (adj ? kq <= 4 * tt + 3 : kq >= 4 * tt)
+                q2_cmfma<double2>(tget(16 * tt + lr, 4 * kq + lk), w[kq >> 2][kq & 3], p1, p2, p3);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w2[tt][i] = combine(p1, p2, p3, i);
+    }
+    // step 3: Y_rows -= V W2, row tile rt accumulates into y[4 rt .. 4 rt + 3]
+#pragma unroll
+    for (int rt = 0; rt < RQ / 4; ++rt) {
+        if (16 * rt >= nrows) continue;
+        Acc p1, p2 = {0, 0, 0, 0}, p3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            p1[i] = y[4 * rt + i].x;
+            p3[i] = y[4 * rt + i].x + y[4 * rt + i].y;
+        }
+        const int tlo = max(0, 16 * rt - b + 1), thi = min(GM, 16 * rt + 16);
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq)
+            if (4 * kq + 3 >= tlo && 4 * kq < thi) {
+                const double2 v = vget(16 * rt + lr, 4 * kq + lk);
+                q2_cmfma<double2>(make_double2(-v.x, -v.y), w2[kq >> 2][kq & 3], p1, p2, p3);
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[4 * rt + i] = combine(p1, p2, p3, i);
+    }
+#pragma unroll
+    for (int q = 0; q < RQ; ++q) {
+        const int r = 4 * q + lk;
+        if (colok && r < nrows) Y[R0 + r + (size_t)cw * ldy] = y[q];
+    }
+}
+
 // reflectors per group (sweeps s0 .. s0 + g - 1 at one step j)
 static int q2_group(int b) { return std::min(b, 32); }
 
@@ -718,13 +861,23 @@ void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, 
         }
         if (jhi < jlo) continue;
         const int ngs = jhi - jlo + 1;
-        const int grid = 8 * cdiv(ngs * ct, 8);
-        if (b <= 32)
-            hipLaunchKernelGGL((q2_wf_kernel<32, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
-                               jlo, ngs, (int)adj, V2, T2, Y, ldy);
-        else
-            hipLaunchKernelGGL((q2_wf_kernel<64, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
-                               jlo, ngs, (int)adj, V2, T2, Y, ldy);
+        if constexpr (std::is_same<E, double2>::value) {
+            const int grid = 8 * cdiv(ngs * cdiv(m, Q2R_NC), 8);
+            if (b <= 32)
+                hipLaunchKernelGGL((q2_reg_kernel<32>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                                   jlo, ngs, (int)adj, V2, T2, Y, ldy);
+            else
+                hipLaunchKernelGGL((q2_reg_kernel<64>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                                   jlo, ngs, (int)adj, V2, T2, Y, ldy);
+        } else {
+            const int grid = 8 * cdiv(ngs * ct, 8);
+            if (b <= 32)
+                hipLaunchKernelGGL((q2_wf_kernel<32, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                                   jlo, ngs, (int)adj, V2, T2, Y, ldy);
+            else
+                hipLaunchKernelGGL((q2_wf_kernel<64, E>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
+                                   jlo, ngs, (int)adj, V2, T2, Y, ldy);
+        }
         HGV_LAUNCH_CHECK();
     }
 }
