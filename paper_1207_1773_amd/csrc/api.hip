@@ -599,6 +599,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
         hipStream_t user = ctx->stream;
         HGV_HIP(hipEventRecord(ctx->fork_ev, user));
         for (int k = 0; k < K; ++k) HGV_HIP(hipStreamWaitEvent(ctx->side[k], ctx->fork_ev, 0));
+        ctx->concurrent = true;
         try {
             for (int idx : order) {
                 int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -618,9 +619,11 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             }
         } catch (...) {
             ctx->stream = user;
+            ctx->concurrent = false;
             throw;
         }
         ctx->stream = user;
+        ctx->concurrent = false;
         for (int k = 0; k < K; ++k) {
             HGV_HIP(hipEventRecord(ctx->side_ev[k], ctx->side[k]));
             HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));

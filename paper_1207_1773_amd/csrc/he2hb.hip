@@ -62,26 +62,15 @@ struct PanelShared {
     double2 red[4][PNB];
 };
 
-// Step j (-1: only prepare column 0) of the panel QR on row chunk g.
+// The three parts of step j (-1: only prepare column 0) of the panel QR on row
+// chunk g: load the chunk's columns c0.. into LDS, compute the step, write the
+// columns back.
 template <class E>
-__device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int j, int g) {
+__device__ void panel_chunk_load(const PanelArgs<E> &a, PanelShared<E> &sh, int g, int c0) {
     auto &Ps = sh.Ps;
-    auto &s = sh.s;
-    auto &r0v = sh.r0v;
-    auto &w = sh.w;
-    auto &vrow = sh.vrow;
-    auto &red = sh.red;
     const int tid = threadIdx.x;
     const int row0 = g * PCH;
     const int rows = min(PCH, a.N - row0);
-    const int c0 = max(j, 0);
-    const int ncol = a.jb - c0;
-    const int ib = (j + 1) & 1, ob = (j + 2) & 1;
-    const double2 *part_in = a.part + (size_t)ib * a.G * PNB;
-    double2 *part_out = a.part + (size_t)ob * a.G * PNB;
-    const double2 *row_in = a.rowb + ib * PNB;
-    double2 *row_out = a.rowb + ob * PNB;
-
     // load the chunk's columns c0..jb-1 through registers: every load is issued
     // (elements outside the chunk read its in-range element (row0, c0)) before
     // the first one is waited for
@@ -103,6 +92,40 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
             Ps[r][c < a.jb ? c : PNB] = pv[u];
         }
     }
+}
+
+template <class E>
+__device__ void panel_chunk_store(const PanelArgs<E> &a, PanelShared<E> &sh, int g, int c0) {
+    auto &Ps = sh.Ps;
+    const int tid = threadIdx.x;
+    const int row0 = g * PCH;
+    const int rows = min(PCH, a.N - row0);
+    const int ncol = a.jb - c0;
+    // write back the updated columns
+    for (int t = tid; t < PCH * ncol; t += 256) {
+        int r = t % PCH, c = c0 + t / PCH;
+        if (r < rows) a.P[row0 + r + (size_t)c * a.ldp] = Ps[r][c];
+    }
+}
+
+template <class E>
+__device__ void panel_chunk_compute(const PanelArgs<E> &a, PanelShared<E> &sh, int j, int g) {
+    auto &Ps = sh.Ps;
+    auto &s = sh.s;
+    auto &r0v = sh.r0v;
+    auto &w = sh.w;
+    auto &vrow = sh.vrow;
+    auto &red = sh.red;
+    const int tid = threadIdx.x;
+    const int row0 = g * PCH;
+    const int rows = min(PCH, a.N - row0);
+    const int c0 = max(j, 0);
+    const int ncol = a.jb - c0;
+    const int ib = (j + 1) & 1, ob = (j + 2) & 1;
+    const double2 *part_in = a.part + (size_t)ib * a.G * PNB;
+    double2 *part_out = a.part + (size_t)ob * a.G * PNB;
+    const double2 *row_in = a.rowb + ib * PNB;
+    double2 *row_out = a.rowb + ob * PNB;
     auto ld = [&](int r, int c) -> double2 { return El<E>::to(Ps[r][c]); };
     if (j >= 0) {
         // finish the reduction of the partial sums for column j: 4 threads per
@@ -200,18 +223,64 @@ __device__ void panel_chunk_step(const PanelArgs<E> &a, PanelShared<E> &sh, int 
             if (lr >= 0 && lr < rows && tid >= jn && tid < a.jb) row_out[tid] = ld(lr, tid);
         }
     }
-    // write back the updated columns
-    for (int t = tid; t < PCH * ncol; t += 256) {
-        int r = t % PCH, c = c0 + t / PCH;
-        if (r < rows) a.P[row0 + r + (size_t)c * a.ldp] = Ps[r][c];
-    }
 }
 
-// Step j (-1: only prepare column 0) of the panel QR; workgroup g = row chunk g.
+// Step j of the panel QR; workgroup g = row chunk g.
 template <class E>
 __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a, int j) {
     __shared__ PanelShared<E> sh;
-    panel_chunk_step<E>(a, sh, j, blockIdx.x);
+    const int c0 = max(j, 0);
+    panel_chunk_load<E>(a, sh, blockIdx.x, c0);
+    panel_chunk_compute<E>(a, sh, j, blockIdx.x);
+    panel_chunk_store<E>(a, sh, blockIdx.x, c0);
+}
+
+// Wait until flags[0 .. G-1] >= target: the lanes of wave 0 poll the flags with
+// relaxed device-scope loads, then take an acquire fence; the workgroup
+// barrier follows.  The wait is bounded: one that gives up sets *err, and
+// every wait that sees *err set returns at once, so the launch always ends
+// (with *err reporting that the result is not valid).
+__device__ inline void panel_wait(const int *flags, int G, int target, int *err) {
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        long spins = 0;
+        for (;;) {
+            bool ok = true;
+            for (int q = tid; q < G; q += 64)
+                ok = ok && __hip_atomic_load(&flags[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+            if (__all(ok)) break;
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1L << 20)) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// The whole panel QR in one cooperative launch: workgroup g keeps row chunk g
+// in LDS for every column step.  After step j it publishes the partial inner
+// products of column j+1 (and, for the chunk holding row j+1, that row) and
+// then flags[g] = gen + j + 2 with a release store; step j+1 starts once every
+// chunk's flag has reached that value.  gen grows from panel to panel, so the
+// flags are cleared once per reduction.
+template <class E>
+__global__ __launch_bounds__(256) void panel_persist_kernel(PanelArgs<E> a, int *flags, int gen, int *err) {
+    __shared__ PanelShared<E> sh;
+    const int g = blockIdx.x;
+    const int r = min(a.N, a.jb);
+    panel_chunk_load<E>(a, sh, g, 0);
+    for (int j = -1; j < r; ++j) {
+        if (j >= 0) panel_wait(flags, a.G, gen + j + 1, err);
+        panel_chunk_compute<E>(a, sh, j, g);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(&flags[g], gen + j + 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    panel_chunk_store<E>(a, sh, g, 0);
 }
 
 // Explicit V (N x r): unit diagonal, zeros above, reflector entries below.
@@ -279,18 +348,42 @@ static int num_panels(int n, int nb) { return (n - nb - 1 >= 0) ? (n - nb - 1) /
 
 // Panel QR + T for panel P (N x jb, r = min(N, jb) reflectors).  Leaves V in
 // P (below the diagonal), beta on the diagonal, R above; T (r x r) in T, ldt.
+// Workgroups of the persistent panel kernel that fit on the device at once.
+template <class E>
+static int panel_persist_capacity(hgv_ctx_s *ctx) {
+    int cus = 0, per = 0;
+    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, panel_persist_kernel<E>, 256, 0));
+    return cus * per;
+}
+
+__global__ void fill_int_kernel(int *p, int n, int v) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// flags: progress flags of the persistent panel kernel (one per row chunk),
+// err: its give-up flag (a slot no chunk uses), gen: this panel's flag base;
+// the per-step launches are used when the chunks cannot all be resident at once
 template <class E>
 static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau, double2 *part, double2 *rowb,
-                     E *Vw, E *Gm, E *T, int ldt, void *ws, size_t wsb) {
+                     E *Vw, E *Gm, E *T, int ldt, void *ws, size_t wsb, int *flags, int *err, int gen,
+                     int capacity) {
     typedef typename El<E>::Gemm Gm_t;
     const int r = std::min(N, jb);
     const int G = cdiv(N, PCH);
     PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
     a.part = part; a.rowb = rowb;
-    for (int j = -1; j < r; ++j) {
-        hipLaunchKernelGGL(panel_step_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a, j);
-        HGV_LAUNCH_CHECK();
+    if (G <= capacity) {
+        void *args[] = {&a, &flags, &gen, &err};
+        HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(panel_persist_kernel<E>), dim3(G), dim3(256),
+                                           args, 0, ctx->stream));
+    } else {
+        for (int j = -1; j < r; ++j) {
+            hipLaunchKernelGGL(panel_step_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a, j);
+            HGV_LAUNCH_CHECK();
+        }
     }
     hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
                        Vw, N);
@@ -322,9 +415,13 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
     E *Gm = ar.take<E>((size_t)nb * nb);
     E *M = ar.take<E>((size_t)nb * nb);
     E *M2 = ar.take<E>((size_t)nb * nb);
+    int *flags = ar.take<int>(Gmax + 1);   // Gmax progress flags, then the give-up flag
     if (ar.measuring() || n == 0) return;
     const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0), mhalf = El<E>::mk(-0.5, 0.0);
     zero_async(ctx, T1, (size_t)std::max(np, 1) * nb * nb);
+    hipLaunchKernelGGL(fill_int_kernel, dim3(cdiv(Gmax + 1, 256)), dim3(256), 0, ctx->stream, flags, Gmax + 1, 0);
+    HGV_LAUNCH_CHECK();
+    const int capacity = ctx->concurrent ? 0 : panel_persist_capacity<E>(ctx);
     for (int p = 0; p < np; ++p) {
         const int k = p * nb;
         const int jb = std::min(nb, n - k);
@@ -332,7 +429,8 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
         const int r = std::min(N, jb);
         E *P = A + (k + nb) + (size_t)k * lda;
         E *T = T1 + (size_t)p * nb * nb;
-        panel_qr<E>(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb);
+        panel_qr<E>(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb, flags, flags + Gmax,
+                    p * (PNB + 2), capacity);
         E *A22 = A + (k + nb) + (size_t)(k + nb) * lda;
         Gm_t g;
         // Y = V T

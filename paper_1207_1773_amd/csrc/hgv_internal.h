@@ -28,6 +28,10 @@ struct hgv_ctx_s {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> side_ev;
     hipEvent_t fork_ev = nullptr;
+    // Set while problems run concurrently on the side streams: kernels whose
+    // workgroups wait for each other (and so need to be resident together)
+    // then use their launch-per-step forms where they have one.
+    bool concurrent = false;
     int magic = 0x68677631;
 };
 
