@@ -246,7 +246,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": gemm_traffic(),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE / WRITE_SIZE counters, copy-calibrated)",
-                     "kernel": "hgv::gemm_kernel<hgv::TZ, 64, 64> (complex-double MFMA GEMM tiles, every launch "
+                     "kernel": "hgv::gemm_kernel<hgv::TZ, 64, 64, 4> (complex-double MFMA GEMM tiles, every launch "
                                "of a step; split-K reductions excluded)",
                      "launches_per_step": gemm_launches / args.steps,
                      "avg_launch_ms": gemm_avg_ms,

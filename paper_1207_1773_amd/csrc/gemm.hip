@@ -87,11 +87,23 @@ struct GemmDev {
     int tiles_m, tiles_n;
 };
 
-// k depth of a staged tile (a depth of 32 for the real 128 x 128 tile runs out
-// of architectural registers and is slower)
+// Tile shape per element type: output BM x BN per workgroup, k depth of a
+// staged tile, waves per workgroup (2 x NW/2, each owning BM/2 x 2BN/NW).  The
+// complex tiles use 4 waves and depth 16 (two workgroups per CU); the real
+// 128 x 128 tile uses 8 waves, so that each thread holds half the accumulators
+// and half the prefetched operands and a depth of 32 fits in registers: its
+// chunk of MFMAs then covers the latency of the next chunk's loads.
+template <class T>
+struct Shape {
+    static constexpr int BM = 64, BN = 64, BK = 16, NW = 4;
+};
+template <>
+struct Shape<TD> {
+    static constexpr int BM = 128, BN = 128, BK = 32, NW = 8;
+};
 template <class T>
 struct KDepth {
-    static constexpr int v = 16;
+    static constexpr int v = Shape<T>::BK;
 };
 constexpr int PAD = 1;
 
@@ -126,22 +138,22 @@ __device__ inline double fix_elem<TD>(double v, unsigned f) { return (f & 1u) ? 
 // affine in t for both access orders); fl receives the fix-up bits (3 per
 // element, at most 21 elements).  op: 0 N, 1 T, 2 C, 3 H (Hermitian, lower
 // triangle stored).
-template <class T, int BM>
+template <class T, int BM, int NT>
 __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int op, int M, int K,
-                              int m0, int k0, int tid, typename T::E (&r)[BM * KDepth<T>::v / 256],
+                              int m0, int k0, int tid, typename T::E (&r)[BM * KDepth<T>::v / NT],
                               int &ibase, int &istep, unsigned long long &fl) {
     constexpr int BK = KDepth<T>::v;
-    constexpr int NE = BM * BK / 256;
+    constexpr int NE = BM * BK / NT;
     const bool mirrored = (op == 1 || op == 2) || (op == 3 && m0 + BM - 1 < k0);
     fl = 0;
     if (!mirrored) {
         const bool herm = op == 3;
         const size_t safe = m0 + (size_t)k0 * lda;
         ibase = (tid / BM) * (BM + PAD) + tid % BM;
-        istep = (256 / BM) * (BM + PAD);
+        istep = (NT / BM) * (BM + PAD);
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            const int e = tid + t * 256;
+            const int e = tid + t * NT;
             const int mm = e % BM, kk = e / BM;
             const int gm = m0 + mm, gk = k0 + kk;
             const bool in = gm < M && gk < K;
@@ -154,10 +166,10 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
         const unsigned cj = (op == 2 || op == 3) ? 2u : 0u;
         const size_t safe = k0 + (size_t)m0 * lda;
         ibase = (tid % BK) * (BM + PAD) + tid / BK;
-        istep = 256 / BK;
+        istep = NT / BK;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            const int e = tid + t * 256;
+            const int e = tid + t * NT;
             const int kk = e % BK, mm = e / BK;
             const int gm = m0 + mm, gk = k0 + kk;
             const bool in = gm < M && gk < K;
@@ -168,20 +180,20 @@ __device__ inline void load_a(const typename T::E *__restrict__ A, int lda, int 
 }
 
 // Load the BK x BN tile of op(B) (rows k0.., cols n0..).  op: 0 N, 1 T, 2 C.
-template <class T, int BN>
+template <class T, int BN, int NT>
 __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int op, int K, int N,
-                              int k0, int n0, int tid, typename T::E (&r)[BN * KDepth<T>::v / 256],
+                              int k0, int n0, int tid, typename T::E (&r)[BN * KDepth<T>::v / NT],
                               int &ibase, int &istep, unsigned long long &fl) {
     constexpr int BK = KDepth<T>::v;
-    constexpr int NE = BN * BK / 256;
+    constexpr int NE = BN * BK / NT;
     fl = 0;
     if (op == 0) {
         const size_t safe = k0 + (size_t)n0 * ldb;
         ibase = (tid % BK) * (BN + PAD) + tid / BK;
-        istep = 256 / BK;
+        istep = NT / BK;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            const int e = tid + t * 256;
+            const int e = tid + t * NT;
             const int kk = e % BK, nn = e / BK;
             const int gk = k0 + kk, gn = n0 + nn;
             const bool in = gk < K && gn < N;
@@ -192,10 +204,10 @@ __device__ inline void load_b(const typename T::E *__restrict__ B, int ldb, int 
         const unsigned cj = (op == 2) ? 2u : 0u;
         const size_t safe = n0 + (size_t)k0 * ldb;
         ibase = (tid / BN) * (BN + PAD) + tid % BN;
-        istep = (256 / BN) * (BN + PAD);
+        istep = (NT / BN) * (BN + PAD);
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-            const int e = tid + t * 256;
+            const int e = tid + t * NT;
             const int nn = e % BN, kk = e / BN;
             const int gk = k0 + kk, gn = n0 + nn;
             const bool in = gk < K && gn < N;
@@ -249,14 +261,15 @@ __device__ inline double2 e_add(double2 a, double2 b) { return make_double2(a.x 
 __device__ inline float2 e_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ inline double e_add(double a, double b) { return a + b; }
 
-template <class T, int BM, int BN>
-__global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g) {
+template <class T, int BM, int BN, int NW>
+__global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
     typedef typename T::E E;
     typedef typename T::Acc Acc;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int NT = NW * 64;
+    constexpr int WM = BM / 2, WN = BN / (NW / 2);
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int BK = KDepth<T>::v;
-    constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+    constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
     __shared__ E As[BK * (BM + PAD)];
     __shared__ E Bs[BK * (BN + PAD)];
 
@@ -332,11 +345,11 @@ __global__ __launch_bounds__(256, T::cplx ? 2 : 1) void gemm_kernel(GemmDev<T> g
         int seg = c / cps;
         int k0 = (c % cps) * BK;
         if (seg == 0) {
-            load_a<T, BM>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
-            load_b<T, BN>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
+            load_a<T, BM, NT>(g.A, g.lda, g.opa, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
+            load_b<T, BN, NT>(g.B, g.ldb, g.opb, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
         } else {
-            load_a<T, BM>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
-            load_b<T, BN>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
+            load_a<T, BM, NT>(g.A2, g.lda2, g.opa2, g.m, g.k, m0, k0, tid, ra, iab, ias, fa);
+            load_b<T, BN, NT>(g.B2, g.ldb2, g.opb2, g.k, g.n, k0, n0, tid, rb, ibb, ibs, fb);
         }
     };
 
@@ -464,8 +477,7 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     // tile shape: 64x64 (4 waves of 32x32) for the complex types; 128x128 for
     // real (one MFMA per 16x16x4 block, so the larger tile keeps the operand
     // bytes per flop as low as the complex tile's)
-    constexpr int BM = T::cplx ? 64 : 128;
-    constexpr int BN = T::cplx ? 64 : 128;
+    constexpr int BM = Shape<T>::BM, BN = Shape<T>::BN, NW = Shape<T>::NW;
     g.tiles_m = cdiv(a.m, BM);
     g.tiles_n = cdiv(a.n, BN);
     int tiles = g.tiles_m * g.tiles_n;
@@ -506,7 +518,7 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         HGV_HIP(hipEventRecord(e0, ctx->stream));
     }
     dim3 grid(tiles, splits);
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN>), grid, dim3(256), 0, ctx->stream, g);
+    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, g);
     HGV_LAUNCH_CHECK();
     if (timed) {
         HGV_HIP(hipEventRecord(e1, ctx->stream));
