@@ -80,9 +80,10 @@ __device__ inline double2 group_sum(double2 x) {
 //   E (rows I_j, columns I_{j-1}) lives in LDS because it is used by rows (the
 //   right application of the previous reflector) and then by columns (the
 //   left application of the new one).
-template <int BM, class E>
-__global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
-    constexpr int TPR = 256 / BM;   // lanes per row
+template <int BM, int NT, class E>
+__global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a) {
+    constexpr int NWV = NT / 64;    // waves
+    constexpr int TPR = NT / BM;    // lanes per row
     constexpr int NU = BM / TPR;    // row elements per lane
     __shared__ double2 Es[BM][BM + 1];
     // staging of E for the LDS-direct loads: column c at Et[c][0 .. BM-1], each
@@ -154,8 +155,8 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
                 // block read the in-range element (r0, r0) and are zeroed in the
                 // copy into Es
 #pragma unroll
-                for (int cc = 0; cc < BM / 4; ++cc) {
-                    const int c = (tid >> 6) + 4 * cc, i = lane;
+                for (int cc = 0; cc < BM / NWV; ++cc) {
+                    const int c = (tid >> 6) + NWV * cc, i = lane;
                     const bool in = i < L && c < b;
                     const size_t idx = in ? (r0 + i - p0 - c) + (size_t)(p0 + c) * ldb : (size_t)r0 * ldb;
                     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(AB + idx),
@@ -167,24 +168,24 @@ __global__ __launch_bounds__(256) void hb2st_kernel(HbArgs<E> a) {
                 __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
 #pragma unroll
-                for (int u = 0; u < BM * BM / 256; ++u) {
-                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                for (int u = 0; u < BM * BM / NT; ++u) {
+                    const int t = tid + NT * u, i = t % BM, c = t / BM;
                     Es[i][c] = zsel(i < L && c < b, El<E>::to(Et[c][i]), zero);
                 }
             } else {
                 // E through registers: all of a thread's E and D loads are issued
                 // before the first one is waited for
-                E ev[BM * BM / 256];
+                E ev[BM * BM / NT];
 #pragma unroll
-                for (int u = 0; u < BM * BM / 256; ++u) {
-                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                for (int u = 0; u < BM * BM / NT; ++u) {
+                    const int t = tid + NT * u, i = t % BM, c = t / BM;
                     const bool in = i < L && c < b;
                     ev[u] = AB[in ? (r0 + i - p0 - c) + (size_t)(p0 + c) * ldb : (size_t)r0 * ldb];
                 }
                 upper = load_d();
 #pragma unroll
-                for (int u = 0; u < BM * BM / 256; ++u) {
-                    const int t = tid + 256 * u, i = t % BM, c = t / BM;
+                for (int u = 0; u < BM * BM / NT; ++u) {
+                    const int t = tid + NT * u, i = t % BM, c = t / BM;
                     Es[i][c] = zsel(i < L && c < b, El<E>::to(ev[u]), zero);
                 }
             }
@@ -354,16 +355,16 @@ static void zero2(hgv_ctx_s *ctx, E *p, size_t cnt) {
     HGV_LAUNCH_CHECK();
 }
 
-template <int BM, class E>
+template <int BM, int NT, class E>
 static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
     int dev = ctx->device, cus = 0, per = 0;
     HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM, E>, 256, 0));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM, NT, E>, NT, 0));
     // a sweep starts two tasks behind its predecessor, so about J/2 sweeps are
     // in flight at once; more workgroups would only poll
     int G = std::max(1, std::min({cus * std::max(per, 1), a.n - 1, a.J / 2 + 4}));
     void *args[] = {&a};
-    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM, E>), dim3(G), dim3(256), args, 0,
+    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM, NT, E>), dim3(G), dim3(NT), args, 0,
                                        ctx->stream));
 }
 
@@ -384,8 +385,10 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     HGV_LAUNCH_CHECK();
     if (n >= 2) {
         HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
-        if (b <= 32) launch_hb2st<32, E>(ctx, a);
-        else launch_hb2st<64, E>(ctx, a);
+        // 64-wide bands: 512 threads (8 elements of a task's diagonal block per
+        // thread), which shortens the arithmetic of the dependent task chain
+        if (b <= 32) launch_hb2st<32, 256, E>(ctx, a);
+        else launch_hb2st<64, 512, E>(ctx, a);
     }
     hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
     HGV_LAUNCH_CHECK();
