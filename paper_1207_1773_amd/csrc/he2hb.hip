@@ -495,8 +495,11 @@ __global__ void place_t_kernel(int r, const E *T, int ldt, E *Tb, int ldb) {
 // I - V T V^H (V: the panels' reflectors side by side, each panel's block
 // starting nb rows below the previous one; T upper triangular with the
 // off-diagonal blocks T[0:c, c:c+r] = -T[0:c, 0:c] (V[:, 0:c]^H V[:, c:c+r]) T_p),
-// so that every pass over Y has inner dimension Q1_MERGE * nb.
-constexpr int Q1_MERGE = 4;
+// so that every pass over Y has inner dimension merge * nb: 8 panels for many
+// columns of Y, 4 for few (building the merged T costs merge^2 nb^2 (n - k)
+// per group whatever the number of columns).
+constexpr int Q1_MERGE = 8;   // largest merge
+static int q1_merge(int m) { return m >= 2048 ? 8 : 4; }
 
 // Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y (last
 // group first), or Y <- Q1^H Y (first group first, T^H in place of T).
@@ -506,7 +509,8 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
     typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
-    const int R = Q1_MERGE * nb;
+    const int mg = q1_merge(m);
+    const int R = mg * nb;
     size_t wsb = zgemm_splitk_bytes(n);
     void *ws = ar.take<char>(wsb);
     E *Vb = ar.take<E>((size_t)std::max(n, 1) * R);
@@ -517,10 +521,10 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
     E *W2 = ar.take<E>((size_t)R * std::max(m, 1));
     if (ar.measuring() || n == 0 || m == 0 || np == 0) return;
     const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0);
-    const int ngrp = cdiv(np, Q1_MERGE);
+    const int ngrp = cdiv(np, mg);
     for (int q = 0; q < ngrp; ++q) {
         const int gi = adj ? q : ngrp - 1 - q;
-        const int p0 = gi * Q1_MERGE, p1 = std::min(np, p0 + Q1_MERGE);
+        const int p0 = gi * mg, p1 = std::min(np, p0 + mg);
         const int k0 = p0 * nb;
         const int Nb = n - k0 - nb;                    // rows of the merged V (start at row k0 + nb)
         if (Nb <= 0) continue;
