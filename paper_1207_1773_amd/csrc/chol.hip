@@ -189,6 +189,7 @@ struct TriCtx {
     hgv_ctx_s *ctx;
     double2 *ws;
     size_t wsb;
+    double2 *zw = nullptr;   // hegst: L21 A'11 of the current split (n2 x n1, ld n2)
 };
 
 static const double2 *linv_at(const double2 *Linv, int off) { return Linv + (size_t)(off / LEAF) * LEAF * LEAF; }
@@ -363,13 +364,13 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
     hegst_rec(t, n1, A11, lda, L11, ldl, Linv);
     trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);      // A21 <- A21 L11^-H
     fill_upper_from_lower(t.ctx, n1, A11, lda);                   // A'11 as a full matrix
-    ZGemm h;  // A21 -= 1/2 L21 A'11
+    ZGemm h;  // Z = L21 A'11, used for both half-updates of A21 (one product instead of two)
     h.m = n2; h.n = n1; h.k = n1;
     h.opa = 'N'; h.A = L21; h.lda = ldl;
     h.opb = 'N'; h.B = A11; h.ldb = lda;
-    h.alpha = make_double2(-0.5, 0.0); h.beta = make_double2(1.0, 0.0);
-    h.C = A21; h.ldc = lda;
+    h.C = t.zw; h.ldc = n2;
     zgemm(t.ctx, h, t.ws, t.wsb);
+    add_scaled(t.ctx, n2, n1, -0.5, t.zw, n2, A21, lda);         // A21 -= 1/2 Z
     ZGemm r;  // A22 -= A21 L21^H + L21 A21^H (lower)
     r.m = n2; r.n = n2; r.k = n1;
     r.opa = 'N'; r.A = A21; r.lda = lda;
@@ -380,7 +381,7 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
     r.C = A22; r.ldc = lda;
     r.lower = 1;
     zgemm(t.ctx, r, t.ws, t.wsb);
-    zgemm(t.ctx, h, t.ws, t.wsb);                                  // A21 -= 1/2 L21 A'11
+    add_scaled(t.ctx, n2, n1, -0.5, t.zw, n2, A21, lda);         // A21 -= 1/2 Z
     trsm_left_ln_rec(t, n2, n1, L22, ldl, linv_at(Linv, n1), A21, lda);   // A21 <- L22^-1 A21
     hegst_rec(t, n2, A22, lda, L22, ldl, linv_at(Linv, n1));
 }
@@ -388,6 +389,9 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
 void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, Arena &ar) {
     double2 *Linv;
     TriCtx t = tri_scratch(ctx, ar, n, &Linv);
+    // every split of the recursion has n1 n2 <= (n / 2 + 64)^2
+    const size_t zh = (size_t)std::max(n, 1) / 2 + LEAF;
+    t.zw = ar.take<double2>(zh * zh);
     if (ar.measuring()) return;
     invert_diag_blocks(ctx, n, L, ldl, Linv);
     hegst_rec(t, n, A, lda, L, ldl, Linv);

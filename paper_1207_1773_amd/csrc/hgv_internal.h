@@ -187,6 +187,8 @@ inline void gemm_any(hgv_ctx_s *ctx, const CGemm &g, void *ws, size_t wsb) {
 void fill_upper_from_lower(hgv_ctx_s *ctx, int n, double2 *A, int lda);
 void zero_strict_upper(hgv_ctx_s *ctx, int n, double2 *A, int lda);
 void copy_matrix(hgv_ctx_s *ctx, int m, int n, const double2 *A, int lda, double2 *B, int ldb);
+// Y += alpha X (m x n, alpha real)
+void add_scaled(hgv_ctx_s *ctx, int m, int n, double alpha, const double2 *X, int ldx, double2 *Y, int ldy);
 void set_info(hgv_ctx_s *ctx, int *d_info, int value);
 
 // ---- stages ----------------------------------------------------------------------

@@ -22,6 +22,16 @@ __global__ void copy_kernel(int m, int n, const double2 *A, int lda, double2 *B,
     if (i < m && j < n) B[i + (size_t)j * ldb] = A[i + (size_t)j * lda];
 }
 
+__global__ void add_scaled_kernel(int m, int n, double alpha, const double2 *X, int ldx, double2 *Y, int ldy) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i < m && j < n) {
+        const double2 x = X[i + (size_t)j * ldx];
+        double2 &y = Y[i + (size_t)j * ldy];
+        y = make_double2(y.x + alpha * x.x, y.y + alpha * x.y);
+    }
+}
+
 __global__ void set_int_kernel(int *p, int v) { *p = v; }
 
 void fill_upper_from_lower(hgv_ctx_s *ctx, int n, double2 *A, int lda) {
@@ -39,6 +49,13 @@ void zero_strict_upper(hgv_ctx_s *ctx, int n, double2 *A, int lda) {
 void copy_matrix(hgv_ctx_s *ctx, int m, int n, const double2 *A, int lda, double2 *B, int ldb) {
     if (m <= 0 || n <= 0) return;
     hipLaunchKernelGGL(copy_kernel, dim3(cdiv(m, 64), cdiv(n, 4)), dim3(256), 0, ctx->stream, m, n, A, lda, B, ldb);
+    HGV_LAUNCH_CHECK();
+}
+
+void add_scaled(hgv_ctx_s *ctx, int m, int n, double alpha, const double2 *X, int ldx, double2 *Y, int ldy) {
+    if (m <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(add_scaled_kernel, dim3(cdiv(m, 64), cdiv(n, 4)), dim3(256), 0, ctx->stream, m, n, alpha, X,
+                       ldx, Y, ldy);
     HGV_LAUNCH_CHECK();
 }
 
