@@ -28,7 +28,9 @@
  *    Numerical failures are written to the device integer *d_info with the
  *    LAPACK xHEGV meaning (0 ok; k in [1,n]: the tridiagonal solver failed on
  *    eigenvalue k; n+k: the leading minor of order k of B is not positive
- *    definite).  d_info may be NULL.
+ *    definite).  d_info = 2n+2 reports that a bounded wait inside a
+ *    persistent kernel gave up (the device was held by other work for
+ *    seconds); the outputs are then not valid.  d_info may be NULL.
  *  - Only the lower triangles of A and B are read; their strict upper
  *    triangles may be overwritten (they are workspace).
  */

@@ -77,7 +77,7 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     const double N = n, M = m;
 
     if (tm) tm->begin(HGV_ST_HE2HB);
-    he2hb_run(ctx, n, nb, A, lda, T1, ar);
+    he2hb_run(ctx, n, nb, A, lda, T1, ar, d_info);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
 

@@ -819,6 +819,225 @@ __global__ __launch_bounds__(256, 2) void q2_reg_kernel(int n, int m, int b, int
     }
 }
 
+// Groups of g = 32 reflectors (band width 32 .. 64) on a pipelined schedule:
+// one persistent workgroup per CU and launch takes a contiguous run of the
+// launch's items (group, 64-column tile), group-major, so consecutive items
+// share the group's V (copied into LDS when the group changes) and T (held in
+// registers).  While item i is computed from registers, the rows of item i + 1
+// are copied into an LDS buffer by LDS-direct loads: the HBM traffic of the
+// next item overlaps the MFMAs of this one, and no operand read needs a mask.
+// V lives in LDS as a zero-padded parallelogram, Vd[t * VP + r] = V(r, t) for
+// the window rows r (zero outside rows t .. t + b - 1 and for reflectors past
+// the last sweep), with an odd pitch VP so that both operand patterns of a
+// 16-lane group (lanes stepping through reflectors, or through rows) hit
+// distinct bank groups; the row buffer keeps column c of the tile at
+// Yb[c * YP] with the same odd pitch.  The zero padding is written once per
+// workgroup; each group overwrites only its parallelogram.
+template <int BMAX> struct Q2F {
+    static constexpr int GM = 32, WR = GM + BMAX - 1, RQ = (WR + 3) / 4, VP = 4 * RQ + 1, YP = 4 * RQ + 1;
+};
+
+template <int BMAX>
+__device__ inline void q2f_zero(double2 *Vd) {
+    for (int e = threadIdx.x; e < 32 * Q2F<BMAX>::VP; e += 256) Vd[e] = make_double2(0.0, 0.0);
+}
+
+// LDS-direct copy of the reflectors of group (B, j): wave w copies reflectors
+// t = 8 w .. 8 w + 7 (lane i -> entry i); reflectors past the last sweep are zeroed
+template <int BMAX>
+__device__ inline void q2f_stage_v(double2 *Vd, const double2 *V2, int b, int J, int B, int j, int tmax) {
+    constexpr int VP = Q2F<BMAX>::VP;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int t = 8 * wave + u, s = B * 32 + t;
+        if (t < tmax) {
+            if (lane < b)
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(V2 + (((size_t)(s / b) * J + j) * b + s % b) * b +
+                                                                     lane),
+                    (__attribute__((address_space(3))) void *)(&Vd[t * VP + t]), 16, 0, 0);
+        } else if (lane < b) {
+            Vd[t * VP + t + lane] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
+// T operands of step 2 in registers: tr[tt][kq] = T(16 tt + lr, 4 kq + lk), or
+// T(4 kq + lk, 16 tt + lr) for Q2^H (conjugated in the product); T upper triangular
+template <int ADJ>
+__device__ inline void q2f_load_t(double2 (&tr)[2][8], const double2 *T2, int J, int B, int j) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const double2 *tg = T2 + ((size_t)B * J + j) * 32 * 32;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq)
+            if (ADJ ? kq <= 4 * tt + 3 : kq >= 4 * tt)
+                tr[tt][kq] = ADJ ? tg[4 * kq + lk + 32 * (16 * tt + lr)] : tg[16 * tt + lr + 32 * (4 * kq + lk)];
+}
+
+// Apply one group to the wave's 16 columns of Y_rows held in y (rows 4 q + lk
+// of the window, column lr): W = V^H Y_rows, W2 = T W (T^H W for Q2^H),
+// Y_rows -= V W2.  Rows at or past nrows must hold zeros.  emit(rt) is called
+// as soon as rows 16 rt .. 16 rt + 15 (y[4 rt .. 4 rt + 3]) are final, so
+// their stores drain while the remaining tiles are computed.
+template <int BMAX, int ADJ, class Emit>
+__device__ __attribute__((always_inline)) inline void q2f_apply(double2 (&y)[Q2F<BMAX>::RQ], const double2 *Vd,
+                                                                const double2 (&tr)[2][8], int nrows, Emit &&emit) {
+    typedef q2v4d Acc;
+    constexpr int GM = 32, RQ = Q2F<BMAX>::RQ, VP = Q2F<BMAX>::VP;
+    constexpr int QS = (15 + BMAX + 3) / 4;   // k-steps of one 16-reflector tile in step 1
+    const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+    const double2 *v1 = Vd + lr * VP + lk;   // V(4 q + lk, 16 tt + lr) = v1[16 tt VP + 4 q]
+    const double2 *v3 = Vd + lk * VP + lr;   // V(16 rt + lr, 4 kq + lk) = v3[4 kq VP + 16 rt]
+    auto mm = [](double a, double c, Acc acc) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, acc, 0, 0, 0); };
+    // step 1: W = V^H Y_rows.  With a = V unconjugated, sum conj(a) c =
+    // (P1 + P2) + i (P3 - P1 + P2) for P1 = sum ar cr, P2 = sum ai ci,
+    // P3 = sum (ar - ai)(cr + ci).
+    double2 w[2][4];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 4 * tt; q < 4 * tt + QS && q < RQ; ++q) {
+            const double2 a = v1[16 * tt * VP + 4 * q];
+            p1 = mm(a.x, y[q].x, p1);
+            p2 = mm(a.y, y[q].y, p2);
+            p3 = mm(a.x - a.y, y[q].x + y[q].y, p3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[tt][i] = make_double2(p1[i] + p2[i], p3[i] - p1[i] + p2[i]);
+    }
+    // step 2: W2 = T W (T upper triangular) or T^H W (lower)
+    double ws[8];
+#pragma unroll
+    for (int kq = 0; kq < 8; ++kq) ws[kq] = w[kq >> 2][kq & 3].x + w[kq >> 2][kq & 3].y;
+    double2 wn[8];   // -W2, the B operand of step 3
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq) {
+            if (ADJ ? kq > 4 * tt + 3 : kq < 4 * tt) continue;
+            const double2 a = tr[tt][kq];
+            const double2 c = w[kq >> 2][kq & 3];
+            p1 = mm(a.x, c.x, p1);
+            p2 = mm(a.y, c.y, p2);
+            p3 = mm(ADJ ? a.x - a.y : a.x + a.y, ws[kq], p3);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            wn[4 * tt + i] = ADJ ? make_double2(-(p1[i] + p2[i]), -(p3[i] - p1[i] + p2[i]))
+                                 : make_double2(p2[i] - p1[i], p1[i] + p2[i] - p3[i]);
+    }
+    double wns[8];
+#pragma unroll
+    for (int kq = 0; kq < 8; ++kq) wns[kq] = wn[kq].x + wn[kq].y;
+    // step 3: Y_rows += V (-W2), row tile rt accumulating into y[4 rt .. 4 rt + 3]
+#pragma unroll
+    for (int rt = 0; rt < RQ / 4; ++rt) {
+        if (16 * rt >= nrows) continue;
+        // reflectors whose rows meet the tile for band width BMAX (a superset
+        // for narrower bands, whose extra entries are zeros of the padding);
+        // the tile's V operands are read before its products
+        const int TLO = max(0, 16 * rt - BMAX + 1), THI = min(GM, 16 * rt + 16);
+        double2 av[8];
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq)
+            if (4 * kq + 3 >= TLO && 4 * kq < THI) av[kq] = v3[4 * kq * VP + 16 * rt];
+        Acc p1, p2 = {0, 0, 0, 0}, p3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            p1[i] = y[4 * rt + i].x;
+            p3[i] = y[4 * rt + i].x + y[4 * rt + i].y;
+        }
+#pragma unroll
+        for (int kq = 0; kq < 8; ++kq)
+            if (4 * kq + 3 >= TLO && 4 * kq < THI) {
+                const double2 a = av[kq];
+                p1 = mm(a.x, wn[kq].x, p1);
+                p2 = mm(a.y, wn[kq].y, p2);
+                p3 = mm(a.x + a.y, wns[kq], p3);
+            }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[4 * rt + i] = make_double2(p1[i] - p2[i], p3[i] - p1[i] - p2[i]);
+        emit(rt);
+    }
+}
+
+template <int BMAX, int ADJ>
+__global__ __launch_bounds__(256, 1) void q2_pipe_kernel(int n, int m, int b, int J, int Bt, int jlo, int ngs,
+                                                          const double2 *V2, const double2 *T2, double2 *Y,
+                                                          int ldy) {
+    constexpr int RQ = Q2F<BMAX>::RQ, YP = Q2F<BMAX>::YP, VP = Q2F<BMAX>::VP;
+    constexpr int YE = 64 * YP;   // elements of the row buffer (64 columns)
+    __shared__ double2 Vd[32 * VP];
+    __shared__ double2 Yb[YE];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int ct = (m + Q2R_NC - 1) / Q2R_NC, items = ngs * ct;
+    const int G = gridDim.x;                      // a multiple of 8
+    const int p = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+    const int per = (items + G - 1) / G;
+    const int i0 = p * per, i1 = min(items, i0 + per);
+    if (i0 >= i1) return;
+    q2f_zero<BMAX>(Vd);
+    // rows of item it into Yb; entries outside the matrix read row R0 of
+    // column c0 and are masked when the rows are taken into registers
+    auto fetch = [&](int it) {
+        const int j = jlo + it / ct, c0 = (it % ct) * Q2R_NC;
+        const int R0 = (Bt + j) * 32 + 1 + j * b;
+        const int nr = min(31 + b, n - R0);
+#pragma unroll
+        for (int u = 0; u < (YE + 255) / 256; ++u) {
+            if (256 * u + 64 * wave >= YE) continue;   // uniform within the wave
+            const int e = 256 * u + 64 * wave + lane, c = e / YP, r = e % YP;
+            const bool ok = r < nr && c0 + c < m;
+            const double2 *src = Y + (ok ? R0 + r + (size_t)(c0 + c) * ldy : R0 + (size_t)c0 * ldy);
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)(&Yb[256 * u + 64 * wave]),
+                                             16, 0, 0);
+        }
+    };
+    double2 tr[2][8];
+    int cur = -1;
+    fetch(i0);
+    for (int it = i0; it < i1; ++it) {
+        const int j = jlo + it / ct, c0 = (it % ct) * Q2R_NC;
+        const int B = Bt + j, s0 = B * 32;
+        const int R0 = s0 + 1 + j * b;
+        const int nrows = min(31 + b, n - R0);
+        if (j != cur) {
+            __syncthreads();   // the previous group's V is no longer read (first time: zero fill done)
+            q2f_stage_v<BMAX>(Vd, V2, b, J, B, j, min(32, n - 1 - s0));
+            q2f_load_t<ADJ>(tr, T2, J, B, j);
+            cur = j;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int cw = c0 + 16 * wave + lr;
+        const bool colok = cw < m;
+        double2 y[RQ];
+#pragma unroll
+        for (int q = 0; q < RQ; ++q) {
+            const double2 v = Yb[(16 * wave + lr) * YP + 4 * q + lk];
+            const bool in = colok && 4 * q + lk < nrows;
+            y[q] = make_double2(in ? v.x : 0.0, in ? v.y : 0.0);
+        }
+        __syncthreads();   // every wave holds its rows: the buffer may be refilled
+        if (it + 1 < i1) fetch(it + 1);
+        double2 *ycol = Y + (size_t)(colok ? cw : c0) * ldy + R0;
+        q2f_apply<BMAX, ADJ>(y, Vd, tr, nrows, [&](int rt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + 4 * i + lk;
+                if (colok && r < nrows) ycol[r] = y[4 * rt + i];
+            }
+        });
+    }
+}
+
 // reflectors per group (sweeps s0 .. s0 + g - 1 at one step j)
 static int q2_group(int b) { return std::min(b, 32); }
 
@@ -852,6 +1071,11 @@ void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, 
     // anti-diagonal w holds the groups B = ngrp - 1 - w + j with j in
     // [max(0, w - ngrp + 1), min(w, J - 1)] and j < jn(B); the valid j form a prefix
     const int nw = ngrp + J - 1, ct = cdiv(m, Q2WF_NC);
+    int pipe_grid = 0;   // one workgroup per CU (a multiple of 8) for the pipelined kernel
+    if (std::is_same<E, double2>::value && g == 32) {
+        HGV_HIP(hipDeviceGetAttribute(&pipe_grid, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        pipe_grid = std::max(8, pipe_grid / 8 * 8);
+    }
     for (int wi = 0; wi < nw; ++wi) {
         const int w = adj ? nw - 1 - wi : wi;
         const int Bt = ngrp - 1 - w;
@@ -866,12 +1090,20 @@ void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, 
         const int ngs = jhi - jlo + 1;
         if constexpr (std::is_same<E, double2>::value) {
             const int grid = 8 * cdiv(ngs * cdiv(m, Q2R_NC), 8);
-            if (b <= 32)
+            if (g == 32) {
+                int n_ = n, m_ = m, b_ = b, J_ = J, Bt_ = Bt, jlo_ = jlo, ngs_ = ngs, ldy_ = ldy;
+                const double2 *V2_ = V2, *T2_ = T2;
+                double2 *Y_ = Y;
+                void *args[] = {&n_, &m_, &b_, &J_, &Bt_, &jlo_, &ngs_, &V2_, &T2_, &Y_, &ldy_};
+                void *kern = b <= 32 ? (adj ? reinterpret_cast<void *>(q2_pipe_kernel<32, 1>)
+                                            : reinterpret_cast<void *>(q2_pipe_kernel<32, 0>))
+                                     : (adj ? reinterpret_cast<void *>(q2_pipe_kernel<64, 1>)
+                                            : reinterpret_cast<void *>(q2_pipe_kernel<64, 0>));
+                HGV_HIP(hipLaunchKernel(kern, dim3(pipe_grid), dim3(256), args, 0, ctx->stream));
+            } else {
                 hipLaunchKernelGGL((q2_reg_kernel<32>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
                                    jlo, ngs, (int)adj, V2, T2, Y, ldy);
-            else
-                hipLaunchKernelGGL((q2_reg_kernel<64>), dim3(grid), dim3(256), 0, ctx->stream, n, m, b, g, J, Bt,
-                                   jlo, ngs, (int)adj, V2, T2, Y, ldy);
+            }
         } else {
             const int grid = 8 * cdiv(ngs * ct, 8);
             if (b <= 32)

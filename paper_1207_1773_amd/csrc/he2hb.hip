@@ -399,7 +399,7 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
 }
 
 template <class E>
-void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
+void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int *d_info) {
     typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
@@ -479,6 +479,7 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar) {
         g.lower = 1;
         gemm_any(ctx, g, ws, wsb);
     }
+    if (capacity > 0) report_wait_fail(ctx, flags + Gmax, d_info, 2 * n + 2);
 }
 
 // Copy the r x r upper-triangular T (ld nb) into the diagonal block of T_big.
@@ -597,8 +598,8 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
     }
 }
 
-template void he2hb_t<double2>(hgv_ctx_s *, int, int, double2 *, int, double2 *, Arena &);
-template void he2hb_t<float2>(hgv_ctx_s *, int, int, float2 *, int, float2 *, Arena &);
+template void he2hb_t<double2>(hgv_ctx_s *, int, int, double2 *, int, double2 *, Arena &, int *);
+template void he2hb_t<float2>(hgv_ctx_s *, int, int, float2 *, int, float2 *, Arena &, int *);
 template void unmtr_q1_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, int, const double2 *, double2 *, int,
                                   bool, Arena &);
 template void unmtr_q1_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, int, const float2 *, float2 *, int, bool,

@@ -190,6 +190,8 @@ void copy_matrix(hgv_ctx_s *ctx, int m, int n, const double2 *A, int lda, double
 // Y += alpha X (m x n, alpha real)
 void add_scaled(hgv_ctx_s *ctx, int m, int n, double alpha, const double2 *X, int ldx, double2 *Y, int ldy);
 void set_info(hgv_ctx_s *ctx, int *d_info, int value);
+// *d_info = code if *err != 0 and *d_info == 0 (device words; d_info may be null)
+void report_wait_fail(hgv_ctx_s *ctx, const int *err, int *d_info, int code);
 
 // ---- stages ----------------------------------------------------------------------
 // Every stage has a plan (arena-driven size) and a run with the same arena.
@@ -204,8 +206,10 @@ void trsm_right_lc(hgv_ctx_s *ctx, int m, int n, const double2 *L, int ldl, doub
 void trsm_left_ln(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
 void trsm_left_lc(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
 
+// d_info (device, may be null) receives 2n+2 if a bounded wait of a
+// persistent kernel gave up (the result is then not valid)
 template <class E>
-void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar);
+void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int *d_info = nullptr);
 // Y <- Q1 Y (adj = false) or Y <- Q1^H Y (adj = true)
 template <class E>
 void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
@@ -223,8 +227,9 @@ template <class E>
 void q2_build_t(hgv_ctx_s *ctx, int n, int nb, const E *V2, const E *tau2, E *T2);
 template <class E>
 void q2_apply_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *T2, E *Y, int ldy, bool adj);
-inline void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar) {
-    he2hb_t<double2>(ctx, n, nb, A, lda, T1, ar);
+inline void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double2 *T1, Arena &ar,
+                      int *d_info = nullptr) {
+    he2hb_t<double2>(ctx, n, nb, A, lda, T1, ar, d_info);
 }
 inline void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e,
                       double2 *V2, double2 *tau2, Arena &ar) {

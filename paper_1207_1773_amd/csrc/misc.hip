@@ -65,4 +65,14 @@ void set_info(hgv_ctx_s *ctx, int *d_info, int value) {
     HGV_LAUNCH_CHECK();
 }
 
+__global__ void wait_fail_kernel(const int *err, int *d_info, int code) {
+    if (*err != 0 && *d_info == 0) *d_info = code;
+}
+
+void report_wait_fail(hgv_ctx_s *ctx, const int *err, int *d_info, int code) {
+    if (!d_info) return;
+    hipLaunchKernelGGL(wait_fail_kernel, dim3(1), dim3(1), 0, ctx->stream, err, d_info, code);
+    HGV_LAUNCH_CHECK();
+}
+
 }  // namespace hgv

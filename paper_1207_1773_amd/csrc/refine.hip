@@ -258,7 +258,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
         HGV_LAUNCH_CHECK();
     }
     if (tm) tm->begin(HGV_ST_HE2HB);
-    he2hb_t<float2>(ctx, n, nb, Ac, n, T1c, ar);
+    he2hb_t<float2>(ctx, n, nb, Ac, n, T1c, ar, d_info);
     ar.release(mk1);
     if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
 
