@@ -864,7 +864,8 @@ __device__ inline void q2f_stage_v(double2 *Vd, const double2 *V2, int b, int J,
 }
 
 // T operands of step 2 in registers: tr[tt][kq] = T(16 tt + lr, 4 kq + lk), or
-// T(4 kq + lk, 16 tt + lr) for Q2^H (conjugated in the product); T upper triangular
+// T(4 kq + lk, 16 tt + lr) for Q2^H (conjugated in the product); T upper
+// triangular.  tget(tt, kq) in q2f_apply returns the same operand.
 template <int ADJ>
 __device__ inline void q2f_load_t(double2 (&tr)[2][8], const double2 *T2, int J, int B, int j) {
     const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
@@ -882,9 +883,9 @@ __device__ inline void q2f_load_t(double2 (&tr)[2][8], const double2 *T2, int J,
 // Y_rows -= V W2.  Rows at or past nrows must hold zeros.  emit(rt) is called
 // as soon as rows 16 rt .. 16 rt + 15 (y[4 rt .. 4 rt + 3]) are final, so
 // their stores drain while the remaining tiles are computed.
-template <int BMAX, int ADJ, class Emit>
+template <int BMAX, int ADJ, class TGet, class Emit>
 __device__ __attribute__((always_inline)) inline void q2f_apply(double2 (&y)[Q2F<BMAX>::RQ], const double2 *Vd,
-                                                                const double2 (&tr)[2][8], int nrows, Emit &&emit) {
+                                                                TGet &&tget, int nrows, Emit &&emit) {
     typedef q2v4d Acc;
     constexpr int GM = 32, RQ = Q2F<BMAX>::RQ, VP = Q2F<BMAX>::VP;
     constexpr int QS = (15 + BMAX + 3) / 4;   // k-steps of one 16-reflector tile in step 1
@@ -899,9 +900,12 @@ __device__ __attribute__((always_inline)) inline void q2f_apply(double2 (&y)[Q2F
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
         Acc p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
+        double2 av[QS];   // the tile's V operands, read before its products
+#pragma unroll
+        for (int q = 4 * tt; q < 4 * tt + QS && q < RQ; ++q) av[q - 4 * tt] = v1[16 * tt * VP + 4 * q];
 #pragma unroll
         for (int q = 4 * tt; q < 4 * tt + QS && q < RQ; ++q) {
-            const double2 a = v1[16 * tt * VP + 4 * q];
+            const double2 a = av[q - 4 * tt];
             p1 = mm(a.x, y[q].x, p1);
             p2 = mm(a.y, y[q].y, p2);
             p3 = mm(a.x - a.y, y[q].x + y[q].y, p3);
@@ -920,7 +924,7 @@ __device__ __attribute__((always_inline)) inline void q2f_apply(double2 (&y)[Q2F
 #pragma unroll
         for (int kq = 0; kq < 8; ++kq) {
             if (ADJ ? kq > 4 * tt + 3 : kq < 4 * tt) continue;
-            const double2 a = tr[tt][kq];
+            const double2 a = tget(tt, kq);
             const double2 c = w[kq >> 2][kq & 3];
             p1 = mm(a.x, c.x, p1);
             p2 = mm(a.y, c.y, p2);
@@ -1028,7 +1032,7 @@ __global__ __launch_bounds__(256, 1) void q2_pipe_kernel(int n, int m, int b, in
         __syncthreads();   // every wave holds its rows: the buffer may be refilled
         if (it + 1 < i1) fetch(it + 1);
         double2 *ycol = Y + (size_t)(colok ? cw : c0) * ldy + R0;
-        q2f_apply<BMAX, ADJ>(y, Vd, tr, nrows, [&](int rt) {
+        q2f_apply<BMAX, ADJ>(y, Vd, [&](int tt, int kq) { return tr[tt][kq]; }, nrows, [&](int rt) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 16 * rt + 4 * i + lk;
