@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--mixed-fractions", type=str, default="0.1,0.25,1.0",
                     help="fractions also solved in mixed precision (side by side with FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured FP64 MFMA / copy peaks")
     ap.add_argument("--cpu-n", type=int, default=2560)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this size 5 times and exit (HBM counter calibration)")
@@ -197,6 +198,18 @@ def main():
             rec["speedup_vs_fp64"] = base["s"] / rec["s"]
         mixed[key] = rec
 
+    # roofline denominators measured on this device (after the timed steps)
+    peaks = None
+    if not args.no_peaks:
+        wb = 2 << 30
+        w = torch.empty(wb, dtype=torch.uint8, device=dev)
+        ptf, pgbs = hgv.hgv_device_peaks(ctx.handle, w.data_ptr(), wb)
+        del w
+        peaks = {"fp64_mfma_tflops": ptf, "copy_gbs": pgbs, "published_fp64_mfma_tflops": PEAK_FP64_TFLOPS,
+                 "published_hbm_gbs": 8000.0,
+                 "method": "hgv_device_peaks: v_mfma_f64_16x16x4f64 chains with no memory traffic (16 waves/CU); "
+                           "16-byte copy of 1 GiB to 1 GiB, bytes read + written"}
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -250,7 +263,10 @@ def main():
                                "of a step; split-K reductions excluded)",
                      "launches_per_step": gemm_launches / args.steps,
                      "avg_launch_ms": gemm_avg_ms,
-                     "gemm_share_of_step": (gemm_ms / args.steps) / ms_per_step},
+                     "gemm_share_of_step": (gemm_ms / args.steps) / ms_per_step,
+                     "peak_measured": peaks["fp64_mfma_tflops"] if peaks else None,
+                     "frac_of_measured": (achieved / peaks["fp64_mfma_tflops"]) if (peaks and achieved) else None},
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "wall_s_timed": wall,
         "input_generation_s": t_gen,

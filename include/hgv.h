@@ -237,6 +237,20 @@ int hgv_zhegvx_backward(hgv_ctx_t ctx, int n, int il, int iu, const double *lamb
                         int ldxa, const double *Wbar, const hgv_c128 *Xbar, int ldxb, hgv_c128 *Abar, int ldab,
                         hgv_c128 *Bbar, int ldbb, void *work, size_t work_bytes);
 
+/* ---- diagnostics ------------------------------------------------------------ */
+/* Measures, on the context's device, the FP64 MFMA rate in TFLOP/s
+ * (independent v_mfma_f64_16x16x4f64 chains with no memory traffic, 16 waves
+ * per CU) and the copy bandwidth in GB/s (bytes read plus bytes written by
+ * 16-byte loads and stores): the denominators of the roofline fractions,
+ * measured next to the published peaks.  work: device buffer, 256-byte
+ * aligned, work_bytes >= 4 MiB; the copy runs over all but its first few MiB
+ * (half source, half destination), so pass well over the 256 MB on-package
+ * cache (e.g. 2 GiB) to measure HBM.  The contents of work are overwritten.
+ * Synchronizes the stream; results are host doubles.  HGV_E_WORKSPACE if
+ * work_bytes is too small.  Argument numbers for -i: ctx 1, work 2,
+ * work_bytes 3, fp64_mfma_tflops 4, copy_gbs 5. */
+int hgv_device_peaks(hgv_ctx_t ctx, void *work, size_t work_bytes, double *fp64_mfma_tflops, double *copy_gbs);
+
 /* ---- building block -------------------------------------------------------- */
 /* C <- alpha op(A) op(B) + beta C on the MFMA tiles the stages use.
  * opa/opb: 'N', 'T' (transpose) or 'C' (conjugate transpose).  C is m x n,

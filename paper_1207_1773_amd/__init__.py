@@ -28,7 +28,7 @@ EXPORTS = [
     "hgv_create", "hgv_destroy", "hgv_set_stream", "hgv_status_string", "hgv_last_hip_error",
     "hgv_default_nb", "hgv_zhegvx_bufsize", "hgv_zhegvx", "hgv_stage_bufsize", "hgv_zpotrf",
     "hgv_zhegst", "hgv_zhe2hb", "hgv_zhb2st", "hgv_v2_elems", "hgv_v2_taus", "hgv_dstedc",
-    "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_gauge_fix",
+    "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_device_peaks", "hgv_gauge_fix",
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
 ]
 
@@ -101,6 +101,7 @@ def load():
         "hgv_zunmtr_q1": (I, [P, ctypes.c_char, I, I, I, P, I, P, P, I, P, SZ]),
         "hgv_ztrsm_lh": (I, [P, I, I, P, I, P, I, P, SZ]),
         "hgv_zgemm": (I, [P, ctypes.c_char, ctypes.c_char, I, I, I, c128, P, I, P, I, c128, P, I]),
+        "hgv_device_peaks": (I, [P, P, SZ, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         "hgv_gauge_fix": (I, [P, I, I, P, I]),
         "hgv_zhegvx_backward_bufsize": (I, [P, I, I, I, ctypes.POINTER(SZ)]),
         "hgv_zhegvx_backward": (I, [P, I, I, I, P, P, I, P, P, I, P, I, P, I, P, SZ]),
@@ -213,6 +214,14 @@ def hgv_zgemm(ctx, opa, opb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc):
     a = c128(alpha.real, alpha.imag)
     b = c128(beta.real, beta.imag)
     _check(load().hgv_zgemm(ctx, opa.encode(), opb.encode(), m, n, k, a, A, lda, B, ldb, b, C, ldc), "hgv_zgemm")
+
+
+def hgv_device_peaks(ctx, work, work_bytes):
+    """Measured FP64 MFMA TFLOP/s and copy GB/s (read + write) of the context's device."""
+    t = ctypes.c_double(0.0)
+    g = ctypes.c_double(0.0)
+    _check(load().hgv_device_peaks(ctx, work, work_bytes, ctypes.byref(t), ctypes.byref(g)), "hgv_device_peaks")
+    return t.value, g.value
 
 
 def hgv_gauge_fix(ctx, n, m, X, ldx):

@@ -483,6 +483,17 @@ int hgv_ztrsm_lh(hgv_ctx_t ctx, int n, int m, const hgv_c128 *L, int ldl, hgv_c1
     });
 }
 
+int hgv_device_peaks(hgv_ctx_t ctx, void *work, size_t work_bytes, double *fp64_mfma_tflops, double *copy_gbs) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -2;
+    if (!fp64_mfma_tflops) return -4;
+    if (!copy_gbs) return -5;
+    return guarded(ctx, [&]() {
+        device_peaks(ctx, work, work_bytes, fp64_mfma_tflops, copy_gbs);
+        return HGV_OK;
+    });
+}
+
 int hgv_zgemm(hgv_ctx_t ctx, char opa, char opb, int m, int n, int k, hgv_c128 alpha, const hgv_c128 *A, int lda,
               const hgv_c128 *B, int ldb, hgv_c128 beta, hgv_c128 *C, int ldc) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;

@@ -190,6 +190,9 @@ void copy_matrix(hgv_ctx_s *ctx, int m, int n, const double2 *A, int lda, double
 // Y += alpha X (m x n, alpha real)
 void add_scaled(hgv_ctx_s *ctx, int m, int n, double alpha, const double2 *X, int ldx, double2 *Y, int ldy);
 void set_info(hgv_ctx_s *ctx, int *d_info, int value);
+// measured FP64 MFMA rate (TFLOP/s) and copy bandwidth (GB/s, read + write)
+// of the context's device; work: device buffer, the copy uses most of it
+void device_peaks(hgv_ctx_s *ctx, void *work, size_t work_bytes, double *tflops, double *gbs);
 // *d_info = code if *err != 0 and *d_info == 0 (device words; d_info may be null)
 void report_wait_fail(hgv_ctx_s *ctx, const int *err, int *d_info, int code);
 

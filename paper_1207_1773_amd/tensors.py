@@ -14,7 +14,7 @@ from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HG
                HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
                hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
                hgv_zhegst, hgv_zhegvx, hgv_zhegvx_batched, hgv_zhegvx_batched_bufsize, hgv_zhegvx_bufsize,
-               hgv_zpotrf, hgv_ztrsm_lh, hgv_zunmtr_q1, hgv_zunmtr_q2, load)
+               hgv_zpotrf, hgv_ztrsm_lh, hgv_zunmtr_q1, hgv_zunmtr_q2, hgv_device_peaks, load)
 
 
 def colmajor(M, dtype=torch.complex128):
@@ -154,6 +154,12 @@ class Context:
         hgv_zunmtr_q1(self.handle, "C" if adj else "N", n, nb, m, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(Yc), max(n, 1),
                       _ptr(w), w.numel())
         return from_colmajor(Yc)
+
+    def device_peaks(self, nbytes=1 << 30):
+        """Measured (FP64 MFMA TFLOP/s, copy GB/s read + write) of this device; nbytes of scratch."""
+        self._sync_stream()
+        w = self._work(nbytes)
+        return hgv_device_peaks(self.handle, _ptr(w), w.numel())
 
     def trsm_lh(self, L, X):
         """Alg. 1 step 4: L^-H X."""
