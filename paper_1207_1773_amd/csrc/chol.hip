@@ -25,27 +25,30 @@ static int split_point(int n) {
 }
 
 // Inverse of the lower-triangular sz x sz block held in S (LDS) into Inv (LDS),
-// 256 threads: column c (independent of the others) solves L x = e_c by
-// forward substitution; the four lanes 4c .. 4c+3 of a wave share a column
-// and split every inner product, combined with two butterfly shuffles.
+// NT threads: column c (independent of the others) solves L x = e_c by
+// forward substitution; the QN = NT / 64 consecutive lanes of a column share
+// it and split every inner product, combined with butterfly shuffles.  The
+// diagonal of L is real (a Cholesky factor), so the division is a scaling.
+template <int NT>
 __device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LEAF + 1], int sz, int tid) {
-    const int c = tid >> 2, q = tid & 3;
+    constexpr int QN = NT / 64;
+    const int c = tid / QN, q = tid % QN;
     for (int i = 0; i < LEAF; ++i) {
         if (i < c || i >= sz || c >= sz) {
             Inv[i][c] = make_double2(0.0, 0.0);
             continue;
         }
         double2 s = make_double2(0.0, 0.0);
-        for (int k = c + q; k < i; k += 4) s = zadd(s, zmul(S[i][k], Inv[k][c]));
+        for (int k = c + q; k < i; k += QN) s = zadd(s, zmul(S[i][k], Inv[k][c]));
 #pragma unroll
-        for (int o = 1; o < 4; o <<= 1) {
+        for (int o = 1; o < QN; o <<= 1) {
             s.x += __shfl_xor(s.x, o, 64);
             s.y += __shfl_xor(s.y, o, 64);
         }
         const double2 rhs = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
-        // the butterfly leaves the same sum in the four lanes, so each lane
+        // the butterfly leaves the same sum in the QN lanes, so each lane
         // stores the (identical) value and later reads only what it stored
-        Inv[i][c] = zdiv(zsub(rhs, s), S[i][i]);
+        Inv[i][c] = zscale(1.0 / S[i][i].x, zsub(rhs, s));
     }
 }
 
@@ -53,14 +56,18 @@ __device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LE
 // Right-looking unblocked Cholesky of the lower triangle held in LDS.  A
 // non-positive (or NaN) pivot at local column j records info = base + j + 1
 // (first failure wins) and stops the factorisation of this block.  The
-// inverse of the factor is written to Linv (64 x 64, column-major).
-__global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, int *info, int base,
-                                                    double2 *Linv) {
+// inverse of the factor is written to Linv (64 x 64, column-major).  The work
+// is a chain of 64 dependent column steps of short arithmetic, so the kernel
+// runs NT = 1024 threads (four waves per SIMD keep the dependent instructions
+// of one another overlapped).
+template <int NT>
+__global__ __launch_bounds__(NT) void potf2_kernel(int n, double2 *A, int lda, int *info, int base,
+                                                   double2 *Linv) {
     __shared__ double2 S[LEAF][LEAF + 1];
     __shared__ double2 Iv[LEAF][LEAF + 1];
     __shared__ int fail;
     const int tid = threadIdx.x;
-    for (int t = tid; t < LEAF * LEAF; t += 256) {
+    for (int t = tid; t < LEAF * LEAF; t += NT) {
         int i = t % LEAF, j = t / LEAF;
         S[i][j] = (i < n && j < n && i >= j) ? A[i + (size_t)j * lda] : make_double2(0.0, 0.0);
     }
@@ -79,10 +86,10 @@ __global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, 
         __syncthreads();
         if (fail) break;
         double inv = 1.0 / S[j][j].x;
-        for (int i = j + 1 + tid; i < n; i += 256) S[i][j] = zscale(inv, S[i][j]);
+        for (int i = j + 1 + tid; i < n; i += NT) S[i][j] = zscale(inv, S[i][j]);
         __syncthreads();
         int m = n - j - 1;
-        for (int t = tid; t < m * m; t += 256) {
+        for (int t = tid; t < m * m; t += NT) {
             int i = j + 1 + t % m, k = j + 1 + t / m;
             if (i >= k) {
                 double2 a = S[i][j], b = S[k][j];
@@ -92,51 +99,55 @@ __global__ __launch_bounds__(256) void potf2_kernel(int n, double2 *A, int lda, 
         }
         __syncthreads();
     }
-    for (int t = tid; t < n * n; t += 256) {
+    for (int t = tid; t < n * n; t += NT) {
         int i = t % n, j = t / n;
         if (i >= j) A[i + (size_t)j * lda] = S[i][j];
     }
     if (Linv) {
         if (fail) {   // keep the solves finite; the result is flagged through info
-            for (int t = tid; t < LEAF * LEAF; t += 256) {
+            for (int t = tid; t < LEAF * LEAF; t += NT) {
                 int i = t % LEAF, j = t / LEAF;
                 S[i][j] = (i == j) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
             }
             __syncthreads();
         }
-        tri_inverse_lds(S, Iv, n, tid);
+        tri_inverse_lds<NT>(S, Iv, n, tid);
         __syncthreads();
-        for (int t = tid; t < LEAF * LEAF; t += 256) Linv[t] = Iv[t % LEAF][t / LEAF];
+        for (int t = tid; t < LEAF * LEAF; t += NT) Linv[t] = Iv[t % LEAF][t / LEAF];
     }
 }
 
 // Inverse of every 64 x 64 diagonal block of the lower-triangular L.
-__global__ __launch_bounds__(256) void trtri_diag_kernel(int n, const double2 *L, int ldl, double2 *Linv) {
+template <int NT>
+__global__ __launch_bounds__(NT) void trtri_diag_kernel(int n, const double2 *L, int ldl, double2 *Linv) {
     __shared__ double2 S[LEAF][LEAF + 1];
     __shared__ double2 Iv[LEAF][LEAF + 1];
     const int blk = blockIdx.x, tid = threadIdx.x;
     const int o = blk * LEAF, sz = min(LEAF, n - o);
-    for (int t = tid; t < LEAF * LEAF; t += 256) {
+    for (int t = tid; t < LEAF * LEAF; t += NT) {
         int i = t % LEAF, j = t / LEAF;
         S[i][j] = (i < sz && j < sz && i >= j) ? L[(o + i) + (size_t)(o + j) * ldl] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    tri_inverse_lds(S, Iv, sz, tid);
+    tri_inverse_lds<NT>(S, Iv, sz, tid);
     __syncthreads();
     double2 *out = Linv + (size_t)blk * LEAF * LEAF;
-    for (int t = tid; t < LEAF * LEAF; t += 256) out[t] = Iv[t % LEAF][t / LEAF];
+    for (int t = tid; t < LEAF * LEAF; t += NT) out[t] = Iv[t % LEAF][t / LEAF];
 }
 
 // ---- leaf reduction to standard form (n <= 64), one workgroup ---------------------
 // C = L^-1 A L^-H for the block with the block's inverse Li = L^-1 (64 x 64,
 // column-major, zero outside the n x n triangle): W = Li A (A full Hermitian
 // from its lower triangle), C = W Li^H; the lower triangle of (C + C^H)/2 is
-// written.  256 threads, each owning 16 elements of the product.
-__global__ __launch_bounds__(256) void hegs2_kernel(int n, double2 *A, int lda, const double2 *Li) {
+// written.  NT threads, each owning 4096 / NT elements of the product (NT =
+// 1024: four waves per SIMD overlap the dependent multiply-add chains).
+template <int NT>
+__global__ __launch_bounds__(NT) void hegs2_kernel(int n, double2 *A, int lda, const double2 *Li) {
+    constexpr int CS = NT / 64, U = LEAF / CS;   // column stride and columns per thread
     __shared__ double2 Ls[LEAF][LEAF + 1];
     __shared__ double2 As[LEAF][LEAF + 1];
     const int tid = threadIdx.x;
-    for (int t = tid; t < LEAF * LEAF; t += 256) {
+    for (int t = tid; t < LEAF * LEAF; t += NT) {
         int i = t % LEAF, j = t / LEAF;
         Ls[i][j] = (i < n && j < n) ? Li[i + (size_t)j * LEAF] : make_double2(0.0, 0.0);
         double2 a = make_double2(0.0, 0.0);
@@ -148,34 +159,34 @@ __global__ __launch_bounds__(256) void hegs2_kernel(int n, double2 *A, int lda, 
         As[i][j] = a;
     }
     __syncthreads();
-    // thread -> row r = tid % 64, columns c = tid / 64 + 4 u (u = 0..15)
+    // thread -> row r = tid % 64, columns c = tid / 64 + CS u (u = 0 .. U-1)
     const int r = tid & 63, c0 = tid >> 6;
-    double2 acc[16];
+    double2 acc[U];
     // W = Li A  (Li lower triangular: k <= r)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = make_double2(0.0, 0.0);
+    for (int u = 0; u < U; ++u) acc[u] = make_double2(0.0, 0.0);
     for (int k = 0; k <= r && k < n; ++k) {
         const double2 l = Ls[r][k];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) zfma(acc[u], l, As[k][c0 + 4 * u]);
+        for (int u = 0; u < U; ++u) zfma(acc[u], l, As[k][c0 + CS * u]);
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) As[r][c0 + 4 * u] = acc[u];
+    for (int u = 0; u < U; ++u) As[r][c0 + CS * u] = acc[u];
     __syncthreads();
     // C = W Li^H:  C[r][c] = sum_k W[r][k] conj(Li[c][k]),  k <= c
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        const int c = c0 + 4 * u;
+    for (int u = 0; u < U; ++u) {
+        const int c = c0 + CS * u;
         double2 s2 = make_double2(0.0, 0.0);
         for (int k = 0; k <= c && k < n; ++k) zfma(s2, As[r][k], zconj(Ls[c][k]));
         acc[u] = s2;
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) As[r][c0 + 4 * u] = acc[u];
+    for (int u = 0; u < U; ++u) As[r][c0 + CS * u] = acc[u];
     __syncthreads();
-    for (int t = tid; t < n * n; t += 256) {
+    for (int t = tid; t < n * n; t += NT) {
         int i = t % n, j = t / n;
         if (i > j) A[i + (size_t)j * lda] = zscale(0.5, zadd(As[i][j], zconj(As[j][i])));
         else if (i == j) A[i + (size_t)i * lda] = make_double2(As[i][i].x, 0.0);
@@ -294,7 +305,7 @@ static TriCtx tri_scratch(hgv_ctx_s *ctx, Arena &ar, int n, double2 **Linv) {
 
 static void invert_diag_blocks(hgv_ctx_s *ctx, int n, const double2 *L, int ldl, double2 *Linv) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(trtri_diag_kernel, dim3(cdiv(n, LEAF)), dim3(256), 0, ctx->stream, n, L, ldl, Linv);
+    hipLaunchKernelGGL(trtri_diag_kernel<1024>, dim3(cdiv(n, LEAF)), dim3(1024), 0, ctx->stream, n, L, ldl, Linv);
     HGV_LAUNCH_CHECK();
 }
 
@@ -326,7 +337,7 @@ void trsm_lh_run(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double
 static void potrf_rec(const TriCtx &t, int n, double2 *A, int lda, int *info, int base, double2 *Linv) {
     if (n <= 0) return;
     if (n <= LEAF) {
-        hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(256), 0, t.ctx->stream, n, A, lda, info, base, Linv);
+        hipLaunchKernelGGL(potf2_kernel<1024>, dim3(1), dim3(1024), 0, t.ctx->stream, n, A, lda, info, base, Linv);
         HGV_LAUNCH_CHECK();
         return;
     }
@@ -354,7 +365,7 @@ void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_inf
 static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2 *L, int ldl, const double2 *Linv) {
     if (n <= 0) return;
     if (n <= LEAF) {
-        hipLaunchKernelGGL(hegs2_kernel, dim3(1), dim3(256), 0, t.ctx->stream, n, A, lda, Linv);
+        hipLaunchKernelGGL(hegs2_kernel<1024>, dim3(1), dim3(1024), 0, t.ctx->stream, n, A, lda, Linv);
         HGV_LAUNCH_CHECK();
         return;
     }

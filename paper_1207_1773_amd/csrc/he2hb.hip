@@ -294,30 +294,33 @@ __global__ void extract_v_kernel(int N, int r, const E *P, int ldp, E *V, int ld
 }
 
 // T (r x r upper, ldt) from tau and G = V^H V:  T_jj = tau_j,
-// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One workgroup of 256 threads,
-// column by column; G is staged in LDS and the four lanes 4i .. 4i+3 share
-// row i of each triangular matrix-vector product (butterfly-combined).
-template <class E>
-__global__ __launch_bounds__(256) void build_t_kernel(int r, const double2 *tau, const E *G, int ldg, E *T, int ldt) {
+// T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].  One workgroup of NT threads,
+// column by column; G is staged in LDS and the QN = NT / 64 consecutive lanes
+// of row i share the row's triangular matrix-vector product (butterfly-
+// combined).  The columns form a chain of short dependent steps, so NT = 1024
+// (four waves per SIMD, a quarter of the chain per lane).
+template <class E, int NT>
+__global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, const E *G, int ldg, E *T, int ldt) {
+    constexpr int QN = NT / 64;
     __shared__ double2 Ts[PNB][PNB + 1];
     __shared__ double2 Gs[PNB][PNB + 1];
     __shared__ double2 taus[PNB];
     const int tid = threadIdx.x;
-    for (int t = tid; t < PNB * PNB; t += 256) {
+    for (int t = tid; t < PNB * PNB; t += NT) {
         const int i = t % PNB, j = t / PNB;
         Ts[i][j] = make_double2(0.0, 0.0);
         Gs[i][j] = (i < r && j < r) ? El<E>::to(G[i + (size_t)j * ldg]) : make_double2(0.0, 0.0);
     }
     if (tid < PNB) taus[tid] = (tid < r) ? tau[tid] : make_double2(0.0, 0.0);
     __syncthreads();
-    const int row = tid >> 2, q = tid & 3;
+    const int row = tid / QN, q = tid % QN;
     for (int j = 0; j < r; ++j) {
         const double2 tj = taus[j];
         if (row < j) {
             double2 acc = make_double2(0.0, 0.0);
-            for (int l = row + q; l < j; l += 4) acc = zadd(acc, zmul(Ts[row][l], Gs[l][j]));
+            for (int l = row + q; l < j; l += QN) acc = zadd(acc, zmul(Ts[row][l], Gs[l][j]));
 #pragma unroll
-            for (int o = 1; o < 4; o <<= 1) {
+            for (int o = 1; o < QN; o <<= 1) {
                 acc.x += __shfl_xor(acc.x, o, 64);
                 acc.y += __shfl_xor(acc.y, o, 64);
             }
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(256) void build_t_kernel(int r, const double2 *tau,
         if (tid == 0) Ts[j][j] = tj;
         __syncthreads();
     }
-    for (int t = tid; t < r * r; t += 256) T[t % r + (size_t)(t / r) * ldt] = El<E>::from(Ts[t % r][t / r]);
+    for (int t = tid; t < r * r; t += NT) T[t % r + (size_t)(t / r) * ldt] = El<E>::from(Ts[t % r][t / r]);
 }
 
 template <class E>
@@ -394,7 +397,7 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
     gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
     gg.C = Gm; gg.ldc = r;
     gemm_any(ctx, gg, ws, wsb);
-    hipLaunchKernelGGL(build_t_kernel<E>, dim3(1), dim3(256), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    hipLaunchKernelGGL((build_t_kernel<E, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt);
     HGV_LAUNCH_CHECK();
 }
 
