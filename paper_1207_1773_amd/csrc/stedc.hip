@@ -195,65 +195,122 @@ __global__ void dc_m1_kernel(DcArgs A) {
     A.perm[m.a + rank] = x;
 }
 
-// M2: normalise u, deflation scan (serial per merge, in sorted order).
-__global__ void dc_m2_kernel(DcArgs A) {
-    int p = blockIdx.x;
-    if (threadIdx.x != 0) return;
-    MergeGeom m = merge_geom(A.n, A.L, p);
+// M2: normalise u, deflation scan.  The norm of z and the largest |d| are
+// reduced by the workgroup (a fixed-order tree, the same in every run); the
+// scan itself is serial in sorted order: thread 0 walks chunks of the merge
+// that the workgroup has copied into LDS (z already scaled), so that its
+// loads are LDS reads and its global stores never wait for them.  The scan
+// changes only the entries at `prev` and `i`; the current values of `prev`
+// stay in registers, and a `prev` left behind in an earlier chunk is written
+// back to global memory directly.
+constexpr int M2CH = 2048;
+
+__global__ __launch_bounds__(256) void dc_m2_kernel(DcArgs A) {
+    __shared__ double sd[M2CH], sz[M2CH];
+    __shared__ double rs[256], rm[256];
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const MergeGeom m = merge_geom(A.n, A.L, p);
     if (m.n2 <= 0) return;
     double *ds = A.ds + m.a, *zs = A.zs + m.a;
     double nz2 = 0.0, dmax = 0.0;
-    for (int i = 0; i < m.k; ++i) {
+    for (int i = tid; i < m.k; i += 256) {
         nz2 += zs[i] * zs[i];
         dmax = fmax(dmax, fabs(ds[i]));
     }
-    double rho = fabs(A.e[m.a + m.n1 - 1]);
-    double rhop = rho * nz2;
-    double inv = nz2 > 0.0 ? 1.0 / sqrt(nz2) : 0.0;
-    for (int i = 0; i < m.k; ++i) zs[i] *= inv;
-    double tol = 8.0 * DBL_EPSILON * fmax(dmax, rhop);
+    rs[tid] = nz2;
+    rm[tid] = dmax;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            rs[tid] += rs[tid + o];
+            rm[tid] = fmax(rm[tid], rm[tid + o]);
+        }
+        __syncthreads();
+    }
+    nz2 = rs[0];
+    dmax = rm[0];
+    const double rho = fabs(A.e[m.a + m.n1 - 1]);
+    const double rhop = rho * nz2;
+    const double inv = nz2 > 0.0 ? 1.0 / sqrt(nz2) : 0.0;
+    const double tol = 8.0 * DBL_EPSILON * fmax(dmax, rhop);
     int kk = 0, nd = 0, nr = 0, prev = -1;
-    for (int i = 0; i < m.k; ++i) {
-        if (rhop * fabs(zs[i]) <= tol) {
-            A.Dpos[m.a + nd++] = i;
-            continue;
+    double dprev = 0.0, zprev = 0.0;   // current values of entry prev (thread 0)
+    for (int c0 = 0; c0 < m.k; c0 += M2CH) {
+        const int cn = min(M2CH, m.k - c0);
+        __syncthreads();   // the previous chunk is written back
+        for (int i = tid; i < cn; i += 256) {
+            sd[i] = ds[c0 + i];
+            sz[i] = zs[c0 + i] * inv;
         }
-        if (prev < 0) { prev = i; continue; }
-        double s = zs[prev], c = zs[i];
-        double r = hypot(c, s);
-        c /= r;
-        s /= r;
-        double t = ds[i] - ds[prev];
-        if (fabs(t * c * s) <= tol) {
-            zs[i] = r;
-            zs[prev] = 0.0;
-            double dp = ds[prev] * c * c + ds[i] * s * s;
-            ds[i] = ds[prev] * s * s + ds[i] * c * c;
-            ds[prev] = dp;
-            A.rot_p[m.a + nr] = prev;
-            A.rot_i[m.a + nr] = i;
-            A.rot_c[m.a + nr] = c;
-            A.rot_s[m.a + nr] = s;
-            ++nr;
-            A.Dpos[m.a + nd++] = prev;
-            prev = i;
-        } else {
+        __syncthreads();
+        if (tid == 0) {
+            for (int il = 0; il < cn; ++il) {
+                const int i = c0 + il;
+                const double di = sd[il], zi = sz[il];
+                if (rhop * fabs(zi) <= tol) {
+                    A.Dpos[m.a + nd++] = i;
+                    continue;
+                }
+                if (prev < 0) {
+                    prev = i;
+                    dprev = di;
+                    zprev = zi;
+                    continue;
+                }
+                double s = zprev, c = zi;
+                const double r = hypot(c, s);
+                c /= r;
+                s /= r;
+                const double t = di - dprev;
+                if (fabs(t * c * s) <= tol) {
+                    const double dp = dprev * c * c + di * s * s;
+                    const double dn = dprev * s * s + di * c * c;
+                    if (prev >= c0) {
+                        sd[prev - c0] = dp;
+                        sz[prev - c0] = 0.0;
+                    } else {
+                        ds[prev] = dp;
+                        zs[prev] = 0.0;
+                    }
+                    sd[il] = dn;
+                    sz[il] = r;
+                    A.rot_p[m.a + nr] = prev;
+                    A.rot_i[m.a + nr] = i;
+                    A.rot_c[m.a + nr] = c;
+                    A.rot_s[m.a + nr] = s;
+                    ++nr;
+                    A.Dpos[m.a + nd++] = prev;
+                    prev = i;
+                    dprev = dn;
+                    zprev = r;
+                } else {
+                    A.Kpos[m.a + kk] = prev;
+                    A.dK[m.a + kk] = dprev;
+                    A.zK[m.a + kk] = zprev;
+                    ++kk;
+                    prev = i;
+                    dprev = di;
+                    zprev = zi;
+                }
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < cn; i += 256) {
+            ds[c0 + i] = sd[i];
+            zs[c0 + i] = sz[i];
+        }
+    }
+    if (tid == 0) {
+        if (prev >= 0) {
             A.Kpos[m.a + kk] = prev;
-            A.dK[m.a + kk] = ds[prev];
-            A.zK[m.a + kk] = zs[prev];
+            A.dK[m.a + kk] = dprev;
+            A.zK[m.a + kk] = zprev;
             ++kk;
-            prev = i;
         }
+        A.kcnt[p] = kk;
+        A.nrot[p] = nr;
+        A.rhop[p] = rhop;
     }
-    if (prev >= 0) {
-        A.Kpos[m.a + kk] = prev;
-        A.dK[m.a + kk] = ds[prev];
-        A.zK[m.a + kk] = zs[prev];
-        ++kk;
-    }
-    A.kcnt[p] = kk;
-    A.nrot[p] = nr;
-    A.rhop[p] = rhop;
 }
 
 // M3: secular roots.  Root j lies in (d_j, d_{j+1}) (last root: right of d_k);
@@ -602,7 +659,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         dim3 gN(cdiv(n, 256));
         hipLaunchKernelGGL(dc_m1_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dc_m2_kernel, dim3(P), dim3(64), 0, ctx->stream, A);
+        hipLaunchKernelGGL(dc_m2_kernel, dim3(P), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m3_kernel, dim3(cdiv(n * M3G, 256)), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
