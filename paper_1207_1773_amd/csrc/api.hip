@@ -176,6 +176,9 @@ int hgv_destroy(hgv_ctx_t ctx) {
     (void)hipSetDevice(ctx->device);
     for (hipStream_t st : ctx->side) (void)hipStreamDestroy(st);
     for (hipEvent_t e : ctx->side_ev) (void)hipEventDestroy(e);
+    if (ctx->la_stream) (void)hipStreamDestroy(ctx->la_stream);
+    for (hipEvent_t e : ctx->la_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
     for (auto &p : ctx->ev_pending) {

@@ -27,7 +27,13 @@
 namespace hgv {
 
 constexpr int PNB = 64;    // largest panel width supported by the column kernel
-constexpr int PCH = 128;   // panel rows per workgroup
+// panel rows per workgroup: 64 for complex double (67 KB of LDS, so that a
+// chunk can share a CU with GEMM tiles while the next panel is factored
+// during an update), 128 for complex float (75 KB)
+template <class E>
+constexpr int pch() {
+    return sizeof(E) == 16 ? 64 : 128;
+}
 
 template <class E>
 struct PanelArgs {
@@ -56,9 +62,9 @@ __device__ inline void make_reflector(double2 alpha, double tail, double &beta, 
 
 template <class E>
 struct PanelShared {
-    E Ps[PCH][PNB + 1];
+    E Ps[pch<E>()][PNB + 1];
     double2 s[PNB], r0v[PNB], w[PNB];
-    double2 vrow[PCH];
+    double2 vrow[pch<E>()];
     double2 red[4][PNB];
 };
 
@@ -69,6 +75,7 @@ template <class E>
 __device__ void panel_chunk_load(const PanelArgs<E> &a, PanelShared<E> &sh, int g, int c0) {
     auto &Ps = sh.Ps;
     const int tid = threadIdx.x;
+    constexpr int PCH = pch<E>();
     const int row0 = g * PCH;
     const int rows = min(PCH, a.N - row0);
     // load the chunk's columns c0..jb-1 through registers: every load is issued
@@ -98,6 +105,7 @@ template <class E>
 __device__ void panel_chunk_store(const PanelArgs<E> &a, PanelShared<E> &sh, int g, int c0) {
     auto &Ps = sh.Ps;
     const int tid = threadIdx.x;
+    constexpr int PCH = pch<E>();
     const int row0 = g * PCH;
     const int rows = min(PCH, a.N - row0);
     const int ncol = a.jb - c0;
@@ -117,6 +125,7 @@ __device__ void panel_chunk_compute(const PanelArgs<E> &a, PanelShared<E> &sh, i
     auto &vrow = sh.vrow;
     auto &red = sh.red;
     const int tid = threadIdx.x;
+    constexpr int PCH = pch<E>();
     const int row0 = g * PCH;
     const int rows = min(PCH, a.N - row0);
     const int c0 = max(j, 0);
@@ -176,15 +185,16 @@ __device__ void panel_chunk_compute(const PanelArgs<E> &a, PanelShared<E> &sh, i
         }
         __syncthreads();
         // apply H^H to columns j+1.., store v below the diagonal and beta on it;
-        // thread -> row tid % PCH and columns cc = tid / PCH, tid / PCH + 2, ...
+        // thread -> row tid % PCH and columns cc = tid / PCH, tid / PCH + NCG, ...
         // (a fixed-count loop, so that its LDS accesses overlap)
         {
-            const int r = tid & (PCH - 1), gr = row0 + r;
+            constexpr int NCG = 256 / PCH;
+            const int r = tid % PCH, gr = row0 + r;
             const bool rok = r < rows && gr >= j;
             const double2 vr = vrow[r];
 #pragma unroll
-            for (int u = 0; u < PNB / 2; ++u) {
-                const int cc = 2 * u + (tid >> 7);
+            for (int u = 0; u < PNB / NCG; ++u) {
+                const int cc = NCG * u + tid / PCH;
                 if (cc < ncol && rok) {
                     const int c = j + cc;
                     Ps[r][c] = El<E>::from(cc == 0 ? zsel(gr == j, make_double2(beta, 0.0), vr)
@@ -374,7 +384,7 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
                      int capacity) {
     typedef typename El<E>::Gemm Gm_t;
     const int r = std::min(N, jb);
-    const int G = cdiv(N, PCH);
+    const int G = cdiv(N, pch<E>());
     PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
     a.part = part; a.rowb = rowb;
@@ -406,13 +416,15 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
     const int np = num_panels(n, nb);
-    const int Gmax = cdiv(std::max(n, 1), PCH);
+    const int Gmax = cdiv(std::max(n, 1), pch<E>());
     size_t wsb = zgemm_splitk_bytes(n);
     void *ws = ar.take<char>(wsb);
     double2 *part = ar.take<double2>((size_t)2 * Gmax * PNB);
     double2 *rowb = ar.take<double2>(2 * PNB);
     double2 *tau = ar.take<double2>(PNB);
     E *Vw = ar.take<E>((size_t)n * nb);
+    E *Vw2 = ar.take<E>((size_t)n * nb);   // V of the next panel while this one's update runs
+    void *ws2 = ar.take<char>(wsb);        // split-K workspace of the look-ahead stream
     E *Y = ar.take<E>((size_t)n * nb);
     E *X = ar.take<E>((size_t)n * nb);
     E *Gm = ar.take<E>((size_t)nb * nb);
@@ -425,21 +437,44 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     hipLaunchKernelGGL(fill_int_kernel, dim3(cdiv(Gmax + 1, 256)), dim3(256), 0, ctx->stream, flags, Gmax + 1, 0);
     HGV_LAUNCH_CHECK();
     const int capacity = ctx->concurrent ? 0 : panel_persist_capacity<E>(ctx);
+    // Look-ahead (the panel of step p + 1 factored while the update of step p
+    // runs, as the paper overlaps its CPU panel with the GPU update): the
+    // update first applies to the next panel's columns, then the next panel
+    // is factored on a second stream while the main stream updates the rest of
+    // the trailing matrix; the streams join before the next update, which
+    // reads all of it.  Off while batched problems run side by side.
+    const bool la = !ctx->concurrent && np > 1;
+    hipStream_t main = ctx->stream;
+    if (la) ensure_lookahead_stream(ctx);
+    auto factor = [&](int p, hipStream_t st, E *Vp, void *wsp) {
+        const int k = p * nb;
+        const int jb = std::min(nb, n - k);
+        const int N = n - k - nb;
+        ctx->stream = st;
+        try {
+            panel_qr<E>(ctx, A + (k + nb) + (size_t)k * lda, lda, N, jb, tau, part, rowb, Vp, Gm,
+                        T1 + (size_t)p * nb * nb, nb, wsp, wsb, flags, flags + Gmax, p * (PNB + 2), capacity);
+        } catch (...) {
+            ctx->stream = main;
+            throw;
+        }
+        ctx->stream = main;
+    };
+    if (la) factor(0, main, Vw, ws);
     for (int p = 0; p < np; ++p) {
         const int k = p * nb;
         const int jb = std::min(nb, n - k);
         const int N = n - k - nb;
         const int r = std::min(N, jb);
-        E *P = A + (k + nb) + (size_t)k * lda;
         E *T = T1 + (size_t)p * nb * nb;
-        panel_qr<E>(ctx, P, lda, N, jb, tau, part, rowb, Vw, Gm, T, nb, ws, wsb, flags, flags + Gmax,
-                    p * (PNB + 2), capacity);
+        E *V = (la && (p & 1)) ? Vw2 : Vw;
+        if (!la) factor(p, main, Vw, ws);
         E *A22 = A + (k + nb) + (size_t)(k + nb) * lda;
         Gm_t g;
         // Y = V T
         g = Gm_t();
         g.m = N; g.n = r; g.k = r;
-        g.A = Vw; g.lda = N; g.B = T; g.ldb = nb;
+        g.A = V; g.lda = N; g.B = T; g.ldb = nb;
         g.C = Y; g.ldc = N;
         gemm_any(ctx, g, ws, wsb);
         // X = A22 Y  (A22 Hermitian, lower triangle stored)
@@ -452,7 +487,7 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
         // M = V^H X
         g = Gm_t();
         g.m = r; g.n = r; g.k = N;
-        g.opa = 'C'; g.A = Vw; g.lda = N;
+        g.opa = 'C'; g.A = V; g.lda = N;
         g.B = X; g.ldb = N;
         g.C = M; g.ldc = r;
         gemm_any(ctx, g, ws, wsb);
@@ -466,21 +501,44 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
         // W = X - 1/2 V M2  (into X)
         g = Gm_t();
         g.m = N; g.n = r; g.k = r;
-        g.A = Vw; g.lda = N; g.B = M2; g.ldb = r;
+        g.A = V; g.lda = N; g.B = M2; g.ldb = r;
         g.alpha = mhalf; g.beta = one;
         g.C = X; g.ldc = N;
         gemm_any(ctx, g, ws, wsb);
         // A22 <- A22 - V W^H - W V^H (lower)
-        g = Gm_t();
-        g.m = N; g.n = N; g.k = r;
-        g.opa = 'N'; g.A = Vw; g.lda = N;
-        g.opb = 'C'; g.B = X; g.ldb = N;
-        g.opa2 = 'N'; g.A2 = X; g.lda2 = N;
-        g.opb2 = 'C'; g.B2 = Vw; g.ldb2 = N;
-        g.alpha = mone; g.beta = one;
-        g.C = A22; g.ldc = lda;
-        g.lower = 1;
-        gemm_any(ctx, g, ws, wsb);
+        auto her2k = [&](int off) {   // rows and columns off.. of A22
+            g = Gm_t();
+            g.m = N - off; g.n = N - off; g.k = r;
+            g.opa = 'N'; g.A = V + off; g.lda = N;
+            g.opb = 'C'; g.B = X + off; g.ldb = N;
+            g.opa2 = 'N'; g.A2 = X + off; g.lda2 = N;
+            g.opb2 = 'C'; g.B2 = V + off; g.ldb2 = N;
+            g.alpha = mone; g.beta = one;
+            g.C = A22 + off + (size_t)off * lda; g.ldc = lda;
+            g.lower = 1;
+            gemm_any(ctx, g, ws, wsb);
+        };
+        if (la && p + 1 < np) {
+            const int nbn = std::min(nb, N);   // width of the next panel (its columns lead A22)
+            g = Gm_t();   // columns 0 .. nbn-1 of A22, every row at or below the diagonal
+            g.m = N; g.n = nbn; g.k = r;
+            g.opa = 'N'; g.A = V; g.lda = N;
+            g.opb = 'C'; g.B = X; g.ldb = N;
+            g.opa2 = 'N'; g.A2 = X; g.lda2 = N;
+            g.opb2 = 'C'; g.B2 = V; g.ldb2 = N;
+            g.alpha = mone; g.beta = one;
+            g.C = A22; g.ldc = lda;
+            g.lower = 1;
+            gemm_any(ctx, g, ws, wsb);
+            HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
+            HGV_HIP(hipStreamWaitEvent(ctx->la_stream, ctx->la_ev[0], 0));
+            factor(p + 1, ctx->la_stream, ((p + 1) & 1) ? Vw2 : Vw, ws2);
+            HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream));
+            her2k(nbn);
+            HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[1], 0));
+        } else {
+            her2k(0);
+        }
     }
     if (capacity > 0) report_wait_fail(ctx, flags + Gmax, d_info, 2 * n + 2);
 }

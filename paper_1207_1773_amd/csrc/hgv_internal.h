@@ -32,6 +32,10 @@ struct hgv_ctx_s {
     // workgroups wait for each other (and so need to be resident together)
     // then use their launch-per-step forms where they have one.
     bool concurrent = false;
+    // Second stream of the panel look-ahead in the band reduction and its two
+    // events (created on first use, default priority).
+    hipStream_t la_stream = nullptr;
+    hipEvent_t la_ev[2] = {nullptr, nullptr};
     int magic = 0x68677631;
 };
 
@@ -193,6 +197,8 @@ void set_info(hgv_ctx_s *ctx, int *d_info, int value);
 // measured FP64 MFMA rate (TFLOP/s) and copy bandwidth (GB/s, read + write)
 // of the context's device; work: device buffer, the copy uses most of it
 void device_peaks(hgv_ctx_s *ctx, void *work, size_t work_bytes, double *tflops, double *gbs);
+// creates ctx->la_stream and ctx->la_ev on first use
+void ensure_lookahead_stream(hgv_ctx_s *ctx);
 // *d_info = code if *err != 0 and *d_info == 0 (device words; d_info may be null)
 void report_wait_fail(hgv_ctx_s *ctx, const int *err, int *d_info, int code);
 

@@ -65,6 +65,13 @@ void set_info(hgv_ctx_s *ctx, int *d_info, int value) {
     HGV_LAUNCH_CHECK();
 }
 
+void ensure_lookahead_stream(hgv_ctx_s *ctx) {
+    if (ctx->la_stream) return;
+    HGV_HIP(hipStreamCreateWithFlags(&ctx->la_stream, hipStreamNonBlocking));
+    HGV_HIP(hipEventCreateWithFlags(&ctx->la_ev[0], hipEventDisableTiming));
+    HGV_HIP(hipEventCreateWithFlags(&ctx->la_ev[1], hipEventDisableTiming));
+}
+
 __global__ void wait_fail_kernel(const int *err, int *d_info, int code) {
     if (*err != 0 && *d_info == 0) *d_info = code;
 }
