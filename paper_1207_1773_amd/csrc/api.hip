@@ -176,7 +176,8 @@ int hgv_destroy(hgv_ctx_t ctx) {
     (void)hipSetDevice(ctx->device);
     for (hipStream_t st : ctx->side) (void)hipStreamDestroy(st);
     for (hipEvent_t e : ctx->side_ev) (void)hipEventDestroy(e);
-    if (ctx->la_stream) (void)hipStreamDestroy(ctx->la_stream);
+    for (hipStream_t st : ctx->la_stream)
+        if (st) (void)hipStreamDestroy(st);
     for (hipEvent_t e : ctx->la_ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);

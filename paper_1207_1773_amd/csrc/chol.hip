@@ -201,6 +201,7 @@ struct TriCtx {
     double2 *ws;
     size_t wsb;
     double2 *zw = nullptr;   // hegst: L21 A'11 of the current split (n2 x n1, ld n2)
+    double2 *ws_side = nullptr;   // hegst: split-K workspace of the side stream (null: no side stream)
 };
 
 static const double2 *linv_at(const double2 *Linv, int off) { return Linv + (size_t)(off / LEAF) * LEAF * LEAF; }
@@ -362,7 +363,11 @@ void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_inf
     potrf_rec(t, n, B, ldb, d_info, info_offset, Linv);
 }
 
-static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2 *L, int ldl, const double2 *Linv) {
+// spine: the block is the trailing one of every enclosing split (its area is
+// never read again by an enclosing level), so its A21 solve may run on the side
+// stream with a single join at the end of the reduction
+static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2 *L, int ldl, const double2 *Linv,
+                      bool spine) {
     if (n <= 0) return;
     if (n <= LEAF) {
         hipLaunchKernelGGL(hegs2_kernel<1024>, dim3(1), dim3(1024), 0, t.ctx->stream, n, A, lda, Linv);
@@ -372,7 +377,7 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
     int n1 = split_point(n), n2 = n - n1;
     double2 *A11 = A, *A21 = A + n1, *A22 = A + n1 + (size_t)n1 * lda;
     const double2 *L11 = L, *L21 = L + n1, *L22 = L + n1 + (size_t)n1 * ldl;
-    hegst_rec(t, n1, A11, lda, L11, ldl, Linv);
+    hegst_rec(t, n1, A11, lda, L11, ldl, Linv, false);
     trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);      // A21 <- A21 L11^-H
     fill_upper_from_lower(t.ctx, n1, A11, lda);                   // A'11 as a full matrix
     ZGemm h;  // Z = L21 A'11, used for both half-updates of A21 (one product instead of two)
@@ -393,8 +398,29 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
     r.lower = 1;
     zgemm(t.ctx, r, t.ws, t.wsb);
     add_scaled(t.ctx, n2, n1, -0.5, t.zw, n2, A21, lda);         // A21 -= 1/2 Z
-    trsm_left_ln_rec(t, n2, n1, L22, ldl, linv_at(Linv, n1), A21, lda);   // A21 <- L22^-1 A21
-    hegst_rec(t, n2, A22, lda, L22, ldl, linv_at(Linv, n1));
+    // A21 <- L22^-1 A21 needs nothing that the reduction of A22 produces; on the
+    // spine nothing reads A21 again before the reduction ends, so with a side
+    // stream it runs there (the spine's solves in order), overlapping the
+    // recursion, and joins at the end
+    if (t.ws_side && spine) {
+        hgv_ctx_s *c = t.ctx;
+        hipStream_t main = c->stream;
+        HGV_HIP(hipEventRecord(c->la_ev[2], main));
+        HGV_HIP(hipStreamWaitEvent(c->la_stream[1], c->la_ev[2], 0));
+        TriCtx ts = t;
+        ts.ws = t.ws_side;
+        c->stream = c->la_stream[1];
+        try {
+            trsm_left_ln_rec(ts, n2, n1, L22, ldl, linv_at(Linv, n1), A21, lda);
+        } catch (...) {
+            c->stream = main;
+            throw;
+        }
+        c->stream = main;
+    } else {
+        trsm_left_ln_rec(t, n2, n1, L22, ldl, linv_at(Linv, n1), A21, lda);
+    }
+    hegst_rec(t, n2, A22, lda, L22, ldl, linv_at(Linv, n1), spine);
 }
 
 void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, Arena &ar) {
@@ -403,9 +429,19 @@ void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int
     // every split of the recursion has n1 n2 <= (n / 2 + 64)^2
     const size_t zh = (size_t)std::max(n, 1) / 2 + LEAF;
     t.zw = ar.take<double2>(zh * zh);
+    double2 *wss = ar.take<double2>(t.wsb / sizeof(double2));
     if (ar.measuring()) return;
     invert_diag_blocks(ctx, n, L, ldl, Linv);
-    hegst_rec(t, n, A, lda, L, ldl, Linv);
+    const bool side = !ctx->concurrent && n > LEAF;
+    if (side) {
+        ensure_lookahead_stream(ctx);
+        t.ws_side = wss;
+    }
+    hegst_rec(t, n, A, lda, L, ldl, Linv, true);
+    if (side) {   // join the left solves
+        HGV_HIP(hipEventRecord(ctx->la_ev[3], ctx->la_stream[1]));
+        HGV_HIP(hipStreamWaitEvent(ctx->stream, ctx->la_ev[3], 0));
+    }
 }
 
 }  // namespace hgv

@@ -531,9 +531,9 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
             g.lower = 1;
             gemm_any(ctx, g, ws, wsb);
             HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
-            HGV_HIP(hipStreamWaitEvent(ctx->la_stream, ctx->la_ev[0], 0));
-            factor(p + 1, ctx->la_stream, ((p + 1) & 1) ? Vw2 : Vw, ws2);
-            HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream));
+            HGV_HIP(hipStreamWaitEvent(ctx->la_stream[0], ctx->la_ev[0], 0));
+            factor(p + 1, ctx->la_stream[0], ((p + 1) & 1) ? Vw2 : Vw, ws2);
+            HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream[0]));
             her2k(nbn);
             HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[1], 0));
         } else {

@@ -32,10 +32,12 @@ struct hgv_ctx_s {
     // workgroups wait for each other (and so need to be resident together)
     // then use their launch-per-step forms where they have one.
     bool concurrent = false;
-    // Second stream of the panel look-ahead in the band reduction and its two
-    // events (created on first use, default priority).
-    hipStream_t la_stream = nullptr;
-    hipEvent_t la_ev[2] = {nullptr, nullptr};
+    // Side streams of one solve (created on first use, default priority) and
+    // their events: [0] runs the next panel of the band reduction under the
+    // current update (events 0, 1), [1] the left triangular solves of the
+    // reduction to standard form under its recursion (events 2, 3).
+    hipStream_t la_stream[2] = {nullptr, nullptr};
+    hipEvent_t la_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     int magic = 0x68677631;
 };
 

@@ -66,10 +66,9 @@ void set_info(hgv_ctx_s *ctx, int *d_info, int value) {
 }
 
 void ensure_lookahead_stream(hgv_ctx_s *ctx) {
-    if (ctx->la_stream) return;
-    HGV_HIP(hipStreamCreateWithFlags(&ctx->la_stream, hipStreamNonBlocking));
-    HGV_HIP(hipEventCreateWithFlags(&ctx->la_ev[0], hipEventDisableTiming));
-    HGV_HIP(hipEventCreateWithFlags(&ctx->la_ev[1], hipEventDisableTiming));
+    if (ctx->la_stream[0]) return;
+    for (hipStream_t &st : ctx->la_stream) HGV_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    for (hipEvent_t &e : ctx->la_ev) HGV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 __global__ void wait_fail_kernel(const int *err, int *d_info, int code) {
