@@ -688,6 +688,29 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
                 hipLaunchKernelGGL((dc_m7_kernel<0>), dim3(ncols), dim3(256), 0, ctx->stream, A, -1);
         }
         HGV_LAUNCH_CHECK();
+        // the products of a level are independent of each other: they are dealt
+        // round-robin to the solve's stream and its two side streams (many of
+        // them are small), which join before the next level
+        const bool fan = !ctx->concurrent;
+        hipStream_t main = ctx->stream;
+        if (fan) {
+            ensure_lookahead_stream(ctx);
+            HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
+            for (hipStream_t st : ctx->la_stream) HGV_HIP(hipStreamWaitEvent(st, ctx->la_ev[0], 0));
+        }
+        int gi = 0;
+        auto dgemm_rr = [&](int mm, int nn, int kk, const double *Am, int ldam, const double *Bm, int ldbm,
+                            double *Cm, int ldcm) {
+            ctx->stream = fan && gi % 3 ? ctx->la_stream[gi % 3 - 1] : main;
+            ++gi;
+            try {
+                dgemm_nn(ctx, mm, nn, kk, 1.0, Am, ldam, Bm, ldbm, 0.0, Cm, ldcm);
+            } catch (...) {
+                ctx->stream = main;
+                throw;
+            }
+            ctx->stream = main;
+        };
         for (int p = 0; p < P; ++p) {
             MergeGeom g = merge_geom(n, L, p);
             if (g.n2 <= 0) {   // unpaired block: carried over unchanged
@@ -697,15 +720,20 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
             const double *Qp = Qb + qoff(L, p);
             if (last) {
                 // wanted columns only, straight into the output
-                dgemm_nn(ctx, g.n1, m, g.n1, 1.0, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, 0.0, Z + g.a, ldz);
-                dgemm_nn(ctx, g.n2, m, g.n2, 1.0, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1, g.k,
-                         0.0, Z + g.a + g.n1, ldz);
+                dgemm_rr(g.n1, m, g.n1, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, Z + g.a, ldz);
+                dgemm_rr(g.n2, m, g.n2, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1, g.k,
+                         Z + g.a + g.n1, ldz);
             } else {
-                dgemm_nn(ctx, g.n1, g.k, g.n1, 1.0, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, 0.0,
-                         Zn + g.a + (size_t)g.a * n, n);
-                dgemm_nn(ctx, g.n2, g.k, g.n2, 1.0, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1,
-                         g.k, 0.0, Zn + (g.a + g.n1) + (size_t)g.a * n, n);
+                dgemm_rr(g.n1, g.k, g.n1, Zc + g.a + (size_t)g.a * n, n, Qp, g.k, Zn + g.a + (size_t)g.a * n, n);
+                dgemm_rr(g.n2, g.k, g.n2, Zc + (g.a + g.n1) + (size_t)(g.a + g.n1) * n, n, Qp + g.n1, g.k,
+                         Zn + (g.a + g.n1) + (size_t)g.a * n, n);
             }
+        }
+        if (fan) {
+            HGV_HIP(hipEventRecord(ctx->la_ev[2], ctx->la_stream[0]));
+            HGV_HIP(hipEventRecord(ctx->la_ev[3], ctx->la_stream[1]));
+            HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[2], 0));
+            HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[3], 0));
         }
         std::swap(Zc, Zn);
         if (last) break;
