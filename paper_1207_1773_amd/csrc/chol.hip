@@ -201,7 +201,8 @@ struct TriCtx {
     double2 *ws;
     size_t wsb;
     double2 *zw = nullptr;   // hegst: L21 A'11 of the current split (n2 x n1, ld n2)
-    double2 *ws_side = nullptr;   // hegst: split-K workspace of the side stream (null: no side stream)
+    double2 *ws_side = nullptr;   // hegst: split-K workspace of side stream 1 (null: no side streams)
+    double2 *ws_side0 = nullptr;  // hegst: split-K workspace of side stream 0
 };
 
 static const double2 *linv_at(const double2 *Linv, int off) { return Linv + (size_t)(off / LEAF) * LEAF * LEAF; }
@@ -377,8 +378,31 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
     int n1 = split_point(n), n2 = n - n1;
     double2 *A11 = A, *A21 = A + n1, *A22 = A + n1 + (size_t)n1 * lda;
     const double2 *L11 = L, *L21 = L + n1, *L22 = L + n1 + (size_t)n1 * ldl;
-    hegst_rec(t, n1, A11, lda, L11, ldl, Linv, false);
-    trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);      // A21 <- A21 L11^-H
+    if (t.ws_side && spine) {
+        // A21 <- A21 L11^-H reads only the original A21 and L11: on side stream 0
+        // while the (non-spine, so fork-free) reduction of A11 runs; joined
+        // before A21 is next used
+        hgv_ctx_s *c = t.ctx;
+        hipStream_t main = c->stream;
+        HGV_HIP(hipEventRecord(c->la_ev[0], main));
+        HGV_HIP(hipStreamWaitEvent(c->la_stream[0], c->la_ev[0], 0));
+        TriCtx ts = t;
+        ts.ws = t.ws_side0;
+        c->stream = c->la_stream[0];
+        try {
+            trsm_right_lc_rec(ts, n2, n1, L11, ldl, Linv, A21, lda);
+        } catch (...) {
+            c->stream = main;
+            throw;
+        }
+        c->stream = main;
+        HGV_HIP(hipEventRecord(c->la_ev[1], c->la_stream[0]));
+        hegst_rec(t, n1, A11, lda, L11, ldl, Linv, false);
+        HGV_HIP(hipStreamWaitEvent(main, c->la_ev[1], 0));
+    } else {
+        hegst_rec(t, n1, A11, lda, L11, ldl, Linv, false);
+        trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);  // A21 <- A21 L11^-H
+    }
     fill_upper_from_lower(t.ctx, n1, A11, lda);                   // A'11 as a full matrix
     ZGemm h;  // Z = L21 A'11, used for both half-updates of A21 (one product instead of two)
     h.m = n2; h.n = n1; h.k = n1;
@@ -430,12 +454,14 @@ void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int
     const size_t zh = (size_t)std::max(n, 1) / 2 + LEAF;
     t.zw = ar.take<double2>(zh * zh);
     double2 *wss = ar.take<double2>(t.wsb / sizeof(double2));
+    double2 *wss0 = ar.take<double2>(t.wsb / sizeof(double2));
     if (ar.measuring()) return;
     invert_diag_blocks(ctx, n, L, ldl, Linv);
     const bool side = !ctx->concurrent && n > LEAF;
     if (side) {
         ensure_lookahead_stream(ctx);
         t.ws_side = wss;
+        t.ws_side0 = wss0;
     }
     hegst_rec(t, n, A, lda, L, ldl, Linv, true);
     if (side) {   // join the left solves
