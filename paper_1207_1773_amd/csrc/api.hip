@@ -71,6 +71,7 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     double *lambda = ar.take<double>(n);
     double2 *V2 = ar.take<double2>(v2_elems(n, nb));
     double2 *tau2 = ar.take<double2>(v2_taus(n, nb));
+    double2 *T2 = ar.take<double2>(q2_t_elems(n, nb));   // Q2's group T factors (built during stedc)
     double *Z = ar.take<double>((size_t)n * m);
     const size_t mk = ar.mark();
     const bool run = !ar.measuring();
@@ -86,6 +87,27 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     ar.release(mk);
     if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
 
+    // the T factors of Q2's reflector groups need only the bulge chasing's
+    // reflectors: built on a side stream while the tridiagonal solver runs
+    const bool side = run && !ctx->concurrent;
+    hipStream_t main = ctx->stream;
+    if (side) {
+        ensure_lookahead_stream(ctx);
+        HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
+        HGV_HIP(hipStreamWaitEvent(ctx->la_stream[0], ctx->la_ev[0], 0));
+        ctx->stream = ctx->la_stream[0];
+        try {
+            q2_build_t<double2>(ctx, n, nb, V2, tau2, T2);
+        } catch (...) {
+            ctx->stream = main;
+            throw;
+        }
+        ctx->stream = main;
+        HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream[0]));
+    } else if (run) {
+        q2_build_t<double2>(ctx, n, nb, V2, tau2, T2);
+    }
+
     if (tm) tm->begin(HGV_ST_STEDC);
     stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info);
     ar.release(mk);
@@ -99,8 +121,9 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     }
     if (tm) tm->end(HGV_ST_STEDC, 4.0 / 3.0 * N * N * N);
 
+    if (side) HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[1], 0));
     if (tm) tm->begin(HGV_ST_Q2);
-    unmtr_q2_run(ctx, n, nb, m, V2, tau2, X, ldx, ar);
+    if (run) q2_apply_t<double2>(ctx, n, nb, m, V2, T2, X, ldx, false);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_Q2, 8.0 * N * N * M);
 

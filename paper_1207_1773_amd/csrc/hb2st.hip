@@ -1136,6 +1136,9 @@ template void unmtr_q2_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, c
 template void unmtr_q2_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, const float2 *, float2 *, int, bool,
                                  Arena &);
 template void q2_build_t<float2>(hgv_ctx_s *, int, int, const float2 *, const float2 *, float2 *);
+template void q2_build_t<double2>(hgv_ctx_s *, int, int, const double2 *, const double2 *, double2 *);
+template void q2_apply_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, const double2 *, double2 *, int,
+                                  bool);
 template void q2_apply_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, const float2 *, float2 *, int, bool);
 
 }  // namespace hgv
