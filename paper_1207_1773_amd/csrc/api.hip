@@ -150,13 +150,10 @@ void zhegvx_full(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb
     const double N = n, M = m;
 
     if (run) set_info(ctx, d_info, 0);
+    // potrf, then hegst; the reduction of the leading block overlaps the
+    // factorisation of the trailing one
     if (tm) tm->begin(HGV_ST_POTRF);
-    potrf_run(ctx, n, B, ldb, ar, d_info, n);
-    ar.release(mk);
-    if (tm) tm->end(HGV_ST_POTRF, 4.0 / 3.0 * N * N * N);
-
-    if (tm) tm->begin(HGV_ST_HEGST);
-    hegst_run(ctx, n, A, lda, B, ldb, ar);
+    potrf_hegst_run(ctx, n, B, ldb, A, lda, ar, d_info, n, tm, 4.0 / 3.0 * N * N * N);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_HEGST, 4.0 * N * N * N);
 

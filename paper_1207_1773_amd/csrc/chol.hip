@@ -364,6 +364,9 @@ void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_inf
     potrf_rec(t, n, B, ldb, d_info, info_offset, Linv);
 }
 
+static void hegst_split_rest(const TriCtx &t, int n, int n1, double2 *A, int lda, const double2 *L, int ldl,
+                             const double2 *Linv, bool spine);
+
 // spine: the block is the trailing one of every enclosing split (its area is
 // never read again by an enclosing level), so its A21 solve may run on the side
 // stream with a single join at the end of the reduction
@@ -376,8 +379,8 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
         return;
     }
     int n1 = split_point(n), n2 = n - n1;
-    double2 *A11 = A, *A21 = A + n1, *A22 = A + n1 + (size_t)n1 * lda;
-    const double2 *L11 = L, *L21 = L + n1, *L22 = L + n1 + (size_t)n1 * ldl;
+    double2 *A11 = A, *A21 = A + n1;
+    const double2 *L11 = L;
     if (t.ws_side && spine) {
         // A21 <- A21 L11^-H reads only the original A21 and L11: on side stream 0
         // while the (non-spine, so fork-free) reduction of A11 runs; joined
@@ -403,6 +406,17 @@ static void hegst_rec(const TriCtx &t, int n, double2 *A, int lda, const double2
         hegst_rec(t, n1, A11, lda, L11, ldl, Linv, false);
         trsm_right_lc_rec(t, n2, n1, L11, ldl, Linv, A21, lda);  // A21 <- A21 L11^-H
     }
+    hegst_split_rest(t, n, n1, A, lda, L, ldl, Linv, spine);
+}
+
+// The rest of a split once A'11 = L11^-1 A11 L11^-H and A21 L11^-H are in place:
+// the two half-updates of A21 around the her2k of A22, the left solve of A21
+// with L22, and the recursion into A22.
+static void hegst_split_rest(const TriCtx &t, int n, int n1, double2 *A, int lda, const double2 *L, int ldl,
+                             const double2 *Linv, bool spine) {
+    const int n2 = n - n1;
+    double2 *A11 = A, *A21 = A + n1, *A22 = A + n1 + (size_t)n1 * lda;
+    const double2 *L21 = L + n1, *L22 = L + n1 + (size_t)n1 * ldl;
     fill_upper_from_lower(t.ctx, n1, A11, lda);                   // A'11 as a full matrix
     ZGemm h;  // Z = L21 A'11, used for both half-updates of A21 (one product instead of two)
     h.m = n2; h.n = n1; h.k = n1;
@@ -468,6 +482,74 @@ void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int
         HGV_HIP(hipEventRecord(ctx->la_ev[3], ctx->la_stream[1]));
         HGV_HIP(hipStreamWaitEvent(ctx->stream, ctx->la_ev[3], 0));
     }
+}
+
+// B = L L^H followed by A' = L^-1 A L^-H, overlapped at the top split: the
+// reduction of A11 and the solve A21 L11^-H need only L11 (and its block
+// inverses, which the leaf Cholesky kernels write), so they run on side stream
+// 0 while the main stream factors the trailing block of B; the rest of the
+// reduction follows on the main stream as in hegst_run.  The stage timer (may
+// be null) marks the end of the factorisation on the main stream.
+void potrf_hegst_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, double2 *A, int lda, Arena &ar, int *d_info,
+                     int info_offset, StageTimer *tm, double potrf_flops) {
+    if (ctx->concurrent || n <= LEAF) {
+        const size_t mk = ar.mark();
+        potrf_run(ctx, n, B, ldb, ar, d_info, info_offset);
+        ar.release(mk);
+        if (tm && !ar.measuring()) {
+            tm->end(HGV_ST_POTRF, potrf_flops);
+            tm->begin(HGV_ST_HEGST);
+        }
+        hegst_run(ctx, n, A, lda, B, ldb, ar);
+        return;
+    }
+    double2 *Linv;
+    TriCtx t = tri_scratch(ctx, ar, n, &Linv);
+    const size_t zh = (size_t)n / 2 + LEAF;
+    t.zw = ar.take<double2>(zh * zh);
+    double2 *wss = ar.take<double2>(t.wsb / sizeof(double2));
+    double2 *wss0 = ar.take<double2>(t.wsb / sizeof(double2));
+    if (ar.measuring()) return;
+    ensure_lookahead_stream(ctx);
+    const int n1 = split_point(n), n2 = n - n1;
+    double2 *B21 = B + n1, *B22 = B + n1 + (size_t)n1 * ldb;
+    potrf_rec(t, n1, B, ldb, d_info, info_offset, Linv);   // L11 and its block inverses
+    hipStream_t main = ctx->stream;
+    HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
+    HGV_HIP(hipStreamWaitEvent(ctx->la_stream[0], ctx->la_ev[0], 0));
+    TriCtx ts = t;   // no forks inside: the A11 block is off the spine
+    ts.ws = wss0;
+    ctx->stream = ctx->la_stream[0];
+    try {
+        hegst_rec(ts, n1, A, lda, B, ldb, Linv, false);               // A'11
+        trsm_right_lc_rec(ts, n2, n1, B, ldb, Linv, A + n1, lda);     // A21 <- A21 L11^-H
+    } catch (...) {
+        ctx->stream = main;
+        throw;
+    }
+    ctx->stream = main;
+    HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream[0]));
+    // the rest of the factorisation (the top split of potrf_rec)
+    trsm_right_lc_rec(t, n2, n1, B, ldb, Linv, B21, ldb);   // L21 = B21 L11^-H
+    ZGemm g;  // B22 -= L21 L21^H (lower)
+    g.m = n2; g.n = n2; g.k = n1;
+    g.opa = 'N'; g.A = B21; g.lda = ldb;
+    g.opb = 'C'; g.B = B21; g.ldb = ldb;
+    g.alpha = make_double2(-1.0, 0.0); g.beta = make_double2(1.0, 0.0);
+    g.C = B22; g.ldc = ldb;
+    g.lower = 1;
+    zgemm(ctx, g, t.ws, t.wsb);
+    potrf_rec(t, n2, B22, ldb, d_info, info_offset + n1, Linv + (size_t)(n1 / LEAF) * LEAF * LEAF);
+    if (tm) {
+        tm->end(HGV_ST_POTRF, potrf_flops);
+        tm->begin(HGV_ST_HEGST);
+    }
+    HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[1], 0));
+    t.ws_side = wss;
+    t.ws_side0 = wss0;
+    hegst_split_rest(t, n, n1, A, lda, B, ldb, Linv, true);
+    HGV_HIP(hipEventRecord(ctx->la_ev[3], ctx->la_stream[1]));   // join the left solves
+    HGV_HIP(hipStreamWaitEvent(main, ctx->la_ev[3], 0));
 }
 
 }  // namespace hgv

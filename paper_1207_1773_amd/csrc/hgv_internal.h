@@ -208,6 +208,9 @@ void report_wait_fail(hgv_ctx_s *ctx, const int *err, int *d_info, int code);
 // Every stage has a plan (arena-driven size) and a run with the same arena.
 void potrf_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, Arena &ar, int *d_info, int info_offset);
 void hegst_run(hgv_ctx_s *ctx, int n, double2 *A, int lda, const double2 *L, int ldl, Arena &ar);
+struct StageTimer;
+void potrf_hegst_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, double2 *A, int lda, Arena &ar, int *d_info,
+                     int info_offset, StageTimer *tm, double potrf_flops);
 void trsm_lh_run(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
 // Triangular solves used by the recursive stages (L lower n x n):
 //   right_lc:  X <- X L^-H      (X m x n)
