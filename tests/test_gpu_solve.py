@@ -79,6 +79,22 @@ def test_not_positive_definite(ctx):
     assert info == info_o == n + 20
 
 
+@pytest.mark.parametrize("k", [19, 249])
+def test_not_positive_definite_split(ctx, k):
+    """n = 300: the first failing pivot in the leading block of the top split (k = 19) or
+    in the trailing one (k = 249), where the factorisation continues after the reduction of
+    the leading block has been started; info = n + k + 1 either way."""
+    n = 300
+    A = rand_herm(n, 3)
+    Lb = np.linalg.cholesky(rand_hpd(n, 4))
+    Dg = np.ones(n)
+    Dg[k] = -1.0
+    B = (Lb * Dg) @ Lb.conj().T
+    _, _, info, _ = ctx.zhegvx(to_dev(A), to_dev(B))
+    _, _, info_o = oracle.zhegv(A, B)
+    assert info == info_o == n + k + 1
+
+
 def test_reads_lower_triangles_only(ctx):
     n = 90
     A = rand_herm(n, 3)
