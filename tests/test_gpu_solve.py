@@ -79,6 +79,30 @@ def test_not_positive_definite(ctx):
     assert info == info_o == n + 20
 
 
+def test_all_columns_constructed_n4096(ctx):
+    """n = 4096, all pairs: lambda = sort(D), and the residual (per half of the columns)
+    and B-orthogonality over every column, beyond the leading columns the benchmark's
+    accuracy check samples."""
+    import torch
+
+    n = 4096
+    A, B, parts = constructed(n, 7, "uniform", return_parts=True)
+    A, B = A.numpy(), B.numpy()
+    W, X, info, _ = ctx.zhegvx(to_dev(A), to_dev(B))
+    assert info == 0
+    D = np.sort(parts["D"])
+    np.testing.assert_allclose(to_np(W), D, rtol=0, atol=1e-12 * np.abs(D).max())
+    # the same metrics as tests.metrics, with the n^3 products on the device
+    Ad, Bd = to_dev(A), to_dev(B)
+    norm1 = lambda M: float(M.abs().sum(0).max())
+    BX = Bd @ X
+    R = Ad @ X - BX * W.to(X.dtype)[None, :]
+    for h in (slice(0, n // 2), slice(n // 2, n)):
+        assert norm1(R[:, h]) / (n * norm1(Ad) * norm1(X[:, h])) <= 1e-14
+    G = X.conj().T @ BX
+    assert norm1(G - torch.eye(n, dtype=G.dtype, device=G.device)) <= 1e-13 * n
+
+
 @pytest.mark.parametrize("k", [19, 249])
 def test_not_positive_definite_split(ctx, k):
     """n = 300: the first failing pivot in the leading block of the top split (k = 19) or
