@@ -115,11 +115,16 @@ def main():
 
     def accuracy(W, X, mm, cols=2000):
         """residual ||AX - BX W||_1 / (n ||A||_1 ||X||_1), ||X^H B X - I||_1 and the eigenvalue error
-        against the constructed spectrum, on the first `cols` pairs (all eigenvalues)."""
+        against the constructed spectrum (all eigenvalues), on `cols` pairs: all of them, or the
+        first and the last cols/2 when there are more."""
         Wn = W.cpu().numpy()
         lerr = float(np.abs(Wn - D_sorted[:mm]).max() / np.abs(D_sorted).max())
-        Xs = X[:, : min(mm, cols)]
-        Ws = W[: min(mm, cols)].to(torch.complex128)
+        if mm <= cols:
+            idx = torch.arange(mm, device=X.device)
+        else:
+            idx = torch.cat([torch.arange(cols // 2), torch.arange(mm - cols // 2, mm)]).to(X.device)
+        Xs = X[:, idx]
+        Ws = W[idx].to(torch.complex128)
         BX = B @ Xs
         R = A @ Xs - BX * Ws[None, :]
         res = n1(R) / (n * n1(A) * n1(Xs))

@@ -1,7 +1,7 @@
 // stedc.hip -- divide-and-conquer eigensolver for the real symmetric
 // tridiagonal T (Alg. 2 step 2, Sec. 4.3), entirely on the device.
 //
-// Split: T is torn into leaves of S rows; at a boundary with coupling e
+// Split: T is torn into leaves of S <= 64 rows; at a boundary with coupling e
 // (rows q-1, q) T = diag(T1, T2) + rho v v^T with rho = |e| and
 // v = e_{q-1} + sign(e) e_q, so |e| is subtracted from d_{q-1} and d_q.
 // Leaves: implicit QL with shifts, one workgroup per leaf (lane r keeps row r
@@ -36,7 +36,19 @@
 
 namespace hgv {
 
-constexpr int DC_LEAF = 32;
+constexpr int DC_LEAF_MAX = 64;   // rows of a leaf: one lane per row
+
+// Leaf size: the fewest doublings that bring the leaves to at most 64 rows,
+// with n spread evenly over them, so that the merges at every level (above all
+// the last one, which holds most of the flops) pair blocks of nearly equal size
+// (n = 10000: leaves of 40 and a last merge of 5120 + 4880, where a fixed
+// leaf of 32 rows gave 8192 + 1808).
+static int dc_leaf_size(int n) {
+    if (n <= DC_LEAF_MAX) return std::max(n, 1);
+    int blocks = 1;
+    while ((n + blocks - 1) / blocks > DC_LEAF_MAX) blocks *= 2;
+    return (n + blocks - 1) / blocks;
+}
 
 struct MergeGeom {
     int a, n1, n2, k;
@@ -607,7 +619,7 @@ static void dcopy2d(hgv_ctx_s *ctx, int m, int n, const double *A, int lda, doub
 
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu, double *lambda, double *Z,
                int ldz, Arena &ar, int *d_info) {
-    const int S = DC_LEAF;
+    const int S = dc_leaf_size(n);
     const int m = iu - il + 1;
     // Q buffer: the largest level's sum of k^2 with offsets p * 4 L^2
     size_t qmax = 1;
