@@ -88,28 +88,37 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
 
     // the T factors of Q2's reflector groups need only the bulge chasing's
-    // reflectors: built on a side stream while the tridiagonal solver runs
+    // reflectors: built on a side stream while the tridiagonal solver runs the
+    // serial kernels of its last merge level (beside its small, latency-bound
+    // levels the build slowed them down)
     const bool side = run && !ctx->concurrent;
     hipStream_t main = ctx->stream;
-    if (side) {
+    bool built = false;
+    auto build_t_side = [&]() {
         ensure_lookahead_stream(ctx);
-        HGV_HIP(hipEventRecord(ctx->la_ev[0], main));
-        HGV_HIP(hipStreamWaitEvent(ctx->la_stream[0], ctx->la_ev[0], 0));
-        ctx->stream = ctx->la_stream[0];
+        HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->stream));
+        HGV_HIP(hipStreamWaitEvent(ctx->la_stream[1], ctx->la_ev[1], 0));
+        hipStream_t cur = ctx->stream;
+        ctx->stream = ctx->la_stream[1];
         try {
             q2_build_t<double2>(ctx, n, nb, V2, tau2, T2);
         } catch (...) {
-            ctx->stream = main;
+            ctx->stream = cur;
             throw;
         }
-        ctx->stream = main;
-        HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream[0]));
-    } else if (run) {
+        ctx->stream = cur;
+        HGV_HIP(hipEventRecord(ctx->la_ev[1], ctx->la_stream[1]));
+        built = true;
+    };
+    if (run && !side) {
         q2_build_t<double2>(ctx, n, nb, V2, tau2, T2);
+        built = true;
     }
 
     if (tm) tm->begin(HGV_ST_STEDC);
-    stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info);
+    if (side) stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info, build_t_side);
+    else stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info);
+    if (side && !built) build_t_side();   // no merge level (n within one leaf)
     ar.release(mk);
     if (run) {
         hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "hgv.h"
@@ -251,8 +252,11 @@ inline void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, 
 }
 size_t v2_elems(int n, int nb);
 size_t v2_taus(int n, int nb);
+// at_last_level (may be empty) is called once, on the host, when the work of
+// the last merge level is about to be enqueued (not at all without merges).
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu,
-               double *lambda, double *Z, int ldz, Arena &ar, int *d_info);
+               double *lambda, double *Z, int ldz, Arena &ar, int *d_info,
+               const std::function<void()> &at_last_level = {});
 inline void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2,
                          double2 *Y, int ldy, Arena &ar) {
     unmtr_q2_t<double2>(ctx, n, nb, m, V2, tau2, Y, ldy, false, ar);

@@ -618,7 +618,7 @@ static void dcopy2d(hgv_ctx_s *ctx, int m, int n, const double *A, int lda, doub
 }
 
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu, double *lambda, double *Z,
-               int ldz, Arena &ar, int *d_info) {
+               int ldz, Arena &ar, int *d_info, const std::function<void()> &at_last_level) {
     const int S = dc_leaf_size(n);
     const int m = iu - il + 1;
     // Q buffer: the largest level's sum of k^2 with offsets p * 4 L^2
@@ -660,6 +660,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
     for (int L = S; L < n; L *= 2) {
         const int P = cdiv(n, 2 * L);
         const bool last = (2 * L >= n);
+        if (last && at_last_level) at_last_level();
         DcArgs A;
         A.n = n; A.L = L; A.P = P; A.e = e; A.D = D; A.Zc = Zc; A.ldz = n;
         A.ds = ds; A.zs = zs; A.perm = perm; A.dK = dK; A.zK = zK; A.Kpos = Kpos; A.Dpos = Dpos;
