@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void dc_m2_kernel(DcArgs A) {
 // butterfly over the group adds the partial sums.  Floating-point addition is
 // commutative, so every lane of the group ends with the same sums bit for bit
 // and takes the same branches of the iteration.
-constexpr int M3G = 16;
+constexpr int M3G = 32;
 
 __device__ inline double group_add(double x) {
 #pragma unroll
