@@ -4,8 +4,10 @@ oracle's implicit QL on the same (d, e).
 Eigenvalues are unique: |lambda_gpu - lambda_oracle| <= 1e-13 ||T||_1 (both backward
 stable, Weyl bound).  Eigenvectors are unique up to sign for simple eigenvalues: the
 tests compare |z_i . z~_i| >= 1 - 1e-20 / relgap_i^2 style bounds through the subspace
-angle, and check orthogonality and the residual for every vector.  Leaves hold 32 rows,
-so sizes span several merge levels and ragged last leaves.
+angle, and check orthogonality and the residual for every vector.  Leaves hold at most 64
+rows (n spread evenly over a power-of-two number of blocks), so sizes above 64 span
+several merge levels, ragged last leaves and, from n = 2049 on, blocks left unpaired at a
+level.
 """
 import numpy as np
 import pytest
@@ -61,13 +63,36 @@ def check(d, e, lam, Z, il, iu):
         assert (1 - align[sep]).max() < 1e-18 / (gaps[sep] / nT).min() ** 2 + 1e-12
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 64, 100, 257, 600])
+@pytest.mark.parametrize("n", [1, 2, 5, 31, 32, 33, 64, 65, 100, 129, 257, 600])
 @pytest.mark.parametrize("kind", ["rand", "toeplitz", "clustered", "glued", "split"])
 def test_stedc_full(ctx, n, kind):
     d, e = tridiag_cases(n, kind, n)
     lam, Z, info = ctx.stedc(to_dev(d), to_dev(e), 1, n)
     assert info == 0
     check(d, e, to_np(lam), to_np(Z), 1, n)
+
+
+@pytest.mark.parametrize("kind", ["rand", "glued"])
+def test_stedc_unpaired_blocks_n2049(ctx, kind):
+    """n = 2049: 63 leaves of 33 rows, so one block per level up the tree is carried over
+    unpaired.  Eigenvalues against LAPACK's tridiagonal eigenvalue routine (the oracle's
+    QL with vectors takes about 10 s at this size); residual and orthogonality of every
+    vector."""
+    from scipy.linalg import eigvalsh_tridiagonal
+
+    n = 2049
+    d, e = tridiag_cases(n, kind, n)
+    lam, Z, info = ctx.stedc(to_dev(d), to_dev(e), 1, n)
+    assert info == 0
+    lam, Z = to_np(lam), to_np(Z)
+    nT = np.abs(np.diag(d) + np.diag(e, -1) + np.diag(e, 1)).sum(axis=0).max()
+    wl = eigvalsh_tridiagonal(d, e)
+    np.testing.assert_allclose(lam, wl, rtol=0, atol=1e-13 * nT * n / 100)
+    TZ = d[:, None] * Z
+    TZ[:-1] += e[:, None] * Z[1:]
+    TZ[1:] += e[:, None] * Z[:-1]
+    assert np.abs(TZ - Z * lam).max() <= 1e-13 * nT * n / 100
+    assert np.abs(Z.T @ Z - np.eye(n)).max() <= 1e-13 * n / 100
 
 
 @pytest.mark.parametrize("n,il,iu", [(300, 1, 30), (300, 271, 300), (513, 100, 100), (97, 1, 97), (1000, 1, 100)])
