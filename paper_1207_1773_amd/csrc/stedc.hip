@@ -463,26 +463,39 @@ __global__ void dc_m3_kernel(DcArgs A) {
     }
 }
 
+__device__ inline double group_mul(double x) {
+#pragma unroll
+    for (int o = 1; o < M3G; o <<= 1) x *= __shfl_xor(x, o, M3G);
+    return x;
+}
+
 // M4: Gu-Eisenstat recomputation of u from the computed roots.
+// One group of M3G lanes per element (as for the roots): lane `sub` multiplies
+// the factors j = sub, sub + M3G, ..., and an xor butterfly multiplies the
+// partial products (multiplication commutes, so every lane of the group ends
+// with the same product).
 __global__ void dc_m4_kernel(DcArgs A) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= A.n) return;
-    int p = g / (2 * A.L);
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gi = g / M3G, sub = g % M3G;
+    // every exit below is taken by whole lane groups (it depends on gi only)
+    if (gi >= A.n) return;
+    int p = gi / (2 * A.L);
     MergeGeom m = merge_geom(A.n, A.L, p);
     if (m.n2 <= 0) return;
-    int i = g - m.a;
+    int i = gi - m.a;
     int kp = A.kcnt[p];
     if (i >= kp) return;
     const double *dK = A.dK + m.a;
     const int *org = A.org + m.a;
     const double *tau = A.tau + m.a;
     double di = dK[i];
-    double prod = ((dK[org[i]] - di) + tau[i]) / A.rhop[p];
-    for (int j = 0; j < kp; ++j) {
+    double prod = 1.0;
+    for (int j = sub; j < kp; j += M3G) {
         if (j == i) continue;
         prod *= ((dK[org[j]] - di) + tau[j]) / (dK[j] - di);
     }
-    A.zh[m.a + i] = copysign(sqrt(fabs(prod)), A.zK[m.a + i]);
+    prod = group_mul(prod) * (((dK[org[i]] - di) + tau[i]) / A.rhop[p]);
+    if (sub == 0) A.zh[m.a + i] = copysign(sqrt(fabs(prod)), A.zK[m.a + i]);
 }
 
 // M5: eigenvalue of every item (roots first, then deflated entries).
@@ -676,7 +689,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m3_kernel, dim3(cdiv(n * M3G, 256)), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dc_m4_kernel, gN, dim3(256), 0, ctx->stream, A);
+        hipLaunchKernelGGL(dc_m4_kernel, dim3(cdiv(n * M3G, 256)), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m5_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
