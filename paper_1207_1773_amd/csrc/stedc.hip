@@ -512,19 +512,27 @@ __global__ void dc_m5_kernel(DcArgs A) {
 }
 
 // M6: sort the items (rank by counting, ties by item index); new spectrum into D.
+// One group of M3G lanes per element: lane `sub` counts over y = sub, sub + M3G,
+// ..., and the group adds the counts (integers: the rank is exact).
 __global__ void dc_m6_kernel(DcArgs A) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= A.n) return;
-    int p = g / (2 * A.L);
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gi = g / M3G, sub = g % M3G;
+    // every exit below is taken by whole lane groups (it depends on gi only)
+    if (gi >= A.n) return;
+    int p = gi / (2 * A.L);
     MergeGeom m = merge_geom(A.n, A.L, p);
     if (m.n2 <= 0) return;
-    int x = g - m.a;
+    int x = gi - m.a;
     const double *iv = A.ival + m.a;
     double v = iv[x];
     int r = 0;
-    for (int y = 0; y < m.k; ++y) r += (iv[y] < v || (iv[y] == v && y < x)) ? 1 : 0;
-    A.D[m.a + r] = v;
-    A.colitem[m.a + r] = x;
+    for (int y = sub; y < m.k; y += M3G) r += (iv[y] < v || (iv[y] == v && y < x)) ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < M3G; o <<= 1) r += __shfl_xor(r, o, M3G);
+    if (sub == 0) {
+        A.D[m.a + r] = v;
+        A.colitem[m.a + r] = x;
+    }
 }
 
 // M7: column `col` of Q (rows in the children's order).  The column is built
@@ -693,7 +701,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(dc_m5_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
-        hipLaunchKernelGGL(dc_m6_kernel, gN, dim3(256), 0, ctx->stream, A);
+        hipLaunchKernelGGL(dc_m6_kernel, dim3(cdiv(n * M3G, 256)), dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();
         const int kmax = std::min(2 * L, n);
         if (last) {
