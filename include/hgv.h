@@ -105,6 +105,18 @@ int hgv_last_hip_error(hgv_ctx_t ctx);
 /* Band width the solver uses for order n and precision when opts->nb == 0. */
 int hgv_default_nb(int n, int precision);
 
+/* Test hooks (for the library's own failure-path tests; 0 = off, the default).
+ * HGV_TEST_WAIT_FAIL: the give-up flags of the kernels with bounded waits
+ *   (band reduction panel, bulge chasing) start set, so every wait returns at
+ *   once, every kernel still runs to its end, and the stage reports
+ *   d_info = 2n+2 (its outputs are then not valid).
+ * HGV_TEST_NAN_RESIDUAL: the mixed-precision refinement sees a NaN residual,
+ *   so it never meets its tolerance (FP64 fallback, or d_info = 2n+1 under
+ *   graph capture).
+ * Returns -2 for unknown bits. */
+enum { HGV_TEST_WAIT_FAIL = 1, HGV_TEST_NAN_RESIDUAL = 2 };
+int hgv_test_hooks(hgv_ctx_t ctx, int mask);
+
 /* ---- full generalized solve (Algorithm 1) -------------------------------- */
 /* Workspace bytes needed by hgv_zhegvx for these arguments. */
 int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts,
@@ -135,8 +147,8 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
                hgv_stats *stats);
 
 /* ---- batched solves ------------------------------------------------------- */
-/* Many independent pencils of uneven orders (the paper's target applications
- * solve such problems many times).  Arrays of length `batch` live in HOST
+/* Many independent pencils of uneven orders (Sec. 1: the paper's target
+ * applications, electronic-structure codes, solve such problems many times).  Arrays of length `batch` live in HOST
  * memory and hold per-problem sizes and DEVICE pointers with the meaning of
  * hgv_zhegvx; nb may be NULL (default band width per order) or hold a band
  * width per problem (e.g. from the autotuner of the Python package).  The
@@ -176,25 +188,30 @@ int hgv_zhegst(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, const hgv_c128 *L, in
  * T1 + p*nb*nb, column-major, upper triangular) holds the compact-WY factors:
  * panel p's transform is I - V_p T_p V_p^H.  Every reflector maps its column
  * onto a real multiple of e_1, so the band's first subdiagonal inside a panel
- * is real. */
+ * is real.  d_info (device int, may be NULL) is set to 0, or to 2n+2 when a
+ * bounded wait of the panel kernel gave up (the result is then not valid). */
 int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1,
-               void *work, size_t work_bytes);
+               void *work, size_t work_bytes, int *d_info);
 
 /* Alg. 2 step 1, second stage (Sec. 4.2): column-wise bulge chasing of the
  * band held in the lower band of A (as left by hgv_zhe2hb; A is not modified)
  * to the real symmetric tridiagonal (d[n], e[n-1]) with Band = Q2 T Q2^H.
  * V2 receives the reflectors (hgv_v2_elems(n, nb) complex entries) and tau2
  * their scalars (hgv_v2_taus(n, nb) entries), in the layout hgv_zunmtr_q2
- * reads. */
+ * reads.  d_info (device int, may be NULL) is set to 0, or to 2n+2 when a
+ * bounded wait of the bulge-chasing kernel gave up (outputs not valid). */
 int hgv_zhb2st(hgv_ctx_t ctx, int n, int nb, const hgv_c128 *A, int lda, double *d,
-               double *e, hgv_c128 *V2, hgv_c128 *tau2, void *work, size_t work_bytes);
+               double *e, hgv_c128 *V2, hgv_c128 *tau2, void *work, size_t work_bytes,
+               int *d_info);
 size_t hgv_v2_elems(int n, int nb);
 size_t hgv_v2_taus(int n, int nb);
 
 /* Alg. 2 step 2 (Sec. 4.3): divide and conquer on the real symmetric
  * tridiagonal (d, e) -> all n eigenvalues ascending in lambda[n], and the
  * eigenvectors il..iu in Z (n x m real, ldz >= n; only the needed columns are
- * formed in the last merge).  d_info gets k >= 1 on failure. */
+ * formed in the last merge).  d_info gets k in [1, n] on failure (a leaf
+ * whose Jacobi sweeps did not converge: its first row; a secular root that
+ * did not converge: its index in its merge); the first failure recorded wins. */
 int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu,
                double *lambda, double *Z, int ldz, void *work, size_t work_bytes,
                int *d_info);

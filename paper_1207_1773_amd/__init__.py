@@ -30,7 +30,10 @@ EXPORTS = [
     "hgv_zhegst", "hgv_zhe2hb", "hgv_zhb2st", "hgv_v2_elems", "hgv_v2_taus", "hgv_dstedc",
     "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_device_peaks", "hgv_gauge_fix",
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
+    "hgv_test_hooks",
 ]
+HGV_TEST_WAIT_FAIL = 1
+HGV_TEST_NAN_RESIDUAL = 2
 
 
 class c128(ctypes.Structure):
@@ -92,8 +95,9 @@ def load():
         "hgv_stage_bufsize": (I, [P, I, I, I, I, ctypes.POINTER(SZ)]),
         "hgv_zpotrf": (I, [P, I, P, I, P, SZ, P]),
         "hgv_zhegst": (I, [P, I, P, I, P, I, P, SZ]),
-        "hgv_zhe2hb": (I, [P, I, I, P, I, P, P, SZ]),
-        "hgv_zhb2st": (I, [P, I, I, P, I, P, P, P, P, P, SZ]),
+        "hgv_zhe2hb": (I, [P, I, I, P, I, P, P, SZ, P]),
+        "hgv_zhb2st": (I, [P, I, I, P, I, P, P, P, P, P, SZ, P]),
+        "hgv_test_hooks": (I, [P, I]),
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
         "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
@@ -176,12 +180,16 @@ def hgv_zhegst(ctx, n, A, lda, L, ldl, work, work_bytes):
     _check(load().hgv_zhegst(ctx, n, A, lda, L, ldl, work, work_bytes), "hgv_zhegst")
 
 
-def hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes):
-    _check(load().hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes), "hgv_zhe2hb")
+def hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes, d_info=None):
+    _check(load().hgv_zhe2hb(ctx, n, nb, A, lda, T1, work, work_bytes, d_info), "hgv_zhe2hb")
 
 
-def hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes):
-    _check(load().hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes), "hgv_zhb2st")
+def hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes, d_info=None):
+    _check(load().hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes, d_info), "hgv_zhb2st")
+
+
+def hgv_test_hooks(ctx, mask):
+    _check(load().hgv_test_hooks(ctx, mask), "hgv_test_hooks")
 
 
 def hgv_v2_elems(n, nb):

@@ -83,7 +83,7 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
 
     if (tm) tm->begin(HGV_ST_HB2ST);
-    hb2st_run(ctx, n, nb, A, lda, d, e, V2, tau2, ar);
+    hb2st_run(ctx, n, nb, A, lda, d, e, V2, tau2, ar, d_info);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
 
@@ -227,6 +227,13 @@ int hgv_set_stream(hgv_ctx_t ctx, void *stream) {
 }
 
 int hgv_last_hip_error(hgv_ctx_t ctx) { return ctx_ok(ctx) ? ctx->last_hip_error : 0; }
+
+int hgv_test_hooks(hgv_ctx_t ctx, int mask) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (mask & ~(HGV_TEST_WAIT_FAIL | HGV_TEST_NAN_RESIDUAL)) return -2;
+    ctx->test_hooks = mask;
+    return HGV_OK;
+}
 
 const char *hgv_status_string(int status) {
     if (status == HGV_OK) return "success";
@@ -391,7 +398,7 @@ int hgv_zhegst(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, const hgv_c128 *L, in
 }
 
 int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1, void *work,
-               size_t work_bytes) {
+               size_t work_bytes, int *d_info) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
     if (n < 0) return -2;
     if (nb < 1) return -3;
@@ -401,8 +408,9 @@ int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1,
     int st = check_work(ctx, HGV_ST_HE2HB, n, nb, 0, work, work_bytes, 7);
     if (st) return st;
     return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
         Arena ar(work, work_bytes);
-        he2hb_run(ctx, n, nb, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(T1), ar);
+        he2hb_run(ctx, n, nb, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(T1), ar, d_info);
         return HGV_OK;
     });
 }
@@ -411,7 +419,7 @@ size_t hgv_v2_elems(int n, int nb) { return (n > 0 && nb > 0) ? v2_elems(n, nb) 
 size_t hgv_v2_taus(int n, int nb) { return (n > 0 && nb > 0) ? v2_taus(n, nb) : 0; }
 
 int hgv_zhb2st(hgv_ctx_t ctx, int n, int nb, const hgv_c128 *A, int lda, double *d, double *e, hgv_c128 *V2,
-               hgv_c128 *tau2, void *work, size_t work_bytes) {
+               hgv_c128 *tau2, void *work, size_t work_bytes, int *d_info) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
     if (n < 0) return -2;
     if (nb < 1) return -3;
@@ -424,9 +432,10 @@ int hgv_zhb2st(hgv_ctx_t ctx, int n, int nb, const hgv_c128 *A, int lda, double 
     int st = check_work(ctx, HGV_ST_HB2ST, n, nb, 0, work, work_bytes, 10);
     if (st) return st;
     return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
         Arena ar(work, work_bytes);
         hb2st_run(ctx, n, nb, reinterpret_cast<const double2 *>(A), lda, d, e, reinterpret_cast<double2 *>(V2),
-                  reinterpret_cast<double2 *>(tau2), ar);
+                  reinterpret_cast<double2 *>(tau2), ar, d_info);
         return HGV_OK;
     });
 }

@@ -107,10 +107,14 @@ __global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a) {
             // ---- wait for sweep s-1 ------------------------------------------------
             if (s > 0 && tid == 0) {
                 // poll with relaxed loads (an acquire per poll would invalidate the
-                // caches for every other workgroup), then one acquire fence
+                // caches for every other workgroup), then one acquire fence.  The
+                // wait is bounded: one that gives up sets *err, and every wait
+                // that sees *err set returns at once, so the launch always ends
+                // (the host side then reports d_info = 2n+2: the band is not valid)
                 const int need = min(j + 2, hb_tasks(n, b, s - 1));
                 long spins = 0;
                 while (__hip_atomic_load(&a.prog[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
                     __builtin_amdgcn_s_sleep(1);
                     if (++spins > (1L << 27)) {
                         __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -369,7 +373,8 @@ static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
 }
 
 template <class E>
-void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar) {
+void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar,
+             int *d_info) {
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
     const int b = nb, ldb = 2 * nb;
     E *AB = ar.take<E>((size_t)ldb * std::max(n, 1));
@@ -383,21 +388,23 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     zero2(ctx, tau2, v2_taus(n, nb));
     hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, ctx->stream, prog, std::max(n, 1) + 1);
     HGV_LAUNCH_CHECK();
+    if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, err, 1);
     if (n >= 2) {
         HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
         // 64-wide bands: 512 threads (8 elements of a task's diagonal block per
         // thread), which shortens the arithmetic of the dependent task chain
         if (b <= 32) launch_hb2st<32, 256, E>(ctx, a);
         else launch_hb2st<64, 512, E>(ctx, a);
+        report_wait_fail(ctx, err, d_info, 2 * n + 2);
     }
     hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
     HGV_LAUNCH_CHECK();
 }
 
 template void hb2st_t<double2>(hgv_ctx_s *, int, int, const double2 *, int, double *, double *, double2 *, double2 *,
-                               Arena &);
+                               Arena &, int *);
 template void hb2st_t<float2>(hgv_ctx_s *, int, int, const float2 *, int, double *, double *, float2 *, float2 *,
-                              Arena &);
+                              Arena &, int *);
 
 // ---- Q2 back-transformation ------------------------------------------------------------------
 // Groups hold g <= b consecutive sweeps at one step j (any g <= b keeps every

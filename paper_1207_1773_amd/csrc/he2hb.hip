@@ -436,6 +436,7 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     zero_async(ctx, T1, (size_t)std::max(np, 1) * nb * nb);
     hipLaunchKernelGGL(fill_int_kernel, dim3(cdiv(Gmax + 1, 256)), dim3(256), 0, ctx->stream, flags, Gmax + 1, 0);
     HGV_LAUNCH_CHECK();
+    if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, flags + Gmax, 1);
     const int capacity = ctx->concurrent ? 0 : panel_persist_capacity<E>(ctx);
     // Look-ahead (the panel of step p + 1 factored while the update of step p
     // runs, as the paper overlaps its CPU panel with the GPU update): the

@@ -39,6 +39,11 @@ struct hgv_ctx_s {
     // reduction to standard form under its recursion (events 2, 3).
     hipStream_t la_stream[2] = {nullptr, nullptr};
     hipEvent_t la_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // Test hooks (hgv_test_hooks, HGV_TEST_* bits): HGV_TEST_WAIT_FAIL starts
+    // the give-up flags of the kernels with bounded waits set, so every wait
+    // returns at once and the stage reports d_info = 2n+2; HGV_TEST_NAN_RESIDUAL
+    // makes the mixed-precision refinement see a NaN residual.
+    int test_hooks = 0;
     int magic = 0x68677631;
 };
 
@@ -230,7 +235,8 @@ template <class E>
 void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
                 Arena &ar);
 template <class E>
-void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar);
+void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar,
+             int *d_info = nullptr);
 template <class E>
 void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
                 Arena &ar);
@@ -247,8 +253,8 @@ inline void he2hb_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double
     he2hb_t<double2>(ctx, n, nb, A, lda, T1, ar, d_info);
 }
 inline void hb2st_run(hgv_ctx_s *ctx, int n, int nb, const double2 *A, int lda, double *d, double *e,
-                      double2 *V2, double2 *tau2, Arena &ar) {
-    hb2st_t<double2>(ctx, n, nb, A, lda, d, e, V2, tau2, ar);
+                      double2 *V2, double2 *tau2, Arena &ar, int *d_info = nullptr) {
+    hb2st_t<double2>(ctx, n, nb, A, lda, d, e, V2, tau2, ar, d_info);
 }
 size_t v2_elems(int n, int nb);
 size_t v2_taus(int n, int nb);

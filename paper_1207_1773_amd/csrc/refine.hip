@@ -100,24 +100,34 @@ __global__ __launch_bounds__(256) void residual_kernel(int n, const double2 *AY,
     if (tid == 0) colres[j] = sqrt(part[0]);
 }
 
+__global__ void set_nan_kernel(double *p) { *p = __builtin_nan(""); }
+
+// max that propagates NaN (fmax drops it, which would let a NaN residual pass
+// the tolerance test)
+__device__ inline double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+
 // rho = max_j colres[j] / ||A'||_2 with ||A'||_2 estimated by the extreme
-// eigenvalues of the complex64 tridiagonal matrix; in fixed-iteration mode a
-// missed tolerance is reported through d_info.
+// eigenvalues of the complex64 tridiagonal matrix; a NaN residual, or a
+// failed Cholesky QR / projected eigensolve (*sub_info != 0), gives rho = NaN,
+// which never meets the tolerance.  In fixed-iteration mode a missed tolerance
+// is reported through d_info.
 __global__ __launch_bounds__(256) void rho_kernel(int m, const double *colres, const double *lam, int n,
-                                                  double *rho, double tol, int *d_info, int code) {
+                                                  double *rho, double tol, int *d_info, int code,
+                                                  const int *sub_info) {
     __shared__ double part[256];
     const int tid = threadIdx.x;
     double mx = 0.0;
-    for (int j = tid; j < m; j += 256) mx = fmax(mx, colres[j]);
+    for (int j = tid; j < m; j += 256) mx = nan_max(mx, colres[j]);
     part[tid] = mx;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) part[tid] = fmax(part[tid], part[tid + w]);
+        if (tid < w) part[tid] = nan_max(part[tid], part[tid + w]);
         __syncthreads();
     }
     if (tid == 0) {
         double an = fmax(fabs(lam[0]), fabs(lam[n - 1]));
         double r = part[0] / fmax(an, DBL_MIN);
+        if (*sub_info != 0) r = __builtin_nan("");
         rho[0] = r;
         if (code && d_info && !(r <= tol) && *d_info == 0) *d_info = code;
     }
@@ -237,6 +247,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
     double2 *ws = ar.take<double2>(wsb / sizeof(double2));
     float2 *T2c = ar.take<float2>(q2_t_elems(n, nb));   // Q2's T factors, built once
     const size_t mk1 = ar.mark();
+    if (run) set_info(ctx, info2, 0);
 
     auto gemm = [&](char opa, char opb, int gm, int gn, int gk, const double2 *a, int la, const double2 *b, int lb,
                     double2 *c, int lc, double2 alpha, double2 beta, int lower) {
@@ -263,7 +274,7 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
     if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
 
     if (tm) tm->begin(HGV_ST_HB2ST);
-    hb2st_t<float2>(ctx, n, nb, Ac, n, d, e, V2c, tau2c, ar);
+    hb2st_t<float2>(ctx, n, nb, Ac, n, d, e, V2c, tau2c, ar, d_info);
     ar.release(mk1);
     if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
 
@@ -386,9 +397,13 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
         ++rr;
         const bool last = iters >= max_iters;
         if (run) {
+            if (ctx->test_hooks & HGV_TEST_NAN_RESIDUAL) {
+                hipLaunchKernelGGL(set_nan_kernel, dim3(1), dim3(1), 0, ctx->stream, colres);
+                HGV_LAUNCH_CHECK();
+            }
             int code = (fixed_iters && last) ? 2 * n + 1 : 0;
             hipLaunchKernelGGL(rho_kernel, dim3(1), dim3(256), 0, ctx->stream, mw, colres, lam, n, rho_d, tol,
-                               d_info, code);
+                               d_info, code, info2);
             HGV_LAUNCH_CHECK();
         }
         if (!run) {

@@ -4,9 +4,8 @@
 // Split: T is torn into leaves of S <= 64 rows; at a boundary with coupling e
 // (rows q-1, q) T = diag(T1, T2) + rho v v^T with rho = |e| and
 // v = e_{q-1} + sign(e) e_q, so |e| is subtracted from d_{q-1} and d_q.
-// Leaves: implicit QL with shifts, one workgroup per leaf (lane r keeps row r
-// of the leaf's eigenvector matrix; lane 0 runs the scalar chase and
-// publishes the rotations).
+// Leaves: cyclic Jacobi on the dense leaf block, one workgroup per leaf, the
+// disjoint rotations of a round applied in parallel.
 // Merge (the displayed identity of Sec. 4.3): with Z1, Z2 the children's
 // eigenvectors, T = diag(Z1, Z2) (diag(L1, L2) + rho u u^T) diag(Z1, Z2)^T,
 // u = [last row of Z1, sign(e) * first row of Z2]; the rank-one problem
@@ -36,7 +35,7 @@
 
 namespace hgv {
 
-constexpr int DC_LEAF_MAX = 64;   // rows of a leaf: one lane per row
+constexpr int DC_LEAF_MAX = 64;   // rows of a leaf (held dense in LDS)
 
 // Leaf size: the fewest doublings that bring the leaves to at most 64 rows,
 // with n spread evenly over them, so that the merges at every level (above all
@@ -48,6 +47,16 @@ static int dc_leaf_size(int n) {
     int blocks = 1;
     while ((n + blocks - 1) / blocks > DC_LEAF_MAX) blocks *= 2;
     return (n + blocks - 1) / blocks;
+}
+
+// Sort key of an eigenvalue: NaN ordered above +inf, so that every ordering
+// below is total and the ranks always form a permutation (the index arrays
+// built from them stay in range whatever the input holds).
+__host__ __device__ inline double dkey(double v) { return v != v ? __builtin_huge_val() : v; }
+__host__ __device__ inline bool key_before(double a, int ia, double b, int ib) {
+    const double ka = dkey(a), kb = dkey(b);
+    const bool na = a != a, nb = b != b;
+    return ka < kb || (ka == kb && (na == nb ? ia < ib : nb));
 }
 
 struct MergeGeom {
@@ -82,100 +91,142 @@ struct DcArgs {
     int *colitem;
     double *Q;
     int c_lo, c_hi;   // columns built at this level (last level: wanted range)
+    int *info;        // device status (may be null): a secular root that did not converge
 };
 
 __host__ __device__ inline size_t qoff(int L, int p) { return (size_t)p * 4 * (size_t)L * L; }
 
 // ---- leaves -------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void dc_leaf_kernel(int n, int S, const double *d, const double *e, double *D,
-                                                     double *Z, int ldz, int *info) {
-    __shared__ double dl[64], el[64];
-    __shared__ double zr[64][65];
-    __shared__ double rc[64], rs[64];
-    __shared__ int rj[64];
-    __shared__ int ctl_nrot, ctl_done;
-    const int lane = threadIdx.x;
+// Each leaf block (S <= 64 rows, torn off its neighbours) is diagonalised by the
+// cyclic two-sided Jacobi method in one workgroup: the block is held dense in
+// LDS and every round applies N/2 disjoint plane rotations at once, the pairs
+// taken from a round-robin tournament (index 0 fixed, the others shifted one
+// place per round), so that a sweep of N-1 rounds rotates every pair once.
+// For a pair (p, q) the rotation [c s; -s c] with t = s/c the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq), zeroes a_pq
+// (Golub & Van Loan, Matrix Computations, Sec. 8.5).  A pair is skipped when
+// |a_pq| <= eps sqrt(|a_pp| |a_qq|) (the relative test of Demmel and Veselic,
+// SIAM J. Matrix Anal. Appl. 13 (1992)); the sweeps stop when a whole sweep
+// skips every pair.  Since the rotations of a round are disjoint, A <- J^T A J
+// splits into independent 2 x 2 blocks (rows of pair a, columns of pair b),
+// one thread per block, and V <- V J into independent row pairs.
+constexpr int JAC_MAX_SWEEPS = 60;
+
+__global__ __launch_bounds__(256) void dc_leaf_kernel(int n, int S, const double *d, const double *e, double *D,
+                                                      double *Z, int ldz, int *info) {
+    __shared__ double Am[DC_LEAF_MAX][DC_LEAF_MAX + 1];
+    __shared__ double Vm[DC_LEAF_MAX][DC_LEAF_MAX + 1];
+    __shared__ double rc[DC_LEAF_MAX / 2], rs[DC_LEAF_MAX / 2];
+    __shared__ int rp[DC_LEAF_MAX / 2], rq[DC_LEAF_MAX / 2], rk[DC_LEAF_MAX / 2];
+    __shared__ int last_rot;   // last sweep that rotated a pair
+    __shared__ int rank[DC_LEAF_MAX];
+    const int tid = threadIdx.x;
     const int a = blockIdx.x * S;
     const int sz = min(S, n - a);
-    if (lane < sz) {
-        double dv = d[a + lane];
-        if (lane == 0 && a > 0) dv -= fabs(e[a - 1]);
-        if (lane == sz - 1 && a + sz < n) dv -= fabs(e[a + sz - 1]);
-        dl[lane] = dv;
-        el[lane] = (lane < sz - 1) ? e[a + lane] : 0.0;
+    const int N = sz + (sz & 1);   // even number of indices; index sz is a dummy when sz is odd
+    const int NP = N / 2;
+    for (int t = tid; t < DC_LEAF_MAX * DC_LEAF_MAX; t += 256) {
+        const int i = t % DC_LEAF_MAX, j = t / DC_LEAF_MAX;
+        double v = 0.0;
+        if (i < sz && j < sz) {
+            if (i == j) {
+                v = d[a + i];
+                // the tears of the neighbouring boundaries
+                if (i == 0 && a > 0) v -= fabs(e[a - 1]);
+                if (i == sz - 1 && a + sz < n) v -= fabs(e[a + sz - 1]);
+            } else if (i == j + 1) {
+                v = e[a + j];
+            } else if (j == i + 1) {
+                v = e[a + i];
+            }
+        }
+        Am[i][j] = v;
+        Vm[i][j] = (i == j) ? 1.0 : 0.0;
     }
-    for (int c = 0; c < sz; ++c) zr[lane][c] = (lane == c) ? 1.0 : 0.0;
-    int l = 0, steps = 0;   // lane 0's QL state
+    if (tid == 0) last_rot = -1;
     __syncthreads();
-    for (;;) {
-        if (lane == 0) {
-            int done = 0, nr = 0;
-            for (;;) {
-                if (l >= sz) { done = 1; break; }
-                int m = l;
-                while (m < sz - 1 && fabs(el[m]) > DBL_EPSILON * (fabs(dl[m]) + fabs(dl[m + 1]))) ++m;
-                if (m == l) { ++l; steps = 0; continue; }
-                if (steps++ >= 30) {
-                    if (info && *info == 0) *info = a + l + 1;
-                    done = 1;
-                    break;
-                }
-                // shift: eigenvalue of [d_l e_l; e_l d_{l+1}] nearest d_l
-                double del = 0.5 * (dl[l + 1] - dl[l]);
-                double rt = hypot(del, el[l]);
-                double sigma = dl[l] - el[l] * el[l] / (del + (del >= 0.0 ? rt : -rt));
-                double bulge = 0.0;
-                for (int jj = m - 1; jj >= l; --jj) {
-                    double x, y;
-                    if (jj == m - 1) { x = dl[m] - sigma; y = el[m - 1]; }
-                    else { x = el[jj + 1]; y = bulge; }
-                    double r = hypot(x, y);
-                    double c = (r == 0.0) ? 1.0 : x / r, s = (r == 0.0) ? 0.0 : y / r;
-                    if (jj != m - 1) el[jj + 1] = r;
-                    double a0 = dl[jj], b0 = el[jj], d0 = dl[jj + 1];
-                    dl[jj] = c * c * a0 - 2.0 * c * s * b0 + s * s * d0;
-                    dl[jj + 1] = s * s * a0 + 2.0 * c * s * b0 + c * c * d0;
-                    el[jj] = c * s * (a0 - d0) + (c * c - s * s) * b0;
-                    if (jj > l) {
-                        bulge = s * el[jj - 1];
-                        el[jj - 1] = c * el[jj - 1];
+    int sweep = 0;
+    for (; sweep < JAC_MAX_SWEEPS; ++sweep) {
+        for (int r = 0; r < N - 1; ++r) {
+            // ---- rotation of every pair of this round ----
+            if (tid < NP) {
+                const int x = (tid == 0) ? 0 : 1 + (tid - 1 + r) % (N - 1);
+                const int y = 1 + (N - 2 - tid + r) % (N - 1);
+                const int p = min(x, y), q = max(x, y);
+                double c = 1.0, s = 0.0;
+                int rot = 0;
+                if (q < sz) {
+                    const double apq = Am[p][q], app = Am[p][p], aqq = Am[q][q];
+                    if (fabs(apq) > DBL_EPSILON * sqrt(fabs(app)) * sqrt(fabs(aqq))) {
+                        const double tau = (aqq - app) / (2.0 * apq);
+                        // for |tau| so large that tau^2 would overflow, t = 1/(2 tau) to working precision
+                        const double t = fabs(tau) > 1e150 ? 0.5 / tau
+                                                           : copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                        rot = 1;
+                        last_rot = sweep;
                     }
-                    rj[nr] = jj; rc[nr] = c; rs[nr] = s;
-                    ++nr;
                 }
-                break;
+                rp[tid] = p;
+                rq[tid] = q;
+                rc[tid] = c;
+                rs[tid] = s;
+                rk[tid] = rot;
             }
-            ctl_nrot = nr;
-            ctl_done = done;
-        }
-        __syncthreads();
-        const int nr = ctl_nrot;
-        // apply this step's rotations to my row:  Z <- Z G^T
-        if (lane < sz) {
-            for (int t = 0; t < nr; ++t) {
-                int jj = rj[t];
-                double c = rc[t], s = rs[t];
-                double zj = zr[lane][jj], zj1 = zr[lane][jj + 1];
-                zr[lane][jj] = c * zj - s * zj1;
-                zr[lane][jj + 1] = s * zj + c * zj1;
+            __syncthreads();
+            // ---- A <- J^T A J by 2 x 2 blocks, V <- V J by row pairs ----
+            for (int t = tid; t < NP * NP; t += 256) {
+                const int ia = t % NP, ib = t / NP;
+                const int pa = rp[ia], qa = rq[ia], pb = rp[ib], qb = rq[ib];
+                const double ca = rc[ia], sa = rs[ia], cb = rc[ib], sb = rs[ib];
+                const double m00 = Am[pa][pb], m01 = Am[pa][qb], m10 = Am[qa][pb], m11 = Am[qa][qb];
+                const double t00 = ca * m00 - sa * m10, t01 = ca * m01 - sa * m11;
+                const double t10 = sa * m00 + ca * m10, t11 = sa * m01 + ca * m11;
+                double n00 = cb * t00 - sb * t01, n01 = sb * t00 + cb * t01;
+                double n10 = cb * t10 - sb * t11, n11 = sb * t10 + cb * t11;
+                if (ia == ib && rk[ia]) {
+                    // the rotated pair: exact zero off the diagonal
+                    const double tt = sa / ca;
+                    n00 = m00 - tt * m01;
+                    n11 = m11 + tt * m01;
+                    n01 = 0.0;
+                    n10 = 0.0;
+                }
+                Am[pa][pb] = n00;
+                Am[pa][qb] = n01;
+                Am[qa][pb] = n10;
+                Am[qa][qb] = n11;
             }
+            for (int t = tid; t < sz * NP; t += 256) {
+                const int i = t % sz, ib = t / sz;
+                const int pb = rp[ib], qb = rq[ib];
+                const double cb = rc[ib], sb = rs[ib];
+                const double vp = Vm[i][pb], vq = Vm[i][qb];
+                Vm[i][pb] = cb * vp - sb * vq;
+                Vm[i][qb] = sb * vp + cb * vq;
+            }
+            __syncthreads();
         }
-        bool stop = ctl_done != 0;
-        __syncthreads();
-        if (stop) break;
+        // no pair rotated in this sweep: converged.  (A thread that is already in
+        // the next sweep can only have raised last_rot further, so the test is
+        // the same in every thread.)
+        if (last_rot < sweep) break;
     }
-    // sort ascending (rank by counting, ties by index) and write D, Z
-    __shared__ int rank[64];
-    if (lane < sz) {
-        double v = dl[lane];
+    if (sweep == JAC_MAX_SWEEPS && tid == 0 && info) atomicCAS(info, 0, a + 1);
+    // ascending order (rank by counting, ties by index); D and the block of Z
+    if (tid < sz) {
+        const double v = Am[tid][tid];
         int r = 0;
-        for (int j = 0; j < sz; ++j) r += (dl[j] < v || (dl[j] == v && j < lane)) ? 1 : 0;
-        rank[lane] = r;
+        for (int j = 0; j < sz; ++j) r += key_before(Am[j][j], j, v, tid) ? 1 : 0;
+        rank[tid] = r;
         D[a + r] = v;
     }
     __syncthreads();
-    if (lane < sz)
-        for (int c = 0; c < sz; ++c) Z[(a + lane) + (size_t)(a + rank[c]) * ldz] = zr[lane][c];
+    for (int t = tid; t < sz * sz; t += 256) {
+        const int i = t % sz, c = t / sz;
+        Z[(a + i) + (size_t)(a + rank[c]) * ldz] = Vm[i][c];
+    }
 }
 
 // ---- merge steps ------------------------------------------------------------------------------
@@ -190,16 +241,17 @@ __global__ void dc_m1_kernel(DcArgs A) {
     double lam = A.D[g];
     double sig = (A.e[m.a + m.n1 - 1] >= 0.0) ? 1.0 : -1.0;
     double z = (x < m.n1) ? A.Zc[(m.a + m.n1 - 1) + (size_t)g * A.ldz] : sig * A.Zc[(m.a + m.n1) + (size_t)g * A.ldz];
+    // (each child is sorted by key_before; ties between the children go left first)
     int rank;
     if (x < m.n1) {   // count right entries strictly below lam
         const double *R = A.D + m.a + m.n1;
         int lo = 0, hi = m.n2;
-        while (lo < hi) { int mid = (lo + hi) >> 1; if (R[mid] < lam) lo = mid + 1; else hi = mid; }
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (key_before(R[mid], 1, lam, 0)) lo = mid + 1; else hi = mid; }
         rank = x + lo;
     } else {          // count left entries <= lam
         const double *Lf = A.D + m.a;
         int lo = 0, hi = m.n1;
-        while (lo < hi) { int mid = (lo + hi) >> 1; if (Lf[mid] <= lam) lo = mid + 1; else hi = mid; }
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (key_before(Lf[mid], 0, lam, 1)) lo = mid + 1; else hi = mid; }
         rank = (x - m.n1) + lo;
     }
     A.ds[m.a + rank] = lam;
@@ -416,13 +468,14 @@ __global__ void dc_m3_kernel(DcArgs A) {
     const double pL = dK[j] - dorg;                          // left pole (relative)
     const double pR = last ? 0.0 : dK[j + 1] - dorg;          // right pole (relative)
     double t = 0.5 * (lo + hi);
+    bool conv = false;
     for (int it = 0; it < 200; ++it) {
         double f, sl, sr, err;
         secular_eval(dK, zK, kp, dorg, rho, t, j, sub, f, sl, sr, err);
-        if (fabs(f) <= err) break;
+        if (fabs(f) <= err) { conv = true; break; }
         if (f < 0.0) lo = t;
         else hi = t;
-        if (hi - lo <= 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+        if (hi - lo <= 4.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) { conv = true; break; }
         double tn = 0.5 * (lo + hi);   // bisection fallback
         if ((it & 3) != 3) {
             // model weights from the derivatives at t
@@ -454,12 +507,16 @@ __global__ void dc_m3_kernel(DcArgs A) {
             }
             if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
         }
-        if (tn == t) break;
+        if (tn == t) { conv = true; break; }
         t = tn;
     }
     if (sub == 0) {
         A.org[m.a + j] = org;
         A.tau[m.a + j] = t;
+        // the iteration ran out without meeting a stopping test: report the root
+        // (its index in the merged block's order, 1-based) unless a failure is
+        // already recorded
+        if (!conv && A.info) atomicCAS(A.info, 0, m.a + j + 1);
     }
 }
 
@@ -526,7 +583,7 @@ __global__ void dc_m6_kernel(DcArgs A) {
     const double *iv = A.ival + m.a;
     double v = iv[x];
     int r = 0;
-    for (int y = sub; y < m.k; y += M3G) r += (iv[y] < v || (iv[y] == v && y < x)) ? 1 : 0;
+    for (int y = sub; y < m.k; y += M3G) r += key_before(iv[y], y, v, x) ? 1 : 0;
 #pragma unroll
     for (int o = 1; o < M3G; o <<= 1) r += __shfl_xor(r, o, M3G);
     if (sub == 0) {
@@ -669,7 +726,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
     if (ar.measuring() || n == 0) return;
 
     const int nleaf = cdiv(n, S);
-    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nleaf), dim3(64), 0, ctx->stream, n, S, d, e, D, Za, n, d_info);
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nleaf), dim3(256), 0, ctx->stream, n, S, d, e, D, Za, n, d_info);
     HGV_LAUNCH_CHECK();
     double *Zc = Za, *Zn = Zb;
     if (n <= S) {
@@ -690,6 +747,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         A.org = org; A.tau = tau; A.zh = zh; A.ival = ival; A.colitem = colitem; A.Q = Qb;
         A.c_lo = last ? il - 1 : 0;
         A.c_hi = last ? iu : 2 * L;
+        A.info = d_info;
         dim3 gN(cdiv(n, 256));
         hipLaunchKernelGGL(dc_m1_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();

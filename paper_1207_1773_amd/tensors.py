@@ -6,6 +6,7 @@ Matrices are handed to the library as column-major buffers.  A torch matrix M
 back as ``buf.mT``.  All arithmetic happens in the library; these helpers only copy,
 allocate and pass pointers.
 """
+import atexit
 import ctypes
 
 import torch
@@ -52,13 +53,23 @@ class Context:
             cls._cache[key] = Context(dev)
         return cls._cache[key]
 
-    def __del__(self):
-        h = getattr(self, "handle", None)
+    def close(self):
+        """Destroy the library context (its streams and events); idempotent."""
+        h, self.handle = getattr(self, "handle", None), None
         if h:
-            try:
-                hgv_destroy(h)
-            except Exception:
-                pass
+            hgv_destroy(h)
+
+    def __del__(self):
+        # never at interpreter shutdown: the cached contexts are closed by the
+        # atexit hook below while the HIP runtime is still fully up, and a
+        # context collected during finalisation would destroy streams after
+        # the runtime (or a profiler attached to it) has begun to shut down
+        if _closing:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def _sync_stream(self):
         hgv_set_stream(self.handle, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
@@ -98,7 +109,9 @@ class Context:
         np_ = (n + nb - 1) // nb
         T1 = torch.zeros((max(np_, 1), nb, nb), dtype=torch.complex128, device=self.device)
         w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_HE2HB, n, nb))
-        hgv_zhe2hb(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(w), w.numel())
+        info = self._info()
+        hgv_zhe2hb(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(w), w.numel(), _ptr(info))
+        self.last_info = info
         return from_colmajor(Ac), T1
 
     def hb2st(self, Aband, nb):
@@ -111,8 +124,10 @@ class Context:
         V2 = torch.zeros(max(hgv_v2_elems(n, nb), 1), dtype=torch.complex128, device=self.device)
         tau2 = torch.zeros(max(hgv_v2_taus(n, nb), 1), dtype=torch.complex128, device=self.device)
         w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_HB2ST, n, nb))
+        info = self._info()
         hgv_zhb2st(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(d), _ptr(e), _ptr(V2), _ptr(tau2), _ptr(w),
-                   w.numel())
+                   w.numel(), _ptr(info))
+        self.last_info = info
         return d[:n], e[:max(n - 1, 0)], V2, tau2
 
     def stedc(self, d, e, il=1, iu=None):
@@ -208,6 +223,25 @@ class Context:
         hgv_zhegvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
                    _ptr(w), w.numel(), opts, _ptr(info), st)
         return W[:m], from_colmajor(Xc)[:n, :m], int(info.item()), (st.as_dict() if st is not None else None)
+
+
+_closing = False
+
+
+@atexit.register
+def _close_cached_contexts():
+    """Destroy the cached contexts at exit, after the device has drained, before
+    the interpreter (and with it torch and the HIP runtime) shuts down."""
+    global _closing
+    _closing = True
+    for key, ctx in list(Context._cache.items()):
+        try:
+            with torch.cuda.device(ctx.device):
+                torch.cuda.synchronize()
+            ctx.close()
+        except Exception:
+            pass
+    Context._cache.clear()
 
 
 def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0):
