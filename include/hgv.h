@@ -69,6 +69,14 @@ typedef struct {
     double refine_tol;     /* HGV_MIXED only: target of max_i ||A'y_i -
                               theta_i y_i||_2 / ||A'||_2 (A' = L^-1 A L^-H);
                               0 -> 32 eps sqrt(n) */
+    int values_only;       /* 1: eigenvalues only (Sec. 1: a fraction of the
+                              spectrum; Sec. 4.3 builds only the needed vectors,
+                              here none): X is not referenced and may be NULL,
+                              the second-stage reflectors are not stored, the
+                              tridiagonal eigenvalues come from Sturm-count
+                              multisection (see hgv_dstebz) and neither back-
+                              transformation nor the back-substitution runs.
+                              HGV_FP64 only (HGV_MIXED -> HGV_E_NOTSUP). */
 } hgv_opts;
 
 /* Stage indices of hgv_stats.ms / flops. */
@@ -139,12 +147,34 @@ int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
  * not reach the tolerance the FP64 path recomputes the result.  While the
  * stream is being captured into a graph the iteration count is fixed
  * (max_refine_iters) and d_info = 2n+1 reports a missed tolerance.
+ * With opts->values_only only W is written (X may be NULL, ldx is ignored).
  * Argument numbers for -i: ctx 1, n 2, A 3, lda 4, B 5, ldb 6, il 7, iu 8,
  * W 9, X 10, ldx 11, work 12, work_bytes 13, opts 14. */
 int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
                int il, int iu, double *W, hgv_c128 *X, int ldx,
                void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
                hgv_stats *stats);
+
+/* ---- selection by value (LAPACK RANGE = 'V') ------------------------------- */
+/* The eigenpairs whose eigenvalues lie in the half-open interval (vl, vu]
+ * (Sec. 1: only a part of the spectrum is wanted).  After the reduction to the
+ * real tridiagonal T (Alg. 1 steps 1-2, Alg. 2 step 1) the index range is taken
+ * on the device from two Sturm counts of T, so nothing is read back to the host
+ * and the whole call can be captured in a HIP graph.  An eigenvalue within a
+ * few ulps of ||T|| of vl or vu may fall on either side.
+ *   mmax [in]   capacity of W (doubles) and X (columns), 1 <= mmax <= n.
+ *   d_m  [out]  device int: m, the number of eigenvalues in (vl, vu].  The
+ *               lowest min(m, mmax) pairs go to W[0..] and X[:, 0..]; the
+ *               remaining entries of W and columns of X (up to mmax) are set
+ *               to zero.  m > mmax means the output was truncated.
+ * Other arguments as hgv_zhegvx (opts->values_only: X may be NULL).
+ * HGV_MIXED is not supported (HGV_E_NOTSUP).  Argument numbers: ctx 1, n 2,
+ * A 3, lda 4, B 5, ldb 6, vl 7, vu 8, mmax 9, W 10, X 11, ldx 12, d_m 13,
+ * work 14, work_bytes 15, opts 16. */
+int hgv_zhegvx_range_bufsize(hgv_ctx_t ctx, int n, int mmax, const hgv_opts *opts, size_t *bytes);
+int hgv_zhegvx_range(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb, double vl,
+                     double vu, int mmax, double *W, hgv_c128 *X, int ldx, int *d_m, void *work,
+                     size_t work_bytes, const hgv_opts *opts, int *d_info, hgv_stats *stats);
 
 /* ---- batched solves ------------------------------------------------------- */
 /* Many independent pencils of uneven orders (Sec. 1: the paper's target
@@ -215,6 +245,17 @@ size_t hgv_v2_taus(int n, int nb);
 int hgv_dstedc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu,
                double *lambda, double *Z, int ldz, void *work, size_t work_bytes,
                int *d_info);
+
+/* Eigenvalues il..iu (1-based, ascending) of the real symmetric tridiagonal
+ * (d, e) into W[0 .. iu-il] by multisection on Sturm counts (the eigenvalue-
+ * only form of Alg. 2 step 2): each eigenvalue is bracketed independently by
+ * 16 lanes that evaluate the count of eigenvalues below 16 points of its
+ * interval per round, to an interval of width about 2 eps max|lambda| + eps
+ * ||T||.  work: hgv_dstebz_bufsize bytes, 256-byte aligned.  Argument
+ * numbers: ctx 1, n 2, d 3, e 4, il 5, iu 6, W 7, work 8. */
+int hgv_dstebz_bufsize(hgv_ctx_t ctx, int n, size_t *bytes);
+int hgv_dstebz(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W,
+               void *work, size_t work_bytes);
 
 /* Alg. 2 step 3, first part: Y <- Q2 Y (trans 'N') or Y <- Q2^H Y (trans 'C');
  * Y n x m complex, ldy >= n.  Argument numbers for -i: ctx 1, trans 2, n 3,

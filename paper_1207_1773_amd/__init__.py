@@ -30,7 +30,7 @@ EXPORTS = [
     "hgv_zhegst", "hgv_zhe2hb", "hgv_zhb2st", "hgv_v2_elems", "hgv_v2_taus", "hgv_dstedc",
     "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_device_peaks", "hgv_gauge_fix",
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
-    "hgv_test_hooks",
+    "hgv_test_hooks", "hgv_zhegvx_range_bufsize", "hgv_zhegvx_range", "hgv_dstebz_bufsize", "hgv_dstebz",
 ]
 HGV_TEST_WAIT_FAIL = 1
 HGV_TEST_NAN_RESIDUAL = 2
@@ -42,7 +42,8 @@ class c128(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int),
-                ("max_refine_iters", ctypes.c_int), ("refine_tol", ctypes.c_double)]
+                ("max_refine_iters", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("values_only", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -98,6 +99,11 @@ def load():
         "hgv_zhe2hb": (I, [P, I, I, P, I, P, P, SZ, P]),
         "hgv_zhb2st": (I, [P, I, I, P, I, P, P, P, P, P, SZ, P]),
         "hgv_test_hooks": (I, [P, I]),
+        "hgv_zhegvx_range_bufsize": (I, [P, I, I, ctypes.POINTER(Opts), ctypes.POINTER(SZ)]),
+        "hgv_zhegvx_range": (I, [P, I, P, I, P, I, ctypes.c_double, ctypes.c_double, I, P, P, I, P, P, SZ,
+                                 ctypes.POINTER(Opts), P, ctypes.POINTER(Stats)]),
+        "hgv_dstebz_bufsize": (I, [P, I, ctypes.POINTER(SZ)]),
+        "hgv_dstebz": (I, [P, I, P, P, I, I, P, P, SZ]),
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
         "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
@@ -190,6 +196,30 @@ def hgv_zhb2st(ctx, n, nb, A, lda, d, e, V2, tau2, work, work_bytes, d_info=None
 
 def hgv_test_hooks(ctx, mask):
     _check(load().hgv_test_hooks(ctx, mask), "hgv_test_hooks")
+
+
+def hgv_zhegvx_range_bufsize(ctx, n, mmax, opts=None):
+    out = SZ()
+    _check(load().hgv_zhegvx_range_bufsize(ctx, n, mmax, ctypes.byref(opts) if opts else None, ctypes.byref(out)),
+           "hgv_zhegvx_range_bufsize")
+    return out.value
+
+
+def hgv_zhegvx_range(ctx, n, A, lda, B, ldb, vl, vu, mmax, W, X, ldx, d_m, work, work_bytes, opts=None,
+                     d_info=None, stats=None):
+    _check(load().hgv_zhegvx_range(ctx, n, A, lda, B, ldb, vl, vu, mmax, W, X, ldx, d_m, work, work_bytes,
+                                   ctypes.byref(opts) if opts else None, d_info,
+                                   ctypes.byref(stats) if stats is not None else None), "hgv_zhegvx_range")
+
+
+def hgv_dstebz_bufsize(ctx, n):
+    out = SZ()
+    _check(load().hgv_dstebz_bufsize(ctx, n, ctypes.byref(out)), "hgv_dstebz_bufsize")
+    return out.value
+
+
+def hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes):
+    _check(load().hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes), "hgv_dstebz")
 
 
 def hgv_v2_elems(n, nb):

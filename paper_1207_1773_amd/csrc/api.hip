@@ -56,15 +56,48 @@ __global__ void copy_doubles_kernel(int n, const double *a, double *b) {
     if (i < n) b[i] = a[i];
 }
 
+// W[s] = lambda[range[0] - 1 + s] for s < range[2], 0 for the other slots.
+__global__ void select_vals_kernel(int nslot, const double *lambda, const int *range, double *W) {
+    int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < nslot) W[s] = s < range[2] ? lambda[range[0] - 1 + s] : 0.0;
+}
+
+__global__ void copy_int_kernel(const int *src, int *dst) { *dst = *src; }
+
 }  // namespace
 
 namespace hgv {
 
 void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *X, int ldx,
-                   Arena &ar, int nb, int *d_info, StageTimer *tm) {
+                   Arena &ar, int nb, int *d_info, StageTimer *tm, const ValueRange *vr, bool values_only) {
     const int m = iu - il + 1;
     const int np = cdiv(n, nb);
     const size_t mk0 = ar.mark();
+    const double N = n, M = m;
+    if (values_only) {
+        // Band reduction and bulge chasing without keeping the second-stage
+        // reflectors, eigenvalues by Sturm-count multisection, no back-transformation.
+        double2 *T1 = ar.take<double2>((size_t)np * nb * nb);
+        double *d = ar.take<double>(n);
+        double *e = ar.take<double>(std::max(n - 1, 1));
+        const size_t mk = ar.mark();
+        if (tm) tm->begin(HGV_ST_HE2HB);
+        he2hb_run(ctx, n, nb, A, lda, T1, ar, d_info);
+        ar.release(mk);
+        if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
+        if (tm) tm->begin(HGV_ST_HB2ST);
+        hb2st_run(ctx, n, nb, A, lda, d, e, nullptr, nullptr, ar, d_info);
+        ar.release(mk);
+        if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+        if (tm) tm->begin(HGV_ST_STEDC);
+        if (vr) sturm_range_run(ctx, n, d, e, vr->vl, vr->vu, m, vr->range, ar);
+        ar.release(mk);
+        stebz_run(ctx, n, d, e, il, m, vr ? vr->range : nullptr, W, ar);
+        ar.release(mk);
+        if (tm) tm->end(HGV_ST_STEDC, 0.0);
+        ar.release(mk0);
+        return;
+    }
     double2 *T1 = ar.take<double2>((size_t)np * nb * nb);
     double *d = ar.take<double>(n);
     double *e = ar.take<double>(std::max(n - 1, 1));
@@ -75,7 +108,6 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     double *Z = ar.take<double>((size_t)n * m);
     const size_t mk = ar.mark();
     const bool run = !ar.measuring();
-    const double N = n, M = m;
 
     if (tm) tm->begin(HGV_ST_HE2HB);
     he2hb_run(ctx, n, nb, A, lda, T1, ar, d_info);
@@ -86,6 +118,10 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     hb2st_run(ctx, n, nb, A, lda, d, e, V2, tau2, ar, d_info);
     ar.release(mk);
     if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+    // selection by value: the index range from Sturm counts of T, on the device
+    if (vr) sturm_range_run(ctx, n, d, e, vr->vl, vr->vu, m, vr->range, ar);
+    ar.release(mk);
+    const int *d_range = vr ? vr->range : nullptr;
 
     // the T factors of Q2's reflector groups need only the bulge chasing's
     // reflectors: built on a side stream while the tridiagonal solver runs the
@@ -116,13 +152,17 @@ void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, d
     }
 
     if (tm) tm->begin(HGV_ST_STEDC);
-    if (side) stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info, build_t_side);
-    else stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info);
+    if (side) stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info, build_t_side, d_range);
+    else stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info, {}, d_range);
     if (side && !built) build_t_side();   // no merge level (n within one leaf)
     ar.release(mk);
     if (run) {
-        hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,
-                           lambda + (il - 1), W);
+        if (d_range)
+            hipLaunchKernelGGL(select_vals_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m, lambda,
+                               d_range, W);
+        else
+            hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,
+                               lambda + (il - 1), W);
         HGV_LAUNCH_CHECK();
         hipLaunchKernelGGL(real_to_complex_kernel, dim3(cdiv(n, 64), cdiv(m, 4)), dim3(256), 0, ctx->stream, n,
                            m, Z, n, X, ldx);
@@ -149,10 +189,12 @@ namespace {
 
 // Full solve (Algorithm 1 with the two-stage Algorithm 2): potrf and hegst in
 // FP64, the standard eigensolve in FP64 or mixed precision, x = L^-H y in
-// FP64.  Shared by the size query (arena without base) and the run.
+// FP64 (skipped for eigenvalues only).  With vr the pairs in (vl, vu] are
+// chosen on the device and il..iu only give the number of slots.  Shared by
+// the size query (arena without base) and the run.
 void zhegvx_full(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb, int il, int iu, double *W,
                  double2 *X, int ldx, Arena &ar, int nb, const hgv_opts *opts, int *d_info, StageTimer *tm,
-                 MixedResult *mres, bool fixed_iters) {
+                 MixedResult *mres, bool fixed_iters, const ValueRange *vr = nullptr) {
     const int m = iu - il + 1;
     const size_t mk = ar.mark();
     const bool run = !ar.measuring();
@@ -173,9 +215,10 @@ void zhegvx_full(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb
         mixed_standard(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, opts->max_refine_iters < 0 ? 0 : iters, tol,
                        fixed_iters, d_info, tm, mres ? mres : &local);
     } else {
-        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, tm);
+        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, tm, vr, opts && opts->values_only);
     }
     ar.release(mk);
+    if (opts && opts->values_only) return;
 
     if (tm) tm->begin(HGV_ST_TRSM);
     trsm_lh_run(ctx, n, m, B, ldb, X, ldx, ar);
@@ -262,6 +305,7 @@ int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
     *bytes = 0;
     if (n == 0) return HGV_OK;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -5;
+    if (opts && opts->values_only && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
     return guarded(ctx, [&]() {
         Arena ar;
         zhegvx_full(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts), opts,
@@ -283,11 +327,13 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
     if (ldb < nn) return -6;
     if (n > 0 && (il < 1 || il > n)) return -7;
     if (n > 0 && (iu < il || iu > n)) return -8;
+    const bool vals = opts && opts->values_only;
     if (n > 0 && !W) return -9;
-    if (n > 0 && !X) return -10;
-    if (ldx < nn) return -11;
+    if (n > 0 && !X && !vals) return -10;
+    if (!vals && ldx < nn) return -11;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
     if (opts && opts->nb < 0) return -14;
+    if (vals && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
     if (n == 0) return guarded(ctx, [&]() {
         set_info(ctx, d_info, 0);
         return HGV_OK;
@@ -611,7 +657,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
         const int nn = std::max(1, n[i]);
         if (n[i] < 0) return -3;
         if (lda[i] < nn || ldb[i] < nn || ldx[i] < nn) return -5;
-        if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || !X[i])) return -4;
+        if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || (!X[i] && !(opts && opts->values_only)))) return -4;
     }
     size_t need = 0;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
@@ -681,6 +727,113 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             HGV_HIP(hipEventRecord(ctx->side_ev[k], ctx->side[k]));
             HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));
         }
+        return HGV_OK;
+    });
+}
+
+// ---- selection by value ------------------------------------------------------------------
+static void zhegvx_range_plan(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb, double vl, double vu,
+                              int mmax, double *W, double2 *X, int ldx, int *d_m, Arena &ar, int nb,
+                              const hgv_opts *opts, int *d_info, StageTimer *tm) {
+    int *range = ar.take<int>(4);
+    ValueRange vr{vl, vu, range};
+    zhegvx_full(ctx, n, A, lda, B, ldb, 1, mmax, W, X, ldx, ar, nb, opts, d_info, tm, nullptr, true, &vr);
+    if (!ar.measuring()) {
+        hipLaunchKernelGGL(copy_int_kernel, dim3(1), dim3(1), 0, ctx->stream, range + 1, d_m);
+        HGV_LAUNCH_CHECK();
+    }
+}
+
+int hgv_zhegvx_range_bufsize(hgv_ctx_t ctx, int n, int mmax, const hgv_opts *opts, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && (mmax < 1 || mmax > n)) return -3;
+    if (!bytes) return -5;
+    *bytes = 0;
+    if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -4;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        zhegvx_range_plan(ctx, n, nullptr, n, nullptr, n, 0.0, 1.0, mmax, nullptr, nullptr, n, nullptr, ar,
+                          resolve_nb(n, opts), opts, nullptr, nullptr);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_zhegvx_range(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb, double vl, double vu,
+                     int mmax, double *W, hgv_c128 *X, int ldx, int *d_m, void *work, size_t work_bytes,
+                     const hgv_opts *opts, int *d_info, hgv_stats *stats) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    const int nn = std::max(1, n);
+    const bool vals = opts && opts->values_only;
+    if (n > 0 && !A) return -3;
+    if (lda < nn) return -4;
+    if (n > 0 && !B) return -5;
+    if (ldb < nn) return -6;
+    if (!(vl == vl)) return -7;
+    if (!(vu > vl)) return -8;
+    if (n > 0 && (mmax < 1 || mmax > n)) return -9;
+    if (n > 0 && !W) return -10;
+    if (n > 0 && !X && !vals) return -11;
+    if (!vals && ldx < nn) return -12;
+    if (!d_m) return -13;
+    if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -16;
+    if (opts && opts->nb < 0) return -16;
+    if (n == 0) return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        set_info(ctx, d_m, 0);
+        return HGV_OK;
+    });
+    size_t need = 0;
+    int st = hgv_zhegvx_range_bufsize(ctx, n, mmax, opts, &need);
+    if (st != HGV_OK) return st;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -14;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        StageTimer tm(ctx, stats);
+        Arena ar(work, work_bytes);
+        const int nb = resolve_nb(n, opts);
+        zhegvx_range_plan(ctx, n, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(B), ldb, vl, vu,
+                          mmax, W, reinterpret_cast<double2 *>(X), ldx, d_m, ar, nb, opts, d_info,
+                          stats ? &tm : nullptr);
+        if (stats) {
+            tm.finish();
+            stats->nb = nb;
+        }
+        return HGV_OK;
+    });
+}
+
+// ---- tridiagonal eigenvalues by Sturm counts --------------------------------------------
+int hgv_dstebz_bufsize(hgv_ctx_t ctx, int n, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (!bytes) return -3;
+    Arena ar;
+    stebz_run(ctx, n, nullptr, nullptr, 1, n, nullptr, nullptr, ar);
+    *bytes = ar.peak + 256;
+    return HGV_OK;
+}
+
+int hgv_dstebz(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W, void *work,
+               size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && !d) return -3;
+    if (n > 1 && !e) return -4;
+    if (n > 0 && (il < 1 || il > n)) return -5;
+    if (n > 0 && (iu < il || iu > n)) return -6;
+    if (n > 0 && !W) return -7;
+    if (n == 0) return HGV_OK;
+    size_t need = 0;
+    hgv_dstebz_bufsize(ctx, n, &need);
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -8;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        stebz_run(ctx, n, d, e, il, iu - il + 1, nullptr, W, ar);
         return HGV_OK;
     });
 }

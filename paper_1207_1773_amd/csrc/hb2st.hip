@@ -296,8 +296,9 @@ __global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a) {
                     }
                 }
             }
-            // ---- store the reflector (group-major layout) and keep it for task j+1 -----
-            {
+            // ---- store the reflector (group-major layout; not kept when only
+            // eigenvalues are wanted) and keep it for task j+1 -----
+            if (a.V2) {
                 const int B = s / b, t = s % b;
                 size_t base = ((size_t)B * a.J + j) * b + t;
                 if (tid < b) a.V2[base * b + tid] = El<E>::from(v[tid]);
@@ -384,8 +385,10 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     hipLaunchKernelGGL(band_copy_kernel<E>, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB,
                        ldb);
     HGV_LAUNCH_CHECK();
-    zero2(ctx, V2, v2_elems(n, nb));
-    zero2(ctx, tau2, v2_taus(n, nb));
+    if (V2) {   // null: eigenvalues only, the reflectors are not stored
+        zero2(ctx, V2, v2_elems(n, nb));
+        zero2(ctx, tau2, v2_taus(n, nb));
+    }
     hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n + 1, 256)), dim3(256), 0, ctx->stream, prog, std::max(n, 1) + 1);
     HGV_LAUNCH_CHECK();
     if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, err, 1);

@@ -260,9 +260,28 @@ size_t v2_elems(int n, int nb);
 size_t v2_taus(int n, int nb);
 // at_last_level (may be empty) is called once, on the host, when the work of
 // the last merge level is about to be enqueued (not at all without merges).
+// d_range (device int[3], may be null): the wanted columns are chosen on the
+// device, range[0] = first index (1-based), range[2] = count; the m = iu-il+1
+// columns of Z are slots, those beyond range[2] are zeroed.
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu,
                double *lambda, double *Z, int ldz, Arena &ar, int *d_info,
-               const std::function<void()> &at_last_level = {});
+               const std::function<void()> &at_last_level = {}, const int *d_range = nullptr);
+
+// ---- eigenvalues by Sturm counts (stebz.hip) ------------------------------------------
+// W[s] = eigenvalue il + s (1-based, ascending) of T = (d, e) for s < nslot; with
+// d_range (device int[3]) the first index is range[0] and slots s >= range[2]
+// are zeroed.
+void stebz_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot, const int *d_range,
+               double *W, Arena &ar);
+// range[0] = 1 + #{eigenvalues <= vl}, range[1] = m = #{eigenvalues in (vl, vu]},
+// range[2] = min(m, mmax), from Sturm counts of T = (d, e) (device int[3]).
+void sturm_range_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, double vl, double vu, int mmax,
+                     int *d_range, Arena &ar);
+// A selection of eigenpairs by value: (vl, vu], at most mmax of them returned.
+struct ValueRange {
+    double vl, vu;
+    int *range;   // device int[3] (see sturm_range_run)
+};
 inline void unmtr_q2_run(hgv_ctx_s *ctx, int n, int nb, int m, const double2 *V2, const double2 *tau2,
                          double2 *Y, int ldy, Arena &ar) {
     unmtr_q2_t<double2>(ctx, n, nb, m, V2, tau2, Y, ldy, false, ar);
@@ -335,9 +354,14 @@ struct StageTimer {
 // Standard eigensolve of the lower triangle of A (n x n, destroyed) in FP64:
 // he2hb, hb2st, stedc for pairs il..iu, then Y = Q1 Q2 Z into Y (n x m).  The
 // eigenvalues il..iu go to W (device).  Used by the generalized solve, by the
-// Rayleigh-Ritz step of the refinement and as its fallback.
+// Rayleigh-Ritz step of the refinement and as its fallback.  With vr the
+// pairs are those in (vr->vl, vr->vu], chosen on the device (il..iu then only
+// give the number m of slots); with values_only Y is not referenced: no
+// second-stage reflectors are kept, the eigenvalues come from Sturm-count
+// multisection and nothing is back-transformed.
 void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
-                   Arena &ar, int nb, int *d_info, StageTimer *tm);
+                   Arena &ar, int nb, int *d_info, StageTimer *tm, const ValueRange *vr = nullptr,
+                   bool values_only = false);
 // Mixed precision standard eigensolve of A' (n x n, FP64, lower triangle;
 // kept intact unless the refinement falls back to standard_fp64): complex64
 // band reduction, bulge chasing and back-transforms, FP64 tridiagonal solve,

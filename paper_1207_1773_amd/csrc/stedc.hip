@@ -92,6 +92,8 @@ struct DcArgs {
     double *Q;
     int c_lo, c_hi;   // columns built at this level (last level: wanted range)
     int *info;        // device status (may be null): a secular root that did not converge
+    const int *range; // last level with a device-side selection (may be null):
+                      // range[0] = first wanted index (1-based), range[2] = columns built
 };
 
 __host__ __device__ inline size_t qoff(int L, int p) { return (size_t)p * 4 * (size_t)L * L; }
@@ -599,21 +601,34 @@ template <int KCAP>
 __global__ __launch_bounds__(256) void dc_m7_kernel(DcArgs A, int p_fixed) {
     __shared__ double col_s[KCAP > 0 ? KCAP : 1];
     __shared__ double red[256];
-    int p, col;
+    int p, col, slot;
+    bool unused = false;   // a slot beyond a device-side selection: zero column
     if (p_fixed >= 0) {
         p = p_fixed;
-        col = A.c_lo + blockIdx.x;
+        slot = blockIdx.x;
+        if (A.range) {
+            col = A.range[0] - 1 + slot;
+            unused = slot >= A.range[2];
+        } else {
+            col = A.c_lo + slot;
+        }
     } else {
         int g = blockIdx.x;
         p = g / (2 * A.L);
         col = g - p * 2 * A.L;
+        slot = col;
     }
     MergeGeom m = merge_geom(A.n, A.L, p);
-    if (m.n2 <= 0 || col >= m.k) return;
+    if (m.n2 <= 0) return;
     const int tid = threadIdx.x;
+    double *Qc = A.Q + qoff(A.L, p) + (size_t)slot * m.k;
+    if (unused) {
+        for (int i = tid; i < m.k; i += 256) Qc[i] = 0.0;
+        return;
+    }
+    if (col >= m.k) return;
     const int kp = A.kcnt[p];
     const int x = A.colitem[m.a + col];
-    double *Qc = A.Q + qoff(A.L, p) + (size_t)(col - (p_fixed >= 0 ? A.c_lo : 0)) * m.k;
     const int *perm = A.perm + m.a;
     // sorted-basis column: KCAP > 0 -> LDS; else written straight to permuted rows
     double inv = 1.0;
@@ -689,6 +704,15 @@ __global__ void dcopy_kernel(int n, const double *a, double *b) {
     if (i < n) b[i] = a[i];
 }
 
+// Z[:, j] = Zc[:, range[0] - 1 + j] for j < range[2], zero for the other slots.
+__global__ void dselect_cols_kernel(int n, int nslot, const double *Zc, int ldzc, const int *range, double *Z,
+                                    int ldz) {
+    int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= n || j >= nslot) return;
+    Z[i + (size_t)j * ldz] = j < range[2] ? Zc[i + (size_t)(range[0] - 1 + j) * ldzc] : 0.0;
+}
+
 static void dcopy2d(hgv_ctx_s *ctx, int m, int n, const double *A, int lda, double *B, int ldb) {
     if (m <= 0 || n <= 0) return;
     hipLaunchKernelGGL(dcopy2d_kernel, dim3(cdiv(m, 64), cdiv(n, 4)), dim3(256), 0, ctx->stream, m, n, A, lda, B, ldb);
@@ -696,7 +720,7 @@ static void dcopy2d(hgv_ctx_s *ctx, int m, int n, const double *A, int lda, doub
 }
 
 void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int iu, double *lambda, double *Z,
-               int ldz, Arena &ar, int *d_info, const std::function<void()> &at_last_level) {
+               int ldz, Arena &ar, int *d_info, const std::function<void()> &at_last_level, const int *d_range) {
     const int S = dc_leaf_size(n);
     const int m = iu - il + 1;
     // Q buffer: the largest level's sum of k^2 with offsets p * 4 L^2
@@ -730,7 +754,13 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
     HGV_LAUNCH_CHECK();
     double *Zc = Za, *Zn = Zb;
     if (n <= S) {
-        dcopy2d(ctx, n, m, Zc + (size_t)(il - 1) * n, n, Z, ldz);
+        if (d_range) {
+            hipLaunchKernelGGL(dselect_cols_kernel, dim3(cdiv(n, 64), cdiv(m, 4)), dim3(256), 0, ctx->stream, n, m,
+                               Zc, n, d_range, Z, ldz);
+            HGV_LAUNCH_CHECK();
+        } else {
+            dcopy2d(ctx, n, m, Zc + (size_t)(il - 1) * n, n, Z, ldz);
+        }
         hipLaunchKernelGGL(dcopy_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, D, lambda);
         HGV_LAUNCH_CHECK();
         return;
@@ -748,6 +778,7 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
         A.c_lo = last ? il - 1 : 0;
         A.c_hi = last ? iu : 2 * L;
         A.info = d_info;
+        A.range = last ? d_range : nullptr;
         dim3 gN(cdiv(n, 256));
         hipLaunchKernelGGL(dc_m1_kernel, gN, dim3(256), 0, ctx->stream, A);
         HGV_LAUNCH_CHECK();

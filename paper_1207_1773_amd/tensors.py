@@ -11,6 +11,7 @@ import ctypes
 
 import torch
 
+from . import (hgv_dstebz, hgv_dstebz_bufsize, hgv_zhegvx_range, hgv_zhegvx_range_bufsize)
 from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HGV_ST_POTRF, HGV_ST_Q1,
                HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
                hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
@@ -148,6 +149,20 @@ class Context:
                    _ptr(info))
         return lam[:n], from_colmajor(Zc)[:n, :m], int(info.item())
 
+    def stebz(self, d, e, il=1, iu=None):
+        """Eigenvalues il..iu of the tridiagonal (d, e) by Sturm-count multisection."""
+        self._sync_stream()
+        n = d.shape[0]
+        iu = n if iu is None else iu
+        dd = d.to(self.device, torch.float64).contiguous()
+        ee = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        if n > 1:
+            ee[:n - 1] = e[:n - 1]
+        W = torch.zeros(max(iu - il + 1, 1), dtype=torch.float64, device=self.device)
+        w = self._work(hgv_dstebz_bufsize(self.handle, n))
+        hgv_dstebz(self.handle, n, _ptr(dd), _ptr(ee), il, iu, _ptr(W), _ptr(w), w.numel())
+        return W[:iu - il + 1]
+
     def q2(self, V2, tau2, Y, nb, adj=False):
         """Alg. 2 step 3 (first part): Q2 Y (Q2^H Y with adj=True)."""
         self._sync_stream()
@@ -201,11 +216,12 @@ class Context:
 
     # ---- full solve ------------------------------------------------------------------------------
     def zhegvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, inplace=False, max_refine_iters=0,
-               refine_tol=0.0):
+               refine_tol=0.0, values_only=False):
         """Eigenpairs il..iu of (A, B).  Returns (W, X, info, stats_dict_or_None).
 
         precision "mixed" runs the complex64 reduction with FP64 refinement
         (max_refine_iters / refine_tol as in hgv_opts; 0 picks the defaults).
+        values_only=True computes the eigenvalues only (X is None).
         With inplace=True, A and B must already be column-major buffers (as made by
         ``colmajor``); they are then destroyed / overwritten by L."""
         self._sync_stream()
@@ -214,15 +230,39 @@ class Context:
         m = iu - il + 1
         Ac = A if inplace else colmajor(A)
         Bc = B if inplace else colmajor(B)
-        opts = _opts(precision, nb, max_refine_iters, refine_tol)
+        opts = _opts(precision, nb, max_refine_iters, refine_tol, values_only)
         W = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
-        Xc = torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex128, device=self.device)
+        Xc = None if values_only else torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex128, device=self.device)
         w = self._work(hgv_zhegvx_bufsize(self.handle, n, il, iu, opts))
         info = self._info()
         st = Stats() if stats else None
         hgv_zhegvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
                    _ptr(w), w.numel(), opts, _ptr(info), st)
-        return W[:m], from_colmajor(Xc)[:n, :m], int(info.item()), (st.as_dict() if st is not None else None)
+        X = None if values_only else from_colmajor(Xc)[:n, :m]
+        return W[:m], X, int(info.item()), (st.as_dict() if st is not None else None)
+
+    def zhegvx_range(self, A, B, vl, vu, mmax=None, nb=0, stats=False, inplace=False, values_only=False):
+        """Eigenpairs with eigenvalues in (vl, vu], at most mmax of them (default n).
+        Returns (W, X, m, info, stats): W and X hold min(m, mmax) pairs, m is the number
+        of eigenvalues in the interval (counted on the device)."""
+        self._sync_stream()
+        n = A.shape[0]
+        mmax = n if mmax is None else mmax
+        Ac = A if inplace else colmajor(A)
+        Bc = B if inplace else colmajor(B)
+        opts = _opts("fp64", nb, 0, 0.0, values_only)
+        W = torch.zeros(max(mmax, 1), dtype=torch.float64, device=self.device)
+        Xc = None if values_only else torch.zeros((max(mmax, 1), max(n, 1)), dtype=torch.complex128,
+                                                  device=self.device)
+        w = self._work(hgv_zhegvx_range_bufsize(self.handle, n, mmax, opts))
+        info = self._info()
+        dm = self._info()
+        st = Stats() if stats else None
+        hgv_zhegvx_range(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), float(vl), float(vu), mmax,
+                         _ptr(W), _ptr(Xc), max(n, 1), _ptr(dm), _ptr(w), w.numel(), opts, _ptr(info), st)
+        m = int(dm.item())
+        X = None if values_only else from_colmajor(Xc)[:n, :mmax]
+        return W[:mmax], X, m, int(info.item()), (st.as_dict() if st is not None else None)
 
 
 _closing = False
@@ -244,10 +284,11 @@ def _close_cached_contexts():
     Context._cache.clear()
 
 
-def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0):
+def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0, values_only=False):
     if precision not in ("fp64", "mixed"):
         raise ValueError("precision must be 'fp64' or 'mixed'")
-    return Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), int(max_refine_iters), float(refine_tol))
+    return Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), int(max_refine_iters), float(refine_tol),
+                int(bool(values_only)))
 
 
 class BatchedSolve:
