@@ -155,6 +155,34 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
                void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
                hgv_stats *stats);
 
+/* ---- other storage types ------------------------------------------------------ */
+/* Complex64 pencils (the paper's method for Hermitian pencils in single
+ * precision): every stage of hgv_zhegvx runs on complex64 storage with FP32
+ * MFMA GEMMs; the 64 x 64 factorisation leaves, the reflector norms and
+ * scalars and the tridiagonal divide and conquer run in FP64.  W in FP32.
+ * Accuracy is that of a complex64 solver (residual and B-orthogonality
+ * errors of order n * eps_fp32 * cond(B)).  Arguments as hgv_zhegvx (same
+ * numbers for -i), with complex64 A, B, X and float W; opts->precision must
+ * be HGV_FP64 (the default; HGV_MIXED -> HGV_E_NOTSUP: there is no
+ * refinement here); opts->values_only is supported. */
+int hgv_chegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts, size_t *bytes);
+int hgv_chegvx(hgv_ctx_t ctx, int n, hgv_c64 *A, int lda, hgv_c64 *B, int ldb, int il, int iu, float *W,
+               hgv_c64 *X, int ldx, void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
+               hgv_stats *stats);
+
+/* Real symmetric-definite pencils (A symmetric, B symmetric positive
+ * definite; the real case of the paper's Hermitian problem), FP64.  The pencil
+ * is solved by the complex-double path on complex copies with zero imaginary
+ * parts (held in the workspace); the solver's reflectors map real vectors onto
+ * real multiples of e_1, so its eigenvectors come out real and their real
+ * parts are returned.  On exit the lower triangle of B holds L.  Arguments as
+ * hgv_zhegvx (same numbers for -i), with real A, B, X; both precisions and
+ * opts->values_only are supported. */
+int hgv_dsygvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts, size_t *bytes);
+int hgv_dsygvx(hgv_ctx_t ctx, int n, double *A, int lda, double *B, int ldb, int il, int iu, double *W,
+               double *X, int ldx, void *work, size_t work_bytes, const hgv_opts *opts, int *d_info,
+               hgv_stats *stats);
+
 /* ---- selection by value (LAPACK RANGE = 'V') ------------------------------- */
 /* The eigenpairs whose eigenvalues lie in the half-open interval (vl, vu]
  * (Sec. 1: only a part of the spectrum is wanted).  After the reduction to the

@@ -31,6 +31,7 @@ EXPORTS = [
     "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_device_peaks", "hgv_gauge_fix",
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
     "hgv_test_hooks", "hgv_zhegvx_range_bufsize", "hgv_zhegvx_range", "hgv_dstebz_bufsize", "hgv_dstebz",
+    "hgv_chegvx_bufsize", "hgv_chegvx", "hgv_dsygvx_bufsize", "hgv_dsygvx",
 ]
 HGV_TEST_WAIT_FAIL = 1
 HGV_TEST_NAN_RESIDUAL = 2
@@ -103,6 +104,12 @@ def load():
         "hgv_zhegvx_range": (I, [P, I, P, I, P, I, ctypes.c_double, ctypes.c_double, I, P, P, I, P, P, SZ,
                                  ctypes.POINTER(Opts), P, ctypes.POINTER(Stats)]),
         "hgv_dstebz_bufsize": (I, [P, I, ctypes.POINTER(SZ)]),
+        "hgv_chegvx_bufsize": (I, [P, I, I, I, ctypes.POINTER(Opts), ctypes.POINTER(SZ)]),
+        "hgv_chegvx": (I, [P, I, P, I, P, I, I, I, P, P, I, P, SZ, ctypes.POINTER(Opts), P,
+                           ctypes.POINTER(Stats)]),
+        "hgv_dsygvx_bufsize": (I, [P, I, I, I, ctypes.POINTER(Opts), ctypes.POINTER(SZ)]),
+        "hgv_dsygvx": (I, [P, I, P, I, P, I, I, I, P, P, I, P, SZ, ctypes.POINTER(Opts), P,
+                           ctypes.POINTER(Stats)]),
         "hgv_dstebz": (I, [P, I, P, P, I, I, P, P, SZ]),
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
@@ -210,6 +217,32 @@ def hgv_zhegvx_range(ctx, n, A, lda, B, ldb, vl, vu, mmax, W, X, ldx, d_m, work,
     _check(load().hgv_zhegvx_range(ctx, n, A, lda, B, ldb, vl, vu, mmax, W, X, ldx, d_m, work, work_bytes,
                                    ctypes.byref(opts) if opts else None, d_info,
                                    ctypes.byref(stats) if stats is not None else None), "hgv_zhegvx_range")
+
+
+def hgv_chegvx_bufsize(ctx, n, il, iu, opts=None):
+    out = SZ()
+    _check(load().hgv_chegvx_bufsize(ctx, n, il, iu, ctypes.byref(opts) if opts else None, ctypes.byref(out)),
+           "hgv_chegvx_bufsize")
+    return out.value
+
+
+def hgv_chegvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes, opts=None, d_info=None, stats=None):
+    _check(load().hgv_chegvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes,
+                             ctypes.byref(opts) if opts else None, d_info,
+                             ctypes.byref(stats) if stats is not None else None), "hgv_chegvx")
+
+
+def hgv_dsygvx_bufsize(ctx, n, il, iu, opts=None):
+    out = SZ()
+    _check(load().hgv_dsygvx_bufsize(ctx, n, il, iu, ctypes.byref(opts) if opts else None, ctypes.byref(out)),
+           "hgv_dsygvx_bufsize")
+    return out.value
+
+
+def hgv_dsygvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes, opts=None, d_info=None, stats=None):
+    _check(load().hgv_dsygvx(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, work, work_bytes,
+                             ctypes.byref(opts) if opts else None, d_info,
+                             ctypes.byref(stats) if stats is not None else None), "hgv_dsygvx")
 
 
 def hgv_dstebz_bufsize(ctx, n):

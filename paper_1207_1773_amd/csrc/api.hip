@@ -367,6 +367,153 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
     });
 }
 
+// ---- complex64 and real front ends (variants.hip) --------------------------------------
+int hgv_chegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && (il < 1 || il > n)) return -3;
+    if (n > 0 && (iu < il || iu > n)) return -4;
+    if (!bytes) return -6;
+    *bytes = 0;
+    if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -5;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        chegvx_full(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts),
+                    opts && opts->values_only, nullptr, nullptr);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_chegvx(hgv_ctx_t ctx, int n, hgv_c64 *A, int lda, hgv_c64 *B, int ldb, int il, int iu, float *W, hgv_c64 *X,
+               int ldx, void *work, size_t work_bytes, const hgv_opts *opts, int *d_info, hgv_stats *stats) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    const int nn = std::max(1, n);
+    const bool vals = opts && opts->values_only;
+    if (n > 0 && !A) return -3;
+    if (lda < nn) return -4;
+    if (n > 0 && !B) return -5;
+    if (ldb < nn) return -6;
+    if (n > 0 && (il < 1 || il > n)) return -7;
+    if (n > 0 && (iu < il || iu > n)) return -8;
+    if (n > 0 && !W) return -9;
+    if (n > 0 && !X && !vals) return -10;
+    if (!vals && ldx < nn) return -11;
+    if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -14;
+    if (opts && opts->nb < 0) return -14;
+    if (n == 0) return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        return HGV_OK;
+    });
+    size_t need = 0;
+    int st = hgv_chegvx_bufsize(ctx, n, il, iu, opts, &need);
+    if (st != HGV_OK) return st;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -12;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        StageTimer tm(ctx, stats);
+        Arena ar(work, work_bytes);
+        const int nb = resolve_nb(n, opts);
+        chegvx_full(ctx, n, reinterpret_cast<float2 *>(A), lda, reinterpret_cast<float2 *>(B), ldb, il, iu, W,
+                    reinterpret_cast<float2 *>(X), ldx, ar, nb, vals, d_info, stats ? &tm : nullptr);
+        if (stats) {
+            tm.finish();
+            stats->nb = nb;
+        }
+        return HGV_OK;
+    });
+}
+
+// Real pencils: complex copies in the workspace, the complex-double solve,
+// real parts back (see variants.hip).
+static void dsygvx_plan(hgv_ctx_s *ctx, int n, double *A, int lda, double *B, int ldb, int il, int iu, double *W,
+                        double *X, int ldx, Arena &ar, int nb, const hgv_opts *opts, int *d_info, StageTimer *tm,
+                        MixedResult *mres, bool fixed) {
+    const int m = iu - il + 1;
+    const bool vals = opts && opts->values_only;
+    double2 *Az = ar.take<double2>((size_t)n * n);
+    double2 *Bz = ar.take<double2>((size_t)n * n);
+    double2 *Xz = vals ? nullptr : ar.take<double2>((size_t)n * m);
+    const bool run = !ar.measuring();
+    if (run) {
+        real_to_complex(ctx, n, n, A, lda, Az, n);
+        real_to_complex(ctx, n, n, B, ldb, Bz, n);
+    }
+    zhegvx_full(ctx, n, Az, n, Bz, n, il, iu, W, Xz, n, ar, nb, opts, d_info, tm, mres, fixed);
+    if (run) {
+        complex_real_part(ctx, n, n, Bz, n, B, ldb, true);
+        if (!vals) complex_real_part(ctx, n, m, Xz, n, X, ldx, false);
+    }
+}
+
+int hgv_dsygvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opts, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (n > 0 && (il < 1 || il > n)) return -3;
+    if (n > 0 && (iu < il || iu > n)) return -4;
+    if (!bytes) return -6;
+    *bytes = 0;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -5;
+    if (opts && opts->values_only && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        dsygvx_plan(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts), opts,
+                    nullptr, nullptr, nullptr, false);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_dsygvx(hgv_ctx_t ctx, int n, double *A, int lda, double *B, int ldb, int il, int iu, double *W, double *X,
+               int ldx, void *work, size_t work_bytes, const hgv_opts *opts, int *d_info, hgv_stats *stats) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    const int nn = std::max(1, n);
+    const bool vals = opts && opts->values_only;
+    if (n > 0 && !A) return -3;
+    if (lda < nn) return -4;
+    if (n > 0 && !B) return -5;
+    if (ldb < nn) return -6;
+    if (n > 0 && (il < 1 || il > n)) return -7;
+    if (n > 0 && (iu < il || iu > n)) return -8;
+    if (n > 0 && !W) return -9;
+    if (n > 0 && !X && !vals) return -10;
+    if (!vals && ldx < nn) return -11;
+    if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
+    if (opts && opts->nb < 0) return -14;
+    if (vals && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    if (n == 0) return guarded(ctx, [&]() {
+        set_info(ctx, d_info, 0);
+        return HGV_OK;
+    });
+    size_t need = 0;
+    int st = hgv_dsygvx_bufsize(ctx, n, il, iu, opts, &need);
+    if (st != HGV_OK) return st;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -12;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        HGV_HIP(hipStreamIsCapturing(ctx->stream, &cap));
+        StageTimer tm(ctx, stats);
+        Arena ar(work, work_bytes);
+        const int nb = resolve_nb(n, opts);
+        MixedResult mres;
+        dsygvx_plan(ctx, n, A, lda, B, ldb, il, iu, W, X, ldx, ar, nb, opts, d_info, stats ? &tm : nullptr, &mres,
+                    cap != hipStreamCaptureStatusNone);
+        if (stats) {
+            tm.finish();
+            stats->nb = nb;
+            stats->refine_iters = mres.iters;
+            stats->refine_resid = mres.rho;
+            stats->fallback = mres.fallback;
+        }
+        return HGV_OK;
+    });
+}
+
 // ---- stage entry points -----------------------------------------------------------
 static void stage_plan(hgv_ctx_s *ctx, int stage, int n, int nb, int m, Arena &ar) {
     switch (stage) {

@@ -218,6 +218,13 @@ struct StageTimer;
 void potrf_hegst_run(hgv_ctx_s *ctx, int n, double2 *B, int ldb, double2 *A, int lda, Arena &ar, int *d_info,
                      int info_offset, StageTimer *tm, double potrf_flops);
 void trsm_lh_run(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, double2 *X, int ldx, Arena &ar);
+// The same stages in the storage type E (double2 or float2; the 64 x 64 leaves
+// compute in FP64 whatever E is, the GEMMs run in E's precision).
+template <class E>
+void trsm_lh_t(hgv_ctx_s *ctx, int n, int m, const E *L, int ldl, E *X, int ldx, Arena &ar);
+template <class E>
+void potrf_hegst_t(hgv_ctx_s *ctx, int n, E *B, int ldb, E *A, int lda, Arena &ar, int *d_info, int info_offset,
+                   StageTimer *tm, double potrf_flops);
 // Triangular solves used by the recursive stages (L lower n x n):
 //   right_lc:  X <- X L^-H      (X m x n)
 //   left_ln:   X <- L^-1 X      (X n x m)
@@ -374,6 +381,16 @@ struct MixedResult {
 void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
                     Arena &ar, int nb, int max_iters, double tol, bool fixed_iters, int *d_info, StageTimer *tm,
                     MixedResult *res);
+
+// ---- other storage types (variants.hip) ---------------------------------------------
+// Complex64 generalized solve (every stage on complex64 storage, FP32 MFMA
+// GEMMs, FP64 leaves / reflector scalars / tridiagonal solve); W in FP32;
+// values_only: W only (X not referenced).
+void chegvx_full(hgv_ctx_s *ctx, int n, float2 *A, int lda, float2 *B, int ldb, int il, int iu, float *W, float2 *X,
+                 int ldx, Arena &ar, int nb, bool values_only, int *d_info, StageTimer *tm);
+// C = R (+ 0 i), n x m; R = Re C (lower triangle only when lower)
+void real_to_complex(hgv_ctx_s *ctx, int n, int m, const double *R, int lr, double2 *C, int lc);
+void complex_real_part(hgv_ctx_s *ctx, int n, int m, const double2 *C, int lc, double *R, int lr, bool lower);
 
 // ---- adjoint (adjoint.hip) --------------------------------------------------------
 void gauge_fix_run(hgv_ctx_s *ctx, int n, int m, double2 *X, int ldx);

@@ -11,7 +11,8 @@ import ctypes
 
 import torch
 
-from . import (hgv_dstebz, hgv_dstebz_bufsize, hgv_zhegvx_range, hgv_zhegvx_range_bufsize)
+from . import (hgv_chegvx, hgv_chegvx_bufsize, hgv_dstebz, hgv_dstebz_bufsize, hgv_dsygvx, hgv_dsygvx_bufsize,
+               hgv_zhegvx_range, hgv_zhegvx_range_bufsize)
 from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HGV_ST_POTRF, HGV_ST_Q1,
                HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
                hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
@@ -240,6 +241,43 @@ class Context:
                    _ptr(w), w.numel(), opts, _ptr(info), st)
         X = None if values_only else from_colmajor(Xc)[:n, :m]
         return W[:m], X, int(info.item()), (st.as_dict() if st is not None else None)
+
+    def chegvx(self, A, B, il=1, iu=None, nb=0, stats=False, values_only=False):
+        """Complex64 pencil: eigenpairs il..iu.  Returns (W float32, X complex64 or None, info, stats)."""
+        self._sync_stream()
+        n = A.shape[0]
+        iu = n if iu is None else iu
+        m = iu - il + 1
+        Ac, Bc = colmajor(A, torch.complex64), colmajor(B, torch.complex64)
+        opts = _opts("fp64", nb, 0, 0.0, values_only)
+        W = torch.zeros(max(m, 1), dtype=torch.float32, device=self.device)
+        Xc = None if values_only else torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex64, device=self.device)
+        w = self._work(hgv_chegvx_bufsize(self.handle, n, il, iu, opts))
+        info = self._info()
+        st = Stats() if stats else None
+        hgv_chegvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
+                   _ptr(w), w.numel(), opts, _ptr(info), st)
+        X = None if values_only else from_colmajor(Xc)[:n, :m]
+        return W[:m], X, int(info.item()), (st.as_dict() if st is not None else None)
+
+    def dsygvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, values_only=False):
+        """Real symmetric-definite pencil: eigenpairs il..iu.  Returns (W, X float64 or None, info,
+        stats, L) where L is the Cholesky factor left in B's lower triangle."""
+        self._sync_stream()
+        n = A.shape[0]
+        iu = n if iu is None else iu
+        m = iu - il + 1
+        Ac, Bc = colmajor(A, torch.float64), colmajor(B, torch.float64)
+        opts = _opts(precision, nb, 0, 0.0, values_only)
+        W = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
+        Xc = None if values_only else torch.zeros((max(m, 1), max(n, 1)), dtype=torch.float64, device=self.device)
+        w = self._work(hgv_dsygvx_bufsize(self.handle, n, il, iu, opts))
+        info = self._info()
+        st = Stats() if stats else None
+        hgv_dsygvx(self.handle, n, _ptr(Ac), max(n, 1), _ptr(Bc), max(n, 1), il, iu, _ptr(W), _ptr(Xc), max(n, 1),
+                   _ptr(w), w.numel(), opts, _ptr(info), st)
+        X = None if values_only else from_colmajor(Xc)[:n, :m]
+        return W[:m], X, int(info.item()), (st.as_dict() if st is not None else None), torch.tril(from_colmajor(Bc))
 
     def zhegvx_range(self, A, B, vl, vu, mmax=None, nb=0, stats=False, inplace=False, values_only=False):
         """Eigenpairs with eigenvalues in (vl, vu], at most mmax of them (default n).
