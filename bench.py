@@ -49,6 +49,123 @@ def gemm_traffic():
     return int(mb.group(1))
 
 
+def run_config1(ctx, dev, reps=3):
+    """n = 4096 GUE-like pencil (cond(B) = 1e3), all pairs, band width 64: seconds (median
+    of `reps` after a warm-up), algorithmic TFLOP/s and the accuracy on 2000 columns."""
+    import numpy as np
+    import torch
+    import paper_1207_1773_amd as hgv
+    from inputs import gue_pair
+    n = 4096
+    A, B = gue_pair(n, 1, cond_b=1e3, device=dev)
+    Ac0, Bc0 = hgv.colmajor(A), hgv.colmajor(B)
+    Ac, Bc = torch.empty_like(Ac0), torch.empty_like(Bc0)
+    times, r = [], None
+    for it in range(reps + 1):
+        Ac.copy_(Ac0)
+        Bc.copy_(Bc0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = ctx.zhegvx(Ac, Bc, 1, n, "fp64", 64, stats=True, inplace=True)
+        e1.record()
+        torch.cuda.synchronize()
+        if it > 0:
+            times.append(e0.elapsed_time(e1))
+    W, X, info, st = r
+    ms = float(np.median(times))
+    n1 = lambda M: float(M.abs().sum(0).max())
+    idx = torch.cat([torch.arange(1000), torch.arange(n - 1000, n)]).to(dev)
+    Xs, Ws = X[:, idx], W[idx].to(torch.complex128)
+    BX = B @ Xs
+    res = n1(A @ Xs - BX * Ws[None, :]) / (n * n1(A) * n1(Xs))
+    G = Xs.conj().T @ BX
+    orth = n1(G - torch.eye(G.shape[0], dtype=G.dtype, device=dev))
+    print("[bench] GUE n=4096 all pairs: %.1f ms" % ms, file=sys.stderr, flush=True)
+    return {"workload": "GUE-like pencil A=(G+G^H)/2, B=U diag(logspace(0,3,n)) U^H, n=4096, all pairs, FP64, nb=64",
+            "s": ms / 1e3, "tflops": solve_flops(n, n) / (ms * 1e-3) / 1e12, "info": info,
+            "stage_ms": {k: v for k, v in st["ms"].items() if v > 0},
+            "gemm_stage_ms": sum(st["ms"][k] for k in ("potrf", "hegst", "he2hb", "q2", "q1", "trsm")),
+            "residual": res, "orthogonality": orth, "orth_over_n": orth / n, "checked_columns": 2000,
+            "times_ms": times}
+
+
+def run_config3(ctx, dev, reps=3):
+    """Batched workload: 64 pencils, n uniform in [500, 3000], lowest 20 % of each, the whole
+    batch captured in one HIP graph (FP64 and mixed precision), against the same problems
+    solved one after another."""
+    import numpy as np
+    import torch
+    import paper_1207_1773_amd as hgv
+    from inputs import batch_problem, batch_sizes
+    sizes = batch_sizes()
+    il = [1] * len(sizes)
+    iu = [int(math.ceil(0.2 * n)) for n in sizes]
+    flops = sum(solve_flops(n, m) for n, m in zip(sizes, iu))
+    As, Bs = [], []
+    for i, n in enumerate(sizes):
+        A, B = batch_problem(i, n, device=dev)
+        As.append(A)
+        Bs.append(B)
+    nb = [hgv.hgv_default_nb(n) for n in sizes]
+    out = {"workload": "64 GUE-like pencils (cond(B)=1e2), n uniform in [500,3000], lowest 20%% of each; "
+                       "sum n^3 = %.3e" % sum(float(n) ** 3 for n in sizes),
+           "algorithmic_flops": flops}
+    for precision in ("fp64", "mixed"):
+        bs = hgv.tensors.BatchedSolve(ctx, As, Bs, il, iu, nb, precision=precision,
+                                      max_refine_iters=2 if precision == "mixed" else 0)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                bs.run()
+        torch.cuda.current_stream().wait_stream(side)
+        ctx._sync_stream()
+        times = []
+        for it in range(reps + 1):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            if it > 0:
+                times.append(e0.elapsed_time(e1))
+        Ws, Xs, infos = bs.results()
+        worst_res = worst_orth = 0.0
+        n1 = lambda M: float(M.abs().sum(0).max())
+        for i, n in enumerate(sizes):
+            BX = Bs[i] @ Xs[i]
+            res = n1(As[i] @ Xs[i] - BX * Ws[i].to(torch.complex128)[None, :]) / (n * n1(As[i]) * n1(Xs[i]))
+            G = Xs[i].conj().T @ BX
+            orth = n1(G - torch.eye(G.shape[0], dtype=G.dtype, device=dev)) / n
+            worst_res, worst_orth = max(worst_res, res), max(worst_orth, orth)
+        ms = float(np.median(times))
+        out[precision] = {"s": ms / 1e3, "tflops": flops / (ms * 1e-3) / 1e12, "times_ms": times,
+                          "infos_nonzero": int(sum(1 for x in infos if x != 0)),
+                          "max_residual": worst_res, "max_orth_over_n": worst_orth}
+        print("[bench] batched 64 pencils %s (one graph): %.1f ms" % (precision, ms), file=sys.stderr, flush=True)
+        del g, bs
+    # the same problems solved one after another (one call each, FP64)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i, n in enumerate(sizes):
+        ctx.zhegvx(As[i], Bs[i], il[i], iu[i], "fp64", nb[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    out["one_by_one_fp64"] = {"s": ms1 / 1e3, "tflops": flops / (ms1 * 1e-3) / 1e12,
+                              "note": "each call synchronises to read back d_info"}
+    out["batched_speedup_vs_one_by_one"] = ms1 / (out["fp64"]["s"] * 1e3)
+    print("[bench] 64 pencils one by one: %.1f ms" % ms1, file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +180,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured FP64 MFMA / copy peaks")
     ap.add_argument("--cpu-n", type=int, default=2560)
+    ap.add_argument("--no-values-only", action="store_true", help="skip the eigenvalues-only solve")
+    ap.add_argument("--no-config1", action="store_true", help="skip the n=4096 GUE-pencil solve")
+    ap.add_argument("--no-config3", action="store_true", help="skip the batched 64-pencil solve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a device buffer of this size 5 times and exit (HBM counter calibration)")
     args = ap.parse_args()
@@ -203,6 +323,31 @@ def main():
             rec["speedup_vs_fp64"] = base["s"] / rec["s"]
         mixed[key] = rec
 
+    # eigenvalues only (no second-stage reflectors, Sturm-count multisection, no back-transforms)
+    values_only = None
+    if not args.no_values_only:
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        Ac.copy_(Ac0)
+        Bc.copy_(Bc0)
+        e0.record()
+        rv = ctx.zhegvx(Ac, Bc, 1, n, "fp64", args.nb, stats=True, inplace=True, values_only=True)
+        e1.record()
+        torch.cuda.synchronize()
+        msv = e0.elapsed_time(e1)
+        Wv = rv[0].cpu().numpy()
+        values_only = {"m": n, "s": msv / 1e3, "info": rv[2],
+                       "stage_ms": {k: v for k, v in rv[3]["ms"].items() if v > 0},
+                       "max_rel_eig_err_vs_constructed": float(np.abs(Wv - D_sorted).max() / np.abs(D_sorted).max()),
+                       "speedup_vs_all_vectors": ms_per_step / msv}
+        print("[bench] eigenvalues only: %.1f ms" % msv, file=sys.stderr, flush=True)
+
+    del Ac, Bc, Ac0, Bc0, A, B, X
+    torch.cuda.empty_cache()
+    config1 = run_config1(ctx, dev) if not args.no_config1 else None
+    config3 = run_config3(ctx, dev) if not args.no_config3 else None
+
     # roofline denominators measured on this device (after the timed steps)
     peaks = None
     if not args.no_peaks:
@@ -261,6 +406,9 @@ def main():
         "accuracy": acc_main,
         "fractions": extra,
         "mixed": mixed,
+        "eigenvalues_only": values_only,
+        "config_gue_n4096": config1,
+        "config_batched_64": config3,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None, "traffic": gemm_traffic(),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE / WRITE_SIZE counters, copy-calibrated)",
