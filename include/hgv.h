@@ -285,6 +285,19 @@ int hgv_dstebz_bufsize(hgv_ctx_t ctx, int n, size_t *bytes);
 int hgv_dstebz(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W,
                void *work, size_t work_bytes);
 
+/* Allocation-free form of hgv_dstebz, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The multisection's scratch (e^2 and the bounds, at most
+ * HGV_DSTEBZ_NOALLOC_MAX + 64 doubles, 2 MiB) lives in a device array that the
+ * library holds on every device it runs on (its address is looked up by
+ * hgv_create) until the process ends; the caller passes only d, e and W.
+ * n <= HGV_DSTEBZ_NOALLOC_MAX, else -2.  Calls that overlap on one device
+ * (several streams or contexts at once) race on that array; calls in one
+ * stream are ordered.  Results equal hgv_dstebz's.  Argument numbers: ctx 1,
+ * n 2, d 3, e 4, il 5, iu 6, W 7. */
+#define HGV_DSTEBZ_NOALLOC_MAX 262144
+int hgv_dstebz_noalloc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W);
+
 /* Alg. 2 step 3, first part: Y <- Q2 Y (trans 'N') or Y <- Q2^H Y (trans 'C');
  * Y n x m complex, ldy >= n.  Argument numbers for -i: ctx 1, trans 2, n 3,
  * nb 4, m 5, V2 6, tau2 7, Y 8, ldy 9, work 10. */

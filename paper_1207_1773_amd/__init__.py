@@ -31,8 +31,9 @@ EXPORTS = [
     "hgv_zunmtr_q2", "hgv_zunmtr_q1", "hgv_ztrsm_lh", "hgv_zgemm", "hgv_device_peaks", "hgv_gauge_fix",
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
     "hgv_test_hooks", "hgv_zhegvx_range_bufsize", "hgv_zhegvx_range", "hgv_dstebz_bufsize", "hgv_dstebz",
-    "hgv_chegvx_bufsize", "hgv_chegvx", "hgv_dsygvx_bufsize", "hgv_dsygvx",
+    "hgv_chegvx_bufsize", "hgv_chegvx", "hgv_dsygvx_bufsize", "hgv_dsygvx", "hgv_dstebz_noalloc",
 ]
+HGV_DSTEBZ_NOALLOC_MAX = 262144
 HGV_TEST_WAIT_FAIL = 1
 HGV_TEST_NAN_RESIDUAL = 2
 
@@ -111,6 +112,7 @@ def load():
         "hgv_dsygvx": (I, [P, I, P, I, P, I, I, I, P, P, I, P, SZ, ctypes.POINTER(Opts), P,
                            ctypes.POINTER(Stats)]),
         "hgv_dstebz": (I, [P, I, P, P, I, I, P, P, SZ]),
+        "hgv_dstebz_noalloc": (I, [P, I, P, P, I, I, P]),
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
         "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
@@ -253,6 +255,10 @@ def hgv_dstebz_bufsize(ctx, n):
 
 def hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes):
     _check(load().hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes), "hgv_dstebz")
+
+
+def hgv_dstebz_noalloc(ctx, n, d, e, il, iu, W):
+    _check(load().hgv_dstebz_noalloc(ctx, n, d, e, il, iu, W), "hgv_dstebz_noalloc")
 
 
 def hgv_v2_elems(n, nb):

@@ -235,6 +235,18 @@ int hgv_create(hgv_ctx_t *ctx, int device) {
     *ctx = nullptr;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return -2;
+    // the allocation-free entry point's device array: its address is looked up
+    // here, once per device, with that device current
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return HGV_E_HIP;
+    try {
+        if (hipSetDevice(device) != hipSuccess) return HGV_E_HIP;
+        stebz_scratch_init(device);
+    } catch (const HipFail &) {
+        (void)hipSetDevice(prev);
+        return HGV_E_HIP;
+    }
+    if (hipSetDevice(prev) != hipSuccess) return HGV_E_HIP;
     hgv_ctx_s *c = new (std::nothrow) hgv_ctx_s();
     if (!c) return HGV_E_HIP;
     c->device = device;
@@ -981,6 +993,21 @@ int hgv_dstebz(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, i
     return guarded(ctx, [&]() {
         Arena ar(work, work_bytes);
         stebz_run(ctx, n, d, e, il, iu - il + 1, nullptr, W, ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_dstebz_noalloc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0 || n > HGV_DSTEBZ_NOALLOC_MAX) return -2;
+    if (n > 0 && !d) return -3;
+    if (n > 1 && !e) return -4;
+    if (n > 0 && (il < 1 || il > n)) return -5;
+    if (n > 0 && (iu < il || iu > n)) return -6;
+    if (n > 0 && !W) return -7;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        stebz_noalloc_run(ctx, n, d, e, il, iu - il + 1, W);
         return HGV_OK;
     });
 }

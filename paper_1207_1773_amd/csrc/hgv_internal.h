@@ -280,6 +280,12 @@ void stedc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, 
 // are zeroed.
 void stebz_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot, const int *d_range,
                double *W, Arena &ar);
+// The same with its scratch in a file-scope device array (no workspace):
+// n <= STEBZ_NOALLOC_MAX; stebz_scratch_init looks the array's address up once
+// per device (the device must be current).
+constexpr int STEBZ_NOALLOC_MAX = HGV_DSTEBZ_NOALLOC_MAX;
+void stebz_scratch_init(int device);
+void stebz_noalloc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot, double *W);
 // range[0] = 1 + #{eigenvalues <= vl}, range[1] = m = #{eigenvalues in (vl, vu]},
 // range[2] = min(m, mmax), from Sturm counts of T = (d, e) (device int[3]).
 void sturm_range_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, double vl, double vu, int mmax,

@@ -20,6 +20,8 @@
 // One round shrinks the interval 17-fold, so about 14 rounds reach eps ||T||
 // from the Gershgorin interval, where bisection needs 53.
 #include <cfloat>
+#include <mutex>
+#include <vector>
 
 #include "hgv_internal.h"
 
@@ -157,16 +159,59 @@ void tri_prep(hgv_ctx_s *ctx, int n, const double *d, const double *e, double *e
     HGV_LAUNCH_CHECK();
 }
 
+static void stebz_launch(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot,
+                         const int *d_range, double *W, double *e2, TriBounds *tb) {
+    if (n == 0 || nslot <= 0) return;
+    tri_prep(ctx, n, d, e, e2, tb);
+    hipLaunchKernelGGL(multisect_kernel, dim3(cdiv(nslot * MSG, 256)), dim3(256), 0, ctx->stream, n, d, e2, tb, il,
+                       nslot, d_range, W);
+    HGV_LAUNCH_CHECK();
+}
+
 void stebz_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot, const int *d_range,
                double *W, Arena &ar) {
     double *e2;
     TriBounds *tb;
     stebz_plan(n, ar, &e2, &tb);
-    if (ar.measuring() || n == 0 || nslot <= 0) return;
-    tri_prep(ctx, n, d, e, e2, tb);
-    hipLaunchKernelGGL(multisect_kernel, dim3(cdiv(nslot * MSG, 256)), dim3(256), 0, ctx->stream, n, d, e2, tb, il,
-                       nslot, d_range, W);
-    HGV_LAUNCH_CHECK();
+    if (ar.measuring()) return;
+    stebz_launch(ctx, n, d, e, il, nslot, d_range, W, e2, tb);
+}
+
+// ---- the allocation-free form -------------------------------------------------------------
+// The scratch of the multisection (e^2 and the bounds) in a file-scope device
+// array, so that a caller that cannot allocate (graph capture, serving loops)
+// passes only its inputs and outputs.  Each device holds its own copy; its
+// address is looked up once per device (stebz_scratch_init, from hgv_create
+// with the device current) and only that address is ever handed to kernels.
+// Every call on a device shares its copy: calls that overlap on one device
+// race (the array keeps whatever the last call left; tri_prep rewrites all of
+// it that a call reads).
+static __device__ __align__(256) double scratch[STEBZ_NOALLOC_MAX + 64];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<double *> scratch_ptr;   // per device, null until looked up
+}  // namespace
+
+void stebz_scratch_init(int device) {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if ((int)scratch_ptr.size() <= device) scratch_ptr.resize(device + 1, nullptr);
+    if (scratch_ptr[device]) return;
+    void *p = nullptr;
+    HGV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    scratch_ptr[device] = static_cast<double *>(p);
+}
+
+void stebz_noalloc_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, int il, int nslot, double *W) {
+    stebz_scratch_init(ctx->device);   // no-op after hgv_create
+    double *base;
+    {
+        std::lock_guard<std::mutex> lk(scratch_mu);
+        base = scratch_ptr[ctx->device];
+    }
+    // e^2 at the start, the bounds 256-byte aligned after STEBZ_NOALLOC_MAX doubles
+    TriBounds *tb = reinterpret_cast<TriBounds *>(base + STEBZ_NOALLOC_MAX);
+    stebz_launch(ctx, n, d, e, il, nslot, nullptr, W, base, tb);
 }
 
 void sturm_range_run(hgv_ctx_s *ctx, int n, const double *d, const double *e, double vl, double vu, int mmax,
