@@ -778,6 +778,95 @@ static int batch_nb(const int *nb, int i, int n) {
     return (nb && nb[i] > 0) ? nb[i] : hgv_default_nb(n, HGV_FP64);
 }
 
+// One problem of an FP64 batched solve.  The solve runs in three phases over
+// the whole batch: (A) per problem on the side streams: Cholesky, reduction to
+// standard form, band reduction, band copy for the bulge chasing; (B) one
+// grouped bulge-chasing kernel over the (problem, sweep) pairs of all problems;
+// (C) per problem on the side streams: tridiagonal solve (or the eigenvalues
+// alone), Q2, Q1, back-substitution.  The buffers that cross the phases are
+// taken first from the problem's workspace slice; each stage's own scratch
+// follows them and is released when the stage returns.
+struct BatchProb {
+    int n = 0, il = 1, iu = 1, nb = 32;
+    bool vals = false;
+    double2 *A = nullptr, *B = nullptr, *X = nullptr;
+    int lda = 1, ldb = 1, ldx = 1;
+    double *W = nullptr;
+    int *d_info = nullptr;
+    double2 *T1 = nullptr, *V2 = nullptr, *tau2 = nullptr, *T2 = nullptr;
+    double *d = nullptr, *e = nullptr, *lambda = nullptr, *Z = nullptr;
+    HbBatchProblem hb;
+    size_t mark = 0;
+};
+
+static void batch_take(BatchProb &p, Arena &ar) {
+    const int n = p.n, m = p.iu - p.il + 1;
+    p.T1 = ar.take<double2>((size_t)cdiv(n, p.nb) * p.nb * p.nb);
+    p.d = ar.take<double>(n);
+    p.e = ar.take<double>(std::max(n - 1, 1));
+    if (!p.vals) {
+        p.lambda = ar.take<double>(n);
+        p.V2 = ar.take<double2>(v2_elems(n, p.nb));
+        p.tau2 = ar.take<double2>(v2_taus(n, p.nb));
+        p.T2 = ar.take<double2>(q2_t_elems(n, p.nb));
+        p.Z = ar.take<double>((size_t)n * m);
+    }
+    hb2st_batch_plan<double2>(n, p.nb, ar, p.hb);
+    p.hb.V2 = p.V2;
+    p.hb.tau2 = p.tau2;
+    p.hb.d_info = p.d_info;
+    p.mark = ar.mark();
+}
+
+static void batch_phase_a(hgv_ctx_s *ctx, BatchProb &p, Arena &ar) {
+    const bool run = !ar.measuring();
+    if (run) set_info(ctx, p.d_info, 0);
+    potrf_hegst_run(ctx, p.n, p.B, p.ldb, p.A, p.lda, ar, p.d_info, p.n, nullptr, 0.0);
+    ar.release(p.mark);
+    he2hb_run(ctx, p.n, p.nb, p.A, p.lda, p.T1, ar, p.d_info);
+    ar.release(p.mark);
+    if (run) hb2st_batch_prep<double2>(ctx, p.hb, p.A, p.lda);
+}
+
+static void batch_phase_c(hgv_ctx_s *ctx, BatchProb &p, Arena &ar) {
+    const bool run = !ar.measuring();
+    const int n = p.n, m = p.iu - p.il + 1;
+    if (run) hb2st_batch_finish<double2>(ctx, p.hb, p.d, p.e);
+    if (p.vals) {
+        stebz_run(ctx, n, p.d, p.e, p.il, m, nullptr, p.W, ar);
+        ar.release(p.mark);
+        return;
+    }
+    if (run) q2_build_t<double2>(ctx, n, p.nb, p.V2, p.tau2, p.T2);
+    stedc_run(ctx, n, p.d, p.e, p.il, p.iu, p.lambda, p.Z, n, ar, p.d_info);
+    ar.release(p.mark);
+    if (run) {
+        hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,
+                           p.lambda + (p.il - 1), p.W);
+        HGV_LAUNCH_CHECK();
+        hipLaunchKernelGGL(real_to_complex_kernel, dim3(cdiv(n, 64), cdiv(m, 4)), dim3(256), 0, ctx->stream, n, m,
+                           p.Z, n, p.X, p.ldx);
+        HGV_LAUNCH_CHECK();
+        q2_apply_t<double2>(ctx, n, p.nb, m, p.V2, p.T2, p.X, p.ldx, false);
+    }
+    unmtr_q1_run(ctx, n, p.nb, m, p.A, p.lda, p.T1, p.X, p.ldx, ar);
+    ar.release(p.mark);
+    trsm_lh_run(ctx, n, m, p.B, p.ldb, p.X, p.ldx, ar);
+    ar.release(p.mark);
+}
+
+// Workspace of one problem of the grouped FP64 path (measured by running its
+// phases in planning mode).
+static size_t batch_prob_bytes(hgv_ctx_s *ctx, BatchProb p) {
+    Arena ar;
+    batch_take(p, ar);
+    batch_phase_a(ctx, p, ar);
+    batch_phase_c(ctx, p, ar);
+    return align256(ar.peak);
+}
+
+static bool batch_grouped(const hgv_opts *opts) { return !opts || opts->precision == HGV_FP64; }
+
 int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu, const int *nb,
                                const hgv_opts *opts, size_t *bytes) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
@@ -785,20 +874,31 @@ int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int
     if (batch > 0 && (!n || !il || !iu)) return -3;
     if (!bytes) return -8;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -7;
+    if (opts && opts->values_only && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
     *bytes = 0;
-    size_t total = 256;
+    size_t total = 512;   // the grouped path's give-up flag, then the problems' slices
     for (int i = 0; i < batch; ++i) {
         if (n[i] < 0) return -3;
         if (n[i] == 0) continue;
         if (il[i] < 1 || il[i] > n[i] || iu[i] < il[i] || iu[i] > n[i]) return -4;
         int b = batch_nb(nb, i, n[i]);
         if (b > 64) return -6;
-        hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
-        o.nb = b;
-        size_t need = 0;
-        int st = hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &need);
-        if (st != HGV_OK) return st;
-        total += align256(need);
+        if (batch_grouped(opts)) {
+            BatchProb p;
+            p.n = n[i]; p.il = il[i]; p.iu = iu[i]; p.nb = b; p.vals = opts && opts->values_only;
+            int st = guarded(ctx, [&]() {
+                total += batch_prob_bytes(ctx, p);
+                return HGV_OK;
+            });
+            if (st != HGV_OK) return st;
+        } else {
+            hgv_opts o = *opts;
+            o.nb = b;
+            size_t need = 0;
+            int st = hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &need);
+            if (st != HGV_OK) return st;
+            total += align256(need);
+        }
     }
     *bytes = total;
     return HGV_OK;
@@ -812,11 +912,12 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
     if (batch < 0) return -2;
     if (batch == 0) return HGV_OK;
     if (!n || !A || !lda || !B || !ldb || !il || !iu || !W || !X || !ldx) return -3;
+    const bool vals = opts && opts->values_only;
     for (int i = 0; i < batch; ++i) {
         const int nn = std::max(1, n[i]);
         if (n[i] < 0) return -3;
-        if (lda[i] < nn || ldb[i] < nn || ldx[i] < nn) return -5;
-        if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || (!X[i] && !(opts && opts->values_only)))) return -4;
+        if (lda[i] < nn || ldb[i] < nn || (!vals && ldx[i] < nn)) return -5;
+        if (n[i] > 0 && (!A[i] || !B[i] || !W[i] || (!X[i] && !vals))) return -4;
     }
     size_t need = 0;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
@@ -837,55 +938,103 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             }
             HGV_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
         }
+        const bool grouped = batch_grouped(opts);
+        char *base = static_cast<char *>(work);
+        int *err = reinterpret_cast<int *>(base);
         // workspace slices in problem order; problems dealt longest first to the
         // least loaded stream (estimated cost ~ n^3)
         std::vector<size_t> off(batch, 0);
-        size_t at = 0;
+        std::vector<BatchProb> probs(batch);
+        size_t at = 512;
         for (int i = 0; i < batch; ++i) {
             off[i] = at;
             if (n[i] == 0) continue;
-            hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
-            o.nb = batch_nb(nb, i, n[i]);
-            size_t b = 0;
-            (void)hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &b);
-            at += align256(b);
+            if (grouped) {
+                BatchProb &p = probs[i];
+                p.n = n[i]; p.il = il[i]; p.iu = iu[i]; p.nb = batch_nb(nb, i, n[i]); p.vals = vals;
+                at += batch_prob_bytes(ctx, p);
+            } else {
+                hgv_opts o = *opts;
+                o.nb = batch_nb(nb, i, n[i]);
+                size_t b = 0;
+                (void)hgv_zhegvx_bufsize(ctx, n[i], il[i], iu[i], &o, &b);
+                at += align256(b);
+            }
         }
         std::vector<int> order(batch);
         for (int i = 0; i < batch; ++i) order[i] = i;
         std::sort(order.begin(), order.end(), [&](int x, int y) { return n[x] > n[y]; });
-        std::vector<double> load(K, 0.0);
         hipStream_t user = ctx->stream;
-        HGV_HIP(hipEventRecord(ctx->fork_ev, user));
-        for (int k = 0; k < K; ++k) HGV_HIP(hipStreamWaitEvent(ctx->side[k], ctx->fork_ev, 0));
-        ctx->concurrent = true;
-        try {
-            for (int idx : order) {
-                int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-                load[k] += (double)n[idx] * n[idx] * n[idx];
-                ctx->stream = ctx->side[k];
+        // every problem of `order` on the least loaded side stream, then join
+        auto fan_out = [&](const std::function<void(int)> &body) {
+            std::vector<double> load(K, 0.0);
+            HGV_HIP(hipEventRecord(ctx->fork_ev, user));
+            for (int k = 0; k < K; ++k) HGV_HIP(hipStreamWaitEvent(ctx->side[k], ctx->fork_ev, 0));
+            ctx->concurrent = true;
+            try {
+                for (int idx : order) {
+                    int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                    load[k] += (double)n[idx] * n[idx] * n[idx];
+                    ctx->stream = ctx->side[k];
+                    body(idx);
+                }
+            } catch (...) {
+                ctx->stream = user;
+                ctx->concurrent = false;
+                throw;
+            }
+            ctx->stream = user;
+            ctx->concurrent = false;
+            for (int k = 0; k < K; ++k) {
+                HGV_HIP(hipEventRecord(ctx->side_ev[k], ctx->side[k]));
+                HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));
+            }
+        };
+        if (!grouped) {
+            fan_out([&](int idx) {
                 int *inf = d_info ? d_info + idx : nullptr;
                 if (n[idx] == 0) {
                     set_info(ctx, inf, 0);
-                    continue;
+                    return;
                 }
-                Arena ar(static_cast<char *>(work) + off[idx], work_bytes - off[idx]);
-                hgv_opts o = opts ? *opts : hgv_opts{HGV_FP64, 0, 0, 0.0};
+                Arena ar(base + off[idx], work_bytes - off[idx]);
+                hgv_opts o = *opts;
                 o.nb = batch_nb(nb, idx, n[idx]);
                 zhegvx_full(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx],
                             reinterpret_cast<double2 *>(B[idx]), ldb[idx], il[idx], iu[idx], W[idx],
                             reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, o.nb, &o, inf, nullptr, nullptr, true);
+            });
+            return HGV_OK;
+        }
+        std::vector<Arena> arenas;
+        arenas.reserve(batch);
+        for (int i = 0; i < batch; ++i) {
+            arenas.emplace_back(base + off[i], work_bytes - off[i]);
+            BatchProb &p = probs[i];
+            p.A = reinterpret_cast<double2 *>(A[i]); p.lda = lda[i];
+            p.B = reinterpret_cast<double2 *>(B[i]); p.ldb = ldb[i];
+            p.X = reinterpret_cast<double2 *>(X[i]); p.ldx = ldx[i];
+            p.W = W[i];
+            p.d_info = d_info ? d_info + i : nullptr;
+            if (n[i] > 0) batch_take(p, arenas[i]);
+        }
+        // (A) factorisations and band reductions
+        fan_out([&](int idx) {
+            if (n[idx] == 0) {
+                set_info(ctx, probs[idx].d_info, 0);
+                return;
             }
-        } catch (...) {
-            ctx->stream = user;
-            ctx->concurrent = false;
-            throw;
-        }
-        ctx->stream = user;
-        ctx->concurrent = false;
-        for (int k = 0; k < K; ++k) {
-            HGV_HIP(hipEventRecord(ctx->side_ev[k], ctx->side[k]));
-            HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));
-        }
+            batch_phase_a(ctx, probs[idx], arenas[idx]);
+        });
+        // (B) one grouped bulge chasing over every problem
+        std::vector<HbBatchProblem> hbs;
+        for (int i = 0; i < batch; ++i)
+            if (n[i] > 0) hbs.push_back(probs[i].hb);
+        hb2st_batch_run<double2>(ctx, hbs, err);
+        // (C) tridiagonal solves and back-transformations
+        fan_out([&](int idx) {
+            if (n[idx] > 0) batch_phase_c(ctx, probs[idx], arenas[idx]);
+        });
         return HGV_OK;
     });
 }

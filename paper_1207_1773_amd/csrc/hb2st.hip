@@ -56,6 +56,37 @@ struct HbArgs {
 
 __host__ __device__ inline int hb_tasks(int n, int b, int s) { return (n - 2 - s) / b + 1; }
 
+// The problems of one grouped launch (batched solves), passed by value, sorted
+// by order n descending (every n >= 2).  Item k of the launch is sweep s of the
+// r-th problem, items ordered by s, then problem: with
+// off(s) = sum_p min(s, n_p - 1) items of sweep index below s, s is the largest
+// index with off(s) <= k and r = k - off(s) (the problems with a sweep s are the
+// first ones of the sorted list).
+constexpr int HB_BATCH_MAX = 32;
+template <class E>
+struct HbBatch {
+    int np, nmax, nitems;
+    HbArgs<E> p[HB_BATCH_MAX];
+};
+
+template <class E>
+__device__ inline int hb_batch_off(const HbBatch<E> &bt, int s) {
+    int o = 0;
+    for (int i = 0; i < bt.np; ++i) o += min(s, bt.p[i].n - 1);
+    return o;
+}
+
+template <class E>
+__device__ inline int2 hb_batch_item(const HbBatch<E> &bt, int k) {
+    int lo = 0, hi = bt.nmax - 2;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (hb_batch_off(bt, mid) <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    return make_int2(k - hb_batch_off(bt, lo), lo);
+}
+
 __device__ inline double wave_sum(double x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -80,8 +111,16 @@ __device__ inline double2 group_sum(double2 x) {
 //   E (rows I_j, columns I_{j-1}) lives in LDS because it is used by rows (the
 //   right application of the previous reflector) and then by columns (the
 //   left application of the new one).
-template <int BM, int NT, class E>
-__global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a) {
+//
+// BATCHED: the workgroups run the sweeps of many problems (the batched solve):
+// item k is sweep s of problem r (hb_batch_item); the items are ordered by
+// sweep index, then problem, and every workgroup takes its items in
+// increasing order.  A sweep waits only for the previous sweep of
+// its own problem, which has a smaller item index, so the smallest unfinished
+// item always has its predecessor done and its workgroup working on it: with
+// every workgroup resident (a cooperative launch) the grid always progresses.
+template <int BM, int NT, class E, bool BATCHED>
+__global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a0, HbBatch<E> bt) {
     constexpr int NWV = NT / 64;    // waves
     constexpr int TPR = NT / BM;    // lanes per row
     constexpr int NU = BM / TPR;    // row elements per lane
@@ -94,14 +133,19 @@ __global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a) {
     __shared__ double sh_beta;
     const int tid = threadIdx.x, lane = tid & 63;
     const int row = tid / TPR, q = tid % TPR;
-    const int n = a.n, b = a.b, ldb = a.ldb;
-    E *AB = a.AB;
     const double2 zero = make_double2(0.0, 0.0);
-    auto bld = [&](size_t idx) -> double2 { return El<E>::to(AB[idx]); };
-    auto bst = [&](size_t idx, double2 v) { AB[idx] = El<E>::from(v); };
     double2 Dr[NU];
+    const int total = BATCHED ? bt.nitems : a0.n - 1;
 
-    for (int s = blockIdx.x; s < n - 1; s += gridDim.x) {
+    for (int k = blockIdx.x; k < total; k += gridDim.x) {
+        int2 it = make_int2(0, k);
+        if constexpr (BATCHED) it = hb_batch_item(bt, k);
+        const HbArgs<E> a = BATCHED ? bt.p[it.x] : a0;
+        const int s = it.y;
+        const int n = a.n, b = a.b, ldb = a.ldb;
+        E *AB = a.AB;
+        auto bld = [&](size_t idx) -> double2 { return El<E>::to(AB[idx]); };
+        auto bst = [&](size_t idx, double2 v) { AB[idx] = El<E>::from(v); };
         const int nt = hb_tasks(n, b, s);
         for (int j = 0; j < nt; ++j) {
             // ---- wait for sweep s-1 ------------------------------------------------
@@ -364,13 +408,15 @@ template <int BM, int NT, class E>
 static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
     int dev = ctx->device, cus = 0, per = 0;
     HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM, NT, E>, NT, 0));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<BM, NT, E, false>, NT, 0));
     // a sweep starts two tasks behind its predecessor, so about J/2 sweeps are
     // in flight at once; more workgroups would only poll
     int G = std::max(1, std::min({cus * std::max(per, 1), a.n - 1, a.J / 2 + 4}));
-    void *args[] = {&a};
-    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM, NT, E>), dim3(G), dim3(NT), args, 0,
-                                       ctx->stream));
+    HbBatch<E> none;
+    none.np = none.nmax = none.nitems = 0;
+    void *args[] = {&a, &none};
+    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<BM, NT, E, false>), dim3(G), dim3(NT),
+                                       args, 0, ctx->stream));
 }
 
 template <class E>
@@ -403,6 +449,90 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
     HGV_LAUNCH_CHECK();
 }
+
+// ---- grouped bulge chasing of many problems (batched solves) ----------------------------------
+template <class E>
+void hb2st_batch_plan(int n, int nb, Arena &ar, HbBatchProblem &pb) {
+    pb.n = n;
+    pb.nb = nb;
+    pb.AB = ar.take<E>((size_t)2 * nb * std::max(n, 1));
+    pb.prog = ar.take<int>(std::max(n, 1));
+}
+
+template <class E>
+void hb2st_batch_prep(hgv_ctx_s *ctx, const HbBatchProblem &pb, const E *A, int lda) {
+    const int n = pb.n, nb = pb.nb, ldb = 2 * nb;
+    if (nb > 64) throw HipFail{hipErrorInvalidValue};
+    if (n == 0) return;
+    E *AB = static_cast<E *>(pb.AB);
+    hipLaunchKernelGGL(band_copy_kernel<E>, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, nb, A, lda, AB,
+                       ldb);
+    HGV_LAUNCH_CHECK();
+    if (pb.V2) {
+        zero2(ctx, static_cast<E *>(pb.V2), v2_elems(n, nb));
+        zero2(ctx, static_cast<E *>(pb.tau2), v2_taus(n, nb));
+    }
+    hipLaunchKernelGGL(zero_int_kernel, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, pb.prog, n);
+    HGV_LAUNCH_CHECK();
+}
+
+template <class E>
+void hb2st_batch_run(hgv_ctx_s *ctx, const std::vector<HbBatchProblem> &pbs, int *err) {
+    if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, err, 1);
+    else set_info(ctx, err, 0);
+    std::vector<int> order;
+    for (int i = 0; i < (int)pbs.size(); ++i)
+        if (pbs[i].n >= 2) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pbs[x].n > pbs[y].n; });
+    int cus = 0, per = 0;
+    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_kernel<64, 512, E, true>, 512, 0));
+    // the largest problems first, HB_BATCH_MAX per launch
+    for (size_t g0 = 0; g0 < order.size(); g0 += HB_BATCH_MAX) {
+        HbBatch<E> bt;
+        std::memset(&bt, 0, sizeof(bt));
+        bt.np = (int)std::min<size_t>(HB_BATCH_MAX, order.size() - g0);
+        long items = 0, inflight = 0;
+        for (int i = 0; i < bt.np; ++i) {
+            const HbBatchProblem &pb = pbs[order[g0 + i]];
+            HbArgs<E> &a = bt.p[i];
+            a.n = pb.n;
+            a.b = pb.nb;
+            a.ldb = 2 * pb.nb;
+            a.AB = static_cast<E *>(pb.AB);
+            a.V2 = static_cast<E *>(pb.V2);
+            a.tau2 = static_cast<E *>(pb.tau2);
+            a.prog = pb.prog;
+            a.err = err;
+            a.J = hb_J(pb.n, pb.nb);
+            items += pb.n - 1;
+            inflight += a.J / 2 + 4;
+        }
+        bt.nmax = bt.p[0].n;
+        bt.nitems = (int)items;
+        // about J/2 sweeps of each problem can be in flight at once
+        const int G = (int)std::max<long>(1, std::min<long>({(long)cus * std::max(per, 1), items, inflight}));
+        HbArgs<E> none{};
+        void *args[] = {&none, &bt};
+        HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_kernel<64, 512, E, true>), dim3(G), dim3(512),
+                                           args, 0, ctx->stream));
+    }
+    for (const HbBatchProblem &pb : pbs)
+        if (pb.n >= 2) report_wait_fail(ctx, err, pb.d_info, 2 * pb.n + 2);
+}
+
+template <class E>
+void hb2st_batch_finish(hgv_ctx_s *ctx, const HbBatchProblem &pb, double *d, double *e) {
+    if (pb.n == 0) return;
+    hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(pb.n, 256)), dim3(256), 0, ctx->stream, pb.n,
+                       static_cast<const E *>(pb.AB), 2 * pb.nb, d, e);
+    HGV_LAUNCH_CHECK();
+}
+
+template void hb2st_batch_plan<double2>(int, int, Arena &, HbBatchProblem &);
+template void hb2st_batch_prep<double2>(hgv_ctx_s *, const HbBatchProblem &, const double2 *, int);
+template void hb2st_batch_run<double2>(hgv_ctx_s *, const std::vector<HbBatchProblem> &, int *);
+template void hb2st_batch_finish<double2>(hgv_ctx_s *, const HbBatchProblem &, double *, double *);
 
 template void hb2st_t<double2>(hgv_ctx_s *, int, int, const double2 *, int, double *, double *, double2 *, double2 *,
                                Arena &, int *);

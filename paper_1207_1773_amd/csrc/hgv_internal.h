@@ -244,6 +244,26 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
 template <class E>
 void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar,
              int *d_info = nullptr);
+// Grouped bulge chasing of the problems of a batched solve: plan takes each
+// problem's band storage and progress counters from its arena; prep (on the
+// problem's stream) copies its band and clears its counters and reflectors;
+// run launches one persistent kernel over the (problem, sweep) pairs of up to
+// 32 problems at a time (on ctx->stream, after every prep has been joined) and
+// reports a given-up wait through each d_info; finish writes (d, e).
+struct HbBatchProblem {
+    int n = 0, nb = 0;
+    void *AB = nullptr, *V2 = nullptr, *tau2 = nullptr;
+    int *prog = nullptr;
+    int *d_info = nullptr;
+};
+template <class E>
+void hb2st_batch_plan(int n, int nb, Arena &ar, HbBatchProblem &pb);
+template <class E>
+void hb2st_batch_prep(hgv_ctx_s *ctx, const HbBatchProblem &pb, const E *A, int lda);
+template <class E>
+void hb2st_batch_run(hgv_ctx_s *ctx, const std::vector<HbBatchProblem> &pbs, int *err);
+template <class E>
+void hb2st_batch_finish(hgv_ctx_s *ctx, const HbBatchProblem &pb, double *d, double *e);
 template <class E>
 void unmtr_q2_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *V2, const E *tau2, E *Y, int ldy, bool adj,
                 Arena &ar);
