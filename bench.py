@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured FP64 MFMA / copy peaks")
     ap.add_argument("--cpu-n", type=int, default=2560)
     ap.add_argument("--no-values-only", action="store_true", help="skip the eigenvalues-only solve")
+    ap.add_argument("--no-one-stage", action="store_true", help="skip the one-stage solve")
     ap.add_argument("--no-config1", action="store_true", help="skip the n=4096 GUE-pencil solve")
     ap.add_argument("--no-config3", action="store_true", help="skip the batched 64-pencil solve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -343,6 +344,26 @@ def main():
                        "speedup_vs_all_vectors": ms_per_step / msv}
         print("[bench] eigenvalues only: %.1f ms" % msv, file=sys.stderr, flush=True)
 
+    # the one-stage tridiagonalisation (Sec. 4.1) as the comparison path, all pairs
+    one_stage = None
+    if not args.no_one_stage:
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        Ac.copy_(Ac0)
+        Bc.copy_(Bc0)
+        e0.record()
+        r1 = ctx.zhegvx(Ac, Bc, 1, n, "fp64", args.nb, stats=True, inplace=True, one_stage=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1)
+        one_stage = {"m": n, "s": ms1 / 1e3, "tflops": solve_flops(n, n) / (ms1 * 1e-3) / 1e12, "info": r1[2],
+                     "stage_ms": {k: v for k, v in r1[3]["ms"].items() if v > 0},
+                     "note": "he2hb = one-stage tridiagonalisation (hemv-based), q1 = its back-transformation",
+                     "accuracy": accuracy(r1[0], r1[1], n),
+                     "two_stage_speedup": ms1 / ms_per_step}
+        print("[bench] one-stage, all pairs: %.1f ms" % ms1, file=sys.stderr, flush=True)
+
     del Ac, Bc, Ac0, Bc0, A, B, X
     torch.cuda.empty_cache()
     config1 = run_config1(ctx, dev) if not args.no_config1 else None
@@ -407,6 +428,7 @@ def main():
         "fractions": extra,
         "mixed": mixed,
         "eigenvalues_only": values_only,
+        "one_stage_all_pairs": one_stage,
         "config_gue_n4096": config1,
         "config_batched_64": config3,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

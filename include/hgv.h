@@ -77,6 +77,11 @@ typedef struct {
                               multisection (see hgv_dstebz) and neither back-
                               transformation nor the back-substitution runs.
                               HGV_FP64 only (HGV_MIXED -> HGV_E_NOTSUP). */
+    int one_stage;         /* 1: one-stage tridiagonalisation (Sec. 4.1; hgv_zhetrd,
+                              hemv-based, bound by memory bandwidth) and one
+                              back-transformation (hgv_zunmtr_tr) in place of
+                              the two-stage reduction (Sec. 4.2); nb <= 64 is its
+                              panel width.  HGV_FP64 only. */
 } hgv_opts;
 
 /* Stage indices of hgv_stats.ms / flops. */
@@ -297,6 +302,25 @@ int hgv_dstebz(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, i
  * n 2, d 3, e 4, il 5, iu 6, W 7. */
 #define HGV_DSTEBZ_NOALLOC_MAX 262144
 int hgv_dstebz_noalloc(hgv_ctx_t ctx, int n, const double *d, const double *e, int il, int iu, double *W);
+
+/* One-stage tridiagonalisation (Sec. 4.1): A = Q T Q^H with T real symmetric
+ * tridiagonal (d[n], e[n-1]), by Householder reflectors H = I - tau v v^H with
+ * H^H x = beta e_1 (beta real), blocked by panels of nb <= 64 columns: per
+ * column a Hermitian matrix-vector product with the trailing matrix (its lower
+ * triangle read once), then a rank-2nb update per panel on the MFMA tiles.  On
+ * exit the reflector of column c sits in A below row c+1 (unit element at row
+ * c+1 implicit; A[c+1, c] holds e[c]) and T1 (ceil(n/nb) blocks of nb x nb)
+ * the compact-WY factors of each panel.  work: hgv_zhetrd_bufsize bytes.
+ * Argument numbers: ctx 1, n 2, nb 3, A 4, lda 5, d 6, e 7, T1 8, work 9. */
+int hgv_zhetrd_bufsize(hgv_ctx_t ctx, int n, int nb, size_t *bytes);
+int hgv_zhetrd(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, double *d, double *e, hgv_c128 *T1,
+               void *work, size_t work_bytes);
+/* Y <- Q Y (trans 'N') or Q^H Y (trans 'C') with Q from hgv_zhetrd (A, T1, nb
+ * as it left them); Y n x m.  work: hgv_stage_bufsize(HGV_ST_Q1, n, nb, m).
+ * Argument numbers: ctx 1, trans 2, n 3, nb 4, m 5, A 6, lda 7, T1 8, Y 9,
+ * ldy 10, work 11. */
+int hgv_zunmtr_tr(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *A, int lda,
+                  const hgv_c128 *T1, hgv_c128 *Y, int ldy, void *work, size_t work_bytes);
 
 /* Alg. 2 step 3, first part: Y <- Q2 Y (trans 'N') or Y <- Q2^H Y (trans 'C');
  * Y n x m complex, ldy >= n.  Argument numbers for -i: ctx 1, trans 2, n 3,

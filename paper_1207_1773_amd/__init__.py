@@ -32,6 +32,7 @@ EXPORTS = [
     "hgv_zhegvx_backward_bufsize", "hgv_zhegvx_backward", "hgv_zhegvx_batched_bufsize", "hgv_zhegvx_batched",
     "hgv_test_hooks", "hgv_zhegvx_range_bufsize", "hgv_zhegvx_range", "hgv_dstebz_bufsize", "hgv_dstebz",
     "hgv_chegvx_bufsize", "hgv_chegvx", "hgv_dsygvx_bufsize", "hgv_dsygvx", "hgv_dstebz_noalloc",
+    "hgv_zhetrd_bufsize", "hgv_zhetrd", "hgv_zunmtr_tr",
 ]
 HGV_DSTEBZ_NOALLOC_MAX = 262144
 HGV_TEST_WAIT_FAIL = 1
@@ -45,7 +46,7 @@ class c128(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int),
                 ("max_refine_iters", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("values_only", ctypes.c_int)]
+                ("values_only", ctypes.c_int), ("one_stage", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -113,6 +114,9 @@ def load():
                            ctypes.POINTER(Stats)]),
         "hgv_dstebz": (I, [P, I, P, P, I, I, P, P, SZ]),
         "hgv_dstebz_noalloc": (I, [P, I, P, P, I, I, P]),
+        "hgv_zhetrd_bufsize": (I, [P, I, I, ctypes.POINTER(SZ)]),
+        "hgv_zhetrd": (I, [P, I, I, P, I, P, P, P, P, SZ]),
+        "hgv_zunmtr_tr": (I, [P, ctypes.c_char, I, I, I, P, I, P, P, I, P, SZ]),
         "hgv_v2_elems": (SZ, [I, I]),
         "hgv_v2_taus": (SZ, [I, I]),
         "hgv_dstedc": (I, [P, I, P, P, I, I, P, P, I, P, SZ, P]),
@@ -255,6 +259,21 @@ def hgv_dstebz_bufsize(ctx, n):
 
 def hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes):
     _check(load().hgv_dstebz(ctx, n, d, e, il, iu, W, work, work_bytes), "hgv_dstebz")
+
+
+def hgv_zhetrd_bufsize(ctx, n, nb):
+    out = SZ()
+    _check(load().hgv_zhetrd_bufsize(ctx, n, nb, ctypes.byref(out)), "hgv_zhetrd_bufsize")
+    return out.value
+
+
+def hgv_zhetrd(ctx, n, nb, A, lda, d, e, T1, work, work_bytes):
+    _check(load().hgv_zhetrd(ctx, n, nb, A, lda, d, e, T1, work, work_bytes), "hgv_zhetrd")
+
+
+def hgv_zunmtr_tr(ctx, trans, n, nb, m, A, lda, T1, Y, ldy, work, work_bytes):
+    _check(load().hgv_zunmtr_tr(ctx, trans.encode() if isinstance(trans, str) else trans, n, nb, m, A, lda, T1, Y,
+                                ldy, work, work_bytes), "hgv_zunmtr_tr")
 
 
 def hgv_dstebz_noalloc(ctx, n, d, e, il, iu, W):

@@ -69,11 +69,59 @@ __global__ void copy_int_kernel(const int *src, int *dst) { *dst = *src; }
 namespace hgv {
 
 void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *X, int ldx,
-                   Arena &ar, int nb, int *d_info, StageTimer *tm, const ValueRange *vr, bool values_only) {
+                   Arena &ar, int nb, int *d_info, StageTimer *tm, const ValueRange *vr, bool values_only,
+                   bool one_stage) {
     const int m = iu - il + 1;
     const int np = cdiv(n, nb);
     const size_t mk0 = ar.mark();
     const double N = n, M = m;
+    if (one_stage) {
+        // Sec. 4.1: one-stage tridiagonalisation, then the tridiagonal solve and a
+        // single back-transformation (reported as the band-reduction and Q1 stages)
+        double2 *T1 = ar.take<double2>((size_t)np * nb * nb);
+        double *d = ar.take<double>(n);
+        double *e = ar.take<double>(std::max(n - 1, 1));
+        double *lambda = values_only ? nullptr : ar.take<double>(n);
+        double *Z = values_only ? nullptr : ar.take<double>((size_t)n * m);
+        const size_t mk = ar.mark();
+        const bool run = !ar.measuring();
+        if (tm) tm->begin(HGV_ST_HE2HB);
+        hetrd_run(ctx, n, nb, A, lda, d, e, T1, ar);
+        ar.release(mk);
+        if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
+        if (vr) sturm_range_run(ctx, n, d, e, vr->vl, vr->vu, m, vr->range, ar);
+        ar.release(mk);
+        const int *d_range = vr ? vr->range : nullptr;
+        if (tm) tm->begin(HGV_ST_STEDC);
+        if (values_only) {
+            stebz_run(ctx, n, d, e, il, m, d_range, W, ar);
+            ar.release(mk);
+            if (tm) tm->end(HGV_ST_STEDC, 0.0);
+            ar.release(mk0);
+            return;
+        }
+        stedc_run(ctx, n, d, e, il, iu, lambda, Z, n, ar, d_info, {}, d_range);
+        ar.release(mk);
+        if (run) {
+            if (d_range)
+                hipLaunchKernelGGL(select_vals_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m, lambda,
+                                   d_range, W);
+            else
+                hipLaunchKernelGGL(copy_doubles_kernel, dim3(cdiv(m, 256)), dim3(256), 0, ctx->stream, m,
+                                   lambda + (il - 1), W);
+            HGV_LAUNCH_CHECK();
+            hipLaunchKernelGGL(real_to_complex_kernel, dim3(cdiv(n, 64), cdiv(m, 4)), dim3(256), 0, ctx->stream, n,
+                               m, Z, n, X, ldx);
+            HGV_LAUNCH_CHECK();
+        }
+        if (tm) tm->end(HGV_ST_STEDC, 4.0 / 3.0 * N * N * N);
+        if (tm) tm->begin(HGV_ST_Q1);
+        unmtr_q1_t<double2>(ctx, n, nb, m, A, lda, T1, X, ldx, false, ar, 1);
+        ar.release(mk);
+        if (tm) tm->end(HGV_ST_Q1, 8.0 * N * N * M);
+        ar.release(mk0);
+        return;
+    }
     if (values_only) {
         // Band reduction and bulge chasing without keeping the second-stage
         // reflectors, eigenvalues by Sturm-count multisection, no back-transformation.
@@ -215,7 +263,8 @@ void zhegvx_full(hgv_ctx_s *ctx, int n, double2 *A, int lda, double2 *B, int ldb
         mixed_standard(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, opts->max_refine_iters < 0 ? 0 : iters, tol,
                        fixed_iters, d_info, tm, mres ? mres : &local);
     } else {
-        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, tm, vr, opts && opts->values_only);
+        standard_fp64(ctx, n, A, lda, il, iu, W, X, ldx, ar, nb, d_info, tm, vr, opts && opts->values_only,
+                      opts && opts->one_stage);
     }
     ar.release(mk);
     if (opts && opts->values_only) return;
@@ -318,6 +367,7 @@ int hgv_zhegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
     if (n == 0) return HGV_OK;
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -5;
     if (opts && opts->values_only && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    if (opts && opts->one_stage && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
     return guarded(ctx, [&]() {
         Arena ar;
         zhegvx_full(ctx, n, nullptr, n, nullptr, n, il, iu, nullptr, nullptr, n, ar, resolve_nb(n, opts), opts,
@@ -346,6 +396,8 @@ int hgv_zhegvx(hgv_ctx_t ctx, int n, hgv_c128 *A, int lda, hgv_c128 *B, int ldb,
     if (opts && opts->precision != HGV_FP64 && opts->precision != HGV_MIXED) return -14;
     if (opts && opts->nb < 0) return -14;
     if (vals && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    if (opts && opts->one_stage && opts->precision == HGV_MIXED) return HGV_E_NOTSUP;
+    if (opts && opts->one_stage && opts->nb > 64) return -14;
     if (n == 0) return guarded(ctx, [&]() {
         set_info(ctx, d_info, 0);
         return HGV_OK;
@@ -388,6 +440,7 @@ int hgv_chegvx_bufsize(hgv_ctx_t ctx, int n, int il, int iu, const hgv_opts *opt
     if (!bytes) return -6;
     *bytes = 0;
     if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -5;
+    if (opts && opts->one_stage) return HGV_E_NOTSUP;
     if (n == 0) return HGV_OK;
     return guarded(ctx, [&]() {
         Arena ar;
@@ -415,6 +468,7 @@ int hgv_chegvx(hgv_ctx_t ctx, int n, hgv_c64 *A, int lda, hgv_c64 *B, int ldb, i
     if (!vals && ldx < nn) return -11;
     if (opts && opts->precision != HGV_FP64) return opts->precision == HGV_MIXED ? HGV_E_NOTSUP : -14;
     if (opts && opts->nb < 0) return -14;
+    if (opts && opts->one_stage) return HGV_E_NOTSUP;
     if (n == 0) return guarded(ctx, [&]() {
         set_info(ctx, d_info, 0);
         return HGV_OK;
@@ -616,6 +670,67 @@ int hgv_zhe2hb(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, hgv_c128 *T1,
         set_info(ctx, d_info, 0);
         Arena ar(work, work_bytes);
         he2hb_run(ctx, n, nb, reinterpret_cast<double2 *>(A), lda, reinterpret_cast<double2 *>(T1), ar, d_info);
+        return HGV_OK;
+    });
+}
+
+int hgv_zhetrd_bufsize(hgv_ctx_t ctx, int n, int nb, size_t *bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1 || nb > 64) return -3;
+    if (!bytes) return -4;
+    *bytes = 0;
+    if (n == 0) return HGV_OK;
+    return guarded(ctx, [&]() {
+        Arena ar;
+        hetrd_run(ctx, n, nb, nullptr, n, nullptr, nullptr, nullptr, ar);
+        *bytes = ar.peak + 256;
+        return HGV_OK;
+    });
+}
+
+int hgv_zhetrd(hgv_ctx_t ctx, int n, int nb, hgv_c128 *A, int lda, double *d, double *e, hgv_c128 *T1, void *work,
+               size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (n < 0) return -2;
+    if (nb < 1 || nb > 64) return -3;
+    if (n > 0 && !A) return -4;
+    if (lda < std::max(1, n)) return -5;
+    if (n > 0 && !d) return -6;
+    if (n > 1 && !e) return -7;
+    if (n > 0 && !T1) return -8;
+    if (n == 0) return HGV_OK;
+    size_t need = 0;
+    int st = hgv_zhetrd_bufsize(ctx, n, nb, &need);
+    if (st != HGV_OK) return st;
+    if (!work || (reinterpret_cast<uintptr_t>(work) & 255)) return -9;
+    if (work_bytes < need) return HGV_E_WORKSPACE;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        hetrd_run(ctx, n, nb, reinterpret_cast<double2 *>(A), lda, d, e, reinterpret_cast<double2 *>(T1), ar);
+        return HGV_OK;
+    });
+}
+
+int hgv_zunmtr_tr(hgv_ctx_t ctx, char trans, int n, int nb, int m, const hgv_c128 *A, int lda, const hgv_c128 *T1,
+                  hgv_c128 *Y, int ldy, void *work, size_t work_bytes) {
+    if (!ctx_ok(ctx)) return HGV_E_CTX;
+    if (trans != 'N' && trans != 'C') return -2;
+    if (n < 0) return -3;
+    if (nb < 1 || nb > 64) return -4;
+    if (m < 0) return -5;
+    if (n > 0 && !A) return -6;
+    if (lda < std::max(1, n)) return -7;
+    if (n > 0 && !T1) return -8;
+    if (n > 0 && m > 0 && !Y) return -9;
+    if (ldy < std::max(1, n)) return -10;
+    int st = check_work(ctx, HGV_ST_Q1, n, nb, m, work, work_bytes, 11);
+    if (st) return st;
+    return guarded(ctx, [&]() {
+        Arena ar(work, work_bytes);
+        unmtr_q1_t<double2>(ctx, n, nb, m, reinterpret_cast<const double2 *>(A), lda,
+                            reinterpret_cast<const double2 *>(T1), reinterpret_cast<double2 *>(Y), ldy, trans == 'C',
+                            ar, 1);
         return HGV_OK;
     });
 }
@@ -865,7 +980,9 @@ static size_t batch_prob_bytes(hgv_ctx_s *ctx, BatchProb p) {
     return align256(ar.peak);
 }
 
-static bool batch_grouped(const hgv_opts *opts) { return !opts || opts->precision == HGV_FP64; }
+static bool batch_grouped(const hgv_opts *opts) {
+    return !opts || (opts->precision == HGV_FP64 && !opts->one_stage);
+}
 
 int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu, const int *nb,
                                const hgv_opts *opts, size_t *bytes) {

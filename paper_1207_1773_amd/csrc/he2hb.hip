@@ -566,12 +566,16 @@ static int q1_merge(int m) { return m >= 2048 ? 8 : 4; }
 
 // Y <- Q1 Y = (I - V_0 T_0 V_0^H) ... (I - V_{P-1} T_{P-1} V_{P-1}^H) Y (last
 // group first), or Y <- Q1^H Y (first group first, T^H in place of T).
+// voff: rows between a panel's first column and its first reflector row (nb for
+// the band reduction; 1 for the one-stage tridiagonalisation, whose panel p
+// holds the reflectors of columns p*nb .. p*nb+nb-1 from row p*nb + 1 on).
 template <class E>
 void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
-                Arena &ar) {
+                Arena &ar, int voff) {
     typedef typename El<E>::Gemm Gm_t;
     if (nb > PNB) throw HipFail{hipErrorInvalidValue};
-    const int np = num_panels(n, nb);
+    const int vo = voff > 0 ? voff : nb;
+    const int np = (n - vo - 1 >= 0) ? (n - vo - 1) / nb + 1 : 0;
     const int mg = q1_merge(m);
     const int R = mg * nb;
     size_t wsb = zgemm_splitk_bytes(n);
@@ -589,13 +593,13 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
         const int gi = adj ? q : ngrp - 1 - q;
         const int p0 = gi * mg, p1 = std::min(np, p0 + mg);
         const int k0 = p0 * nb;
-        const int Nb = n - k0 - nb;                    // rows of the merged V (start at row k0 + nb)
+        const int Nb = n - k0 - vo;                    // rows of the merged V (start at row k0 + vo)
         if (Nb <= 0) continue;
         // columns of panel p: c_p .. c_p + r_p - 1
         int cols[Q1_MERGE + 1], rs[Q1_MERGE];
         cols[0] = 0;
         for (int p = p0; p < p1; ++p) {
-            const int k = p * nb, jb = std::min(nb, n - k), N = n - k - nb;
+            const int k = p * nb, jb = std::min(nb, n - k), N = n - k - vo;
             rs[p - p0] = std::max(0, std::min(N, jb));
             cols[p - p0 + 1] = cols[p - p0] + rs[p - p0];
         }
@@ -604,11 +608,11 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
         zero_async(ctx, Vb, (size_t)Nb * Rg);
         zero_async(ctx, Tb, (size_t)Rg * Rg);
         for (int p = p0; p < p1; ++p) {
-            const int k = p * nb, N = n - k - nb, r = rs[p - p0];
+            const int k = p * nb, N = n - k - vo, r = rs[p - p0];
             if (r == 0) continue;
             const int off = (p - p0) * nb;
             hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r,
-                               A + (k + nb) + (size_t)k * lda, lda, Vb + off + (size_t)cols[p - p0] * Nb, Nb);
+                               A + (k + vo) + (size_t)k * lda, lda, Vb + off + (size_t)cols[p - p0] * Nb, Nb);
             HGV_LAUNCH_CHECK();
             hipLaunchKernelGGL(place_t_kernel<E>, dim3(cdiv(r, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, r,
                                T1 + (size_t)p * nb * nb, nb, Tb + cols[p - p0] + (size_t)cols[p - p0] * Rg, Rg);
@@ -639,7 +643,7 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
                 gemm_any(ctx, g, ws, wsb);
             }
         }
-        E *Ys = Y + (k0 + nb);
+        E *Ys = Y + (k0 + vo);
         Gm_t g;  // W1 = V^H Ys
         g.m = Rg; g.n = m; g.k = Nb;
         g.opa = 'C'; g.A = Vb; g.lda = Nb;
@@ -663,8 +667,27 @@ void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const
 template void he2hb_t<double2>(hgv_ctx_s *, int, int, double2 *, int, double2 *, Arena &, int *);
 template void he2hb_t<float2>(hgv_ctx_s *, int, int, float2 *, int, float2 *, Arena &, int *);
 template void unmtr_q1_t<double2>(hgv_ctx_s *, int, int, int, const double2 *, int, const double2 *, double2 *, int,
-                                  bool, Arena &);
+                                  bool, Arena &, int);
 template void unmtr_q1_t<float2>(hgv_ctx_s *, int, int, int, const float2 *, int, const float2 *, float2 *, int, bool,
-                                 Arena &);
+                                 Arena &, int);
+
+// T factor of a panel whose r reflectors sit in P (N x r, ldp, unit diagonal
+// implicit) with scalars tau (device, double2): explicit V into Vw (N x r),
+// G = V^H V into Gm (r x r), then T (ldt) by the column recurrence.
+void panel_t_build(hgv_ctx_s *ctx, int N, int r, const double2 *P, int ldp, const double2 *tau, double2 *Vw,
+                   double2 *Gm, double2 *T, int ldt, void *ws, size_t wsb) {
+    if (N <= 0 || r <= 0) return;
+    hipLaunchKernelGGL(extract_v_kernel<double2>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P,
+                       ldp, Vw, N);
+    HGV_LAUNCH_CHECK();
+    ZGemm gg;
+    gg.m = r; gg.n = r; gg.k = N;
+    gg.opa = 'C'; gg.A = Vw; gg.lda = N;
+    gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
+    gg.C = Gm; gg.ldc = r;
+    zgemm(ctx, gg, static_cast<double2 *>(ws), wsb);
+    hipLaunchKernelGGL((build_t_kernel<double2, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    HGV_LAUNCH_CHECK();
+}
 
 }  // namespace hgv

@@ -238,9 +238,18 @@ void trsm_left_lc(hgv_ctx_s *ctx, int n, int m, const double2 *L, int ldl, doubl
 template <class E>
 void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int *d_info = nullptr);
 // Y <- Q1 Y (adj = false) or Y <- Q1^H Y (adj = true)
+// voff: first reflector row of panel p is p*nb + voff (0: nb, the band reduction;
+// 1: the one-stage tridiagonalisation)
 template <class E>
 void unmtr_q1_t(hgv_ctx_s *ctx, int n, int nb, int m, const E *A, int lda, const E *T1, E *Y, int ldy, bool adj,
-                Arena &ar);
+                Arena &ar, int voff = 0);
+// T factor of a panel of r reflectors held in P (N x r, unit diagonal implicit)
+void panel_t_build(hgv_ctx_s *ctx, int N, int r, const double2 *P, int ldp, const double2 *tau, double2 *Vw,
+                   double2 *Gm, double2 *T, int ldt, void *ws, size_t wsb);
+// One-stage tridiagonalisation (hetrd.hip): A = Q T Q^H with T real (d, e),
+// the reflectors of panel p (columns p*nb ..) below the first subdiagonal of A
+// and their compact-WY factors in T1 (as the band reduction's, voff = 1).
+void hetrd_run(hgv_ctx_s *ctx, int n, int nb, double2 *A, int lda, double *d, double *e, double2 *T1, Arena &ar);
 template <class E>
 void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar,
              int *d_info = nullptr);
@@ -394,7 +403,7 @@ struct StageTimer {
 // multisection and nothing is back-transformed.
 void standard_fp64(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
                    Arena &ar, int nb, int *d_info, StageTimer *tm, const ValueRange *vr = nullptr,
-                   bool values_only = false);
+                   bool values_only = false, bool one_stage = false);
 // Mixed precision standard eigensolve of A' (n x n, FP64, lower triangle;
 // kept intact unless the refinement falls back to standard_fp64): complex64
 // band reduction, bulge chasing and back-transforms, FP64 tridiagonal solve,

@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import (hgv_chegvx, hgv_chegvx_bufsize, hgv_dstebz, hgv_dstebz_bufsize, hgv_dsygvx, hgv_dsygvx_bufsize,
-               hgv_zhegvx_range, hgv_zhegvx_range_bufsize)
+               hgv_zhegvx_range, hgv_zhegvx_range_bufsize, hgv_zhetrd, hgv_zhetrd_bufsize, hgv_zunmtr_tr)
 from . import (HGV_FP64, HGV_MIXED, HGV_ST_HB2ST, HGV_ST_HE2HB, HGV_ST_HEGST, HGV_ST_POTRF, HGV_ST_Q1,
                HGV_ST_Q2, HGV_ST_STEDC, HGV_ST_TRSM, Opts, Stats, c128, hgv_create, hgv_destroy, hgv_dstedc,
                hgv_set_stream, hgv_stage_bufsize, hgv_v2_elems, hgv_v2_taus, hgv_zgemm, hgv_zhb2st, hgv_zhe2hb,
@@ -150,6 +150,29 @@ class Context:
                    _ptr(info))
         return lam[:n], from_colmajor(Zc)[:n, :m], int(info.item())
 
+    def hetrd(self, A, nb):
+        """One-stage tridiagonalisation (Sec. 4.1): (A_out column-major view, d, e, T1)."""
+        self._sync_stream()
+        n = A.shape[0]
+        Ac = colmajor(A)
+        d = torch.zeros(max(n, 1), dtype=torch.float64, device=self.device)
+        e = torch.zeros(max(n - 1, 1), dtype=torch.float64, device=self.device)
+        T1 = torch.zeros((max((n + nb - 1) // nb, 1), nb, nb), dtype=torch.complex128, device=self.device)
+        w = self._work(hgv_zhetrd_bufsize(self.handle, n, nb))
+        hgv_zhetrd(self.handle, n, nb, _ptr(Ac), max(n, 1), _ptr(d), _ptr(e), _ptr(T1), _ptr(w), w.numel())
+        return from_colmajor(Ac), d[:n], e[:max(n - 1, 0)], T1
+
+    def unmtr_tr(self, Ab, T1, Y, nb, adj=False):
+        """Q Y (Q^H Y with adj=True) with Q from hetrd (Ab as returned by hetrd)."""
+        self._sync_stream()
+        n, m = Y.shape
+        Ac = colmajor(Ab)
+        Yc = colmajor(Y)
+        w = self._work(hgv_stage_bufsize(self.handle, HGV_ST_Q1, n, nb, m))
+        hgv_zunmtr_tr(self.handle, "C" if adj else "N", n, nb, m, _ptr(Ac), max(n, 1), _ptr(T1), _ptr(Yc), max(n, 1),
+                      _ptr(w), w.numel())
+        return from_colmajor(Yc)
+
     def stebz(self, d, e, il=1, iu=None):
         """Eigenvalues il..iu of the tridiagonal (d, e) by Sturm-count multisection."""
         self._sync_stream()
@@ -217,7 +240,7 @@ class Context:
 
     # ---- full solve ------------------------------------------------------------------------------
     def zhegvx(self, A, B, il=1, iu=None, precision="fp64", nb=0, stats=False, inplace=False, max_refine_iters=0,
-               refine_tol=0.0, values_only=False):
+               refine_tol=0.0, values_only=False, one_stage=False):
         """Eigenpairs il..iu of (A, B).  Returns (W, X, info, stats_dict_or_None).
 
         precision "mixed" runs the complex64 reduction with FP64 refinement
@@ -231,7 +254,7 @@ class Context:
         m = iu - il + 1
         Ac = A if inplace else colmajor(A)
         Bc = B if inplace else colmajor(B)
-        opts = _opts(precision, nb, max_refine_iters, refine_tol, values_only)
+        opts = _opts(precision, nb, max_refine_iters, refine_tol, values_only, one_stage)
         W = torch.zeros(max(m, 1), dtype=torch.float64, device=self.device)
         Xc = None if values_only else torch.zeros((max(m, 1), max(n, 1)), dtype=torch.complex128, device=self.device)
         w = self._work(hgv_zhegvx_bufsize(self.handle, n, il, iu, opts))
@@ -322,11 +345,11 @@ def _close_cached_contexts():
     Context._cache.clear()
 
 
-def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0, values_only=False):
+def _opts(precision, nb=0, max_refine_iters=0, refine_tol=0.0, values_only=False, one_stage=False):
     if precision not in ("fp64", "mixed"):
         raise ValueError("precision must be 'fp64' or 'mixed'")
     return Opts(HGV_FP64 if precision == "fp64" else HGV_MIXED, int(nb), int(max_refine_iters), float(refine_tol),
-                int(bool(values_only)))
+                int(bool(values_only)), int(bool(one_stage)))
 
 
 class BatchedSolve:
