@@ -270,8 +270,8 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int BK = KDepth<T>::v;
     constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
-    __shared__ E As[BK * (BM + PAD)];
-    __shared__ E Bs[BK * (BN + PAD)];
+    __shared__ E As[2][BK * (BM + PAD)];
+    __shared__ E Bs[2][BK * (BN + PAD)];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -353,23 +353,21 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
         }
     };
 
-    if (c_beg < c_end) fetch(c_beg);
-    for (int c = c_beg; c < c_end; ++c) {
-        __syncthreads();
+    auto stage = [&](int buf) {
 #pragma unroll
-        for (int t = 0; t < NA; ++t) As[iab + t * ias] = fix_elem<T>(ra[t], (unsigned)(fa >> (3 * t)) & 7u);
+        for (int t = 0; t < NA; ++t) As[buf][iab + t * ias] = fix_elem<T>(ra[t], (unsigned)(fa >> (3 * t)) & 7u);
 #pragma unroll
-        for (int t = 0; t < NB; ++t) Bs[ibb + t * ibs] = fix_elem<T>(rb[t], (unsigned)(fb >> (3 * t)) & 7u);
-        __syncthreads();
-        if (c + 1 < c_end) fetch(c + 1);
+        for (int t = 0; t < NB; ++t) Bs[buf][ibb + t * ibs] = fix_elem<T>(rb[t], (unsigned)(fb >> (3 * t)) & 7u);
+    };
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kl = ks * 4 + (lane >> 4);
             E af[FM], bf[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) af[i] = As[kl * (BM + PAD) + wm * WM + i * 16 + (lane & 15)];
+            for (int i = 0; i < FM; ++i) af[i] = As[buf][kl * (BM + PAD) + wm * WM + i * 16 + (lane & 15)];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) bf[j] = Bs[kl * (BN + PAD) + wn * WN + j * 16 + (lane & 15)];
+            for (int j = 0; j < FN; ++j) bf[j] = Bs[buf][kl * (BN + PAD) + wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -377,6 +375,21 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
                     mfma_step<T>(af[i], bf[j], acc1[i][j], acc2[T::cplx ? i : 0][T::cplx ? j : 0],
                                  acc3[T::cplx ? i : 0][T::cplx ? j : 0]);
         }
+    };
+    // two LDS buffers, one barrier per chunk: the next chunk's global loads are
+    // issued before this chunk's MFMAs and stored to the other buffer after them
+    // (that buffer was last read before the previous barrier)
+    if (c_beg < c_end) {
+        fetch(c_beg);
+        stage(0);
+    }
+    __syncthreads();
+    for (int c = c_beg; c < c_end; ++c) {
+        const int buf = (c - c_beg) & 1;
+        if (c + 1 < c_end) fetch(c + 1);
+        compute(buf);
+        if (c + 1 < c_end) stage(buf ^ 1);
+        __syncthreads();
     }
 
     // epilogue: each lane holds four rows (T::out_row) of column lane%16 of each
