@@ -134,6 +134,17 @@ def run_config3(ctx, dev, reps=3):
             torch.cuda.synchronize()
             if it > 0:
                 times.append(e0.elapsed_time(e1))
+        # the same batch launched eagerly (no graph), for comparison
+        eager = []
+        for it in range(2):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bs.run()
+            e1.record()
+            torch.cuda.synchronize()
+            eager.append(e0.elapsed_time(e1))
         Ws, Xs, infos = bs.results()
         worst_res = worst_orth = 0.0
         n1 = lambda M: float(M.abs().sum(0).max())
@@ -145,6 +156,7 @@ def run_config3(ctx, dev, reps=3):
             worst_res, worst_orth = max(worst_res, res), max(worst_orth, orth)
         ms = float(np.median(times))
         out[precision] = {"s": ms / 1e3, "tflops": flops / (ms * 1e-3) / 1e12, "times_ms": times,
+                          "eager_s": min(eager) / 1e3,
                           "infos_nonzero": int(sum(1 for x in infos if x != 0)),
                           "max_residual": worst_res, "max_orth_over_n": worst_orth}
         print("[bench] batched 64 pencils %s (one graph): %.1f ms" % (precision, ms), file=sys.stderr, flush=True)
@@ -391,11 +403,20 @@ def main():
         tcpu = time.time() - tc
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         cores = min(cores, os.cpu_count() or cores)
+        model = "unknown"
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
         cpu = {"value": solve_flops(args.cpu_n, args.cpu_n) / tcpu / 1e12, "unit": "TFLOP/s", "cores": cores,
                "kind": "oracle",
-               "sample": "oracle full solve (all pairs) of the same pencil recipe at n=%d: %.2f s (info %d); "
-                         "n^3-scaled estimate for n=%d: %.0f s" % (args.cpu_n, tcpu, cinfo, n,
-                                                                    tcpu * (n / args.cpu_n) ** 3)}
+               "cpu_model": model,
+               "sample": "oracle full solve (all pairs) of the same pencil recipe at n=%d: %.2f s (info %d), "
+                         "TFLOP/s with the n=%d flop count; an n^3-scaled ESTIMATE (not measured) for n=%d: %.0f s"
+                         % (args.cpu_n, tcpu, cinfo, args.cpu_n, n, tcpu * (n / args.cpu_n) ** 3)}
 
     stage_avg = {k: v / args.steps for k, v in stage_ms.items() if v > 0}
     stage_tflops = {k: st["flops"][k] / (v * 1e-3) / 1e12 for k, v in stage_avg.items() if st["flops"].get(k)}
