@@ -983,6 +983,11 @@ static size_t batch_prob_bytes(hgv_ctx_s *ctx, BatchProb p) {
 static bool batch_grouped(const hgv_opts *opts) {
     return !opts || (opts->precision == HGV_FP64 && !opts->one_stage);
 }
+// mixed precision: the same three phases (complex64 band reduction, grouped
+// complex64 bulge chasing, then the rest with the refinement)
+static bool batch_grouped_mixed(const hgv_opts *opts) {
+    return opts && opts->precision == HGV_MIXED && !opts->one_stage && !opts->values_only;
+}
 
 int hgv_zhegvx_batched_bufsize(hgv_ctx_t ctx, int batch, const int *n, const int *il, const int *iu, const int *nb,
                                const hgv_opts *opts, size_t *bytes) {
@@ -1107,6 +1112,53 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
                 HGV_HIP(hipStreamWaitEvent(user, ctx->side_ev[k], 0));
             }
         };
+        if (batch_grouped_mixed(opts)) {
+            const int iters = opts->max_refine_iters > 0 ? opts->max_refine_iters : 3;
+            const int its = opts->max_refine_iters < 0 ? 0 : iters;
+            std::vector<HbBatchProblem> hbm(batch);
+            // (A) FP64 factorisation and reduction to standard form, complex64 band reduction
+            fan_out([&](int idx) {
+                int *inf = d_info ? d_info + idx : nullptr;
+                if (n[idx] == 0) {
+                    set_info(ctx, inf, 0);
+                    return;
+                }
+                Arena ar(base + off[idx], work_bytes - off[idx]);
+                const int nbi = batch_nb(nb, idx, n[idx]);
+                const double tol = opts->refine_tol > 0.0 ? opts->refine_tol
+                                                         : 32.0 * DBL_EPSILON * std::sqrt((double)n[idx]);
+                set_info(ctx, inf, 0);
+                potrf_hegst_run(ctx, n[idx], reinterpret_cast<double2 *>(B[idx]), ldb[idx],
+                                reinterpret_cast<double2 *>(A[idx]), lda[idx], ar, inf, n[idx], nullptr, 0.0);
+                ar.release(0);
+                MixedResult mr;
+                mixed_standard(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx], il[idx], iu[idx], W[idx],
+                               reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, nbi, its, tol, true, inf, nullptr,
+                               &mr, 1, &hbm[idx]);
+            });
+            // (B) one grouped complex64 bulge chasing
+            std::vector<HbBatchProblem> hbs;
+            for (int i = 0; i < batch; ++i)
+                if (n[i] > 0) hbs.push_back(hbm[i]);
+            hb2st_batch_run<float2>(ctx, hbs, err);
+            // (C) tridiagonal solves, complex64 back-transformations, FP64 refinement, back-substitution
+            fan_out([&](int idx) {
+                if (n[idx] == 0) return;
+                int *inf = d_info ? d_info + idx : nullptr;
+                Arena ar(base + off[idx], work_bytes - off[idx]);
+                const int nbi = batch_nb(nb, idx, n[idx]);
+                const double tol = opts->refine_tol > 0.0 ? opts->refine_tol
+                                                         : 32.0 * DBL_EPSILON * std::sqrt((double)n[idx]);
+                MixedResult mr;
+                mixed_standard(ctx, n[idx], reinterpret_cast<double2 *>(A[idx]), lda[idx], il[idx], iu[idx], W[idx],
+                               reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, nbi, its, tol, true, inf, nullptr,
+                               &mr, 2, &hbm[idx]);
+                ar.release(0);
+                trsm_lh_run(ctx, n[idx], iu[idx] - il[idx] + 1, reinterpret_cast<double2 *>(B[idx]), ldb[idx],
+                            reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar);
+            });
+            return HGV_OK;
+        }
         if (!grouped) {
             fan_out([&](int idx) {
                 int *inf = d_info ? d_info + idx : nullptr;

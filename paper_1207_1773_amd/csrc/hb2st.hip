@@ -533,6 +533,10 @@ template void hb2st_batch_plan<double2>(int, int, Arena &, HbBatchProblem &);
 template void hb2st_batch_prep<double2>(hgv_ctx_s *, const HbBatchProblem &, const double2 *, int);
 template void hb2st_batch_run<double2>(hgv_ctx_s *, const std::vector<HbBatchProblem> &, int *);
 template void hb2st_batch_finish<double2>(hgv_ctx_s *, const HbBatchProblem &, double *, double *);
+template void hb2st_batch_plan<float2>(int, int, Arena &, HbBatchProblem &);
+template void hb2st_batch_prep<float2>(hgv_ctx_s *, const HbBatchProblem &, const float2 *, int);
+template void hb2st_batch_run<float2>(hgv_ctx_s *, const std::vector<HbBatchProblem> &, int *);
+template void hb2st_batch_finish<float2>(hgv_ctx_s *, const HbBatchProblem &, double *, double *);
 
 template void hb2st_t<double2>(hgv_ctx_s *, int, int, const double2 *, int, double *, double *, double2 *, double2 *,
                                Arena &, int *);

@@ -413,9 +413,13 @@ struct MixedResult {
     int fallback = 0;    // 1: the FP64 path produced the result
     double rho = 0.0;    // final max_i ||A' y_i - theta_i y_i||_2 / ||A'||_2 (host-checked runs)
 };
+// phase: 0 the whole solve; for batched solves 1 = up to the band copy of the
+// bulge chasing (hb receives its buffers), 2 = the rest after the grouped bulge
+// chasing (called with an arena in the same state as for phase 1).
+struct HbBatchProblem;
 void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *Y, int ldy,
                     Arena &ar, int nb, int max_iters, double tol, bool fixed_iters, int *d_info, StageTimer *tm,
-                    MixedResult *res);
+                    MixedResult *res, int phase = 0, HbBatchProblem *hb = nullptr);
 
 // ---- other storage types (variants.hip) ---------------------------------------------
 // Complex64 generalized solve (every stage on complex64 storage, FP32 MFMA

@@ -212,7 +212,7 @@ inline dim3 grid2(int n, int m) { return dim3(cdiv(n, 64), cdiv(m, 4)); }
 
 void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, double *W, double2 *X, int ldx,
                     Arena &ar, int nb, int max_iters, double tol, bool fixed_iters, int *d_info, StageTimer *tm,
-                    MixedResult *res) {
+                    MixedResult *res, int phase, HbBatchProblem *hb) {
     const int m = iu - il + 1;
     const int il2 = std::max(1, il - kGuard), iu2 = std::min(n, iu + kGuard);
     const int mw = iu2 - il2 + 1, off = il - il2;
@@ -264,19 +264,43 @@ void mixed_standard(hgv_ctx_s *ctx, int n, double2 *A, int lda, int il, int iu, 
     const double2 one = make_double2(1.0, 0.0), zero = make_double2(0.0, 0.0), mone = make_double2(-1.0, 0.0);
 
     // ---- complex64 reduction and back-transform of T's eigenvectors ----
-    if (run) {
-        hipLaunchKernelGGL(to_c64_kernel, grid2(n, n), dim3(256), 0, ctx->stream, n, n, A, lda, Ac, n);
-        HGV_LAUNCH_CHECK();
+    // (phase 1 of a batched solve stops after the band copy of the bulge chasing,
+    // phase 2 resumes after the grouped bulge chasing; the buffers above come out
+    // of the arena at the same places both times)
+    if (phase != 2) {
+        if (run) {
+            hipLaunchKernelGGL(to_c64_kernel, grid2(n, n), dim3(256), 0, ctx->stream, n, n, A, lda, Ac, n);
+            HGV_LAUNCH_CHECK();
+        }
+        if (tm) tm->begin(HGV_ST_HE2HB);
+        he2hb_t<float2>(ctx, n, nb, Ac, n, T1c, ar, d_info);
+        ar.release(mk1);
+        if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
     }
-    if (tm) tm->begin(HGV_ST_HE2HB);
-    he2hb_t<float2>(ctx, n, nb, Ac, n, T1c, ar, d_info);
-    ar.release(mk1);
-    if (tm) tm->end(HGV_ST_HE2HB, 16.0 / 3.0 * N * N * N);
-
-    if (tm) tm->begin(HGV_ST_HB2ST);
-    hb2st_t<float2>(ctx, n, nb, Ac, n, d, e, V2c, tau2c, ar, d_info);
-    ar.release(mk1);
-    if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+    if (phase == 0) {
+        if (tm) tm->begin(HGV_ST_HB2ST);
+        hb2st_t<float2>(ctx, n, nb, Ac, n, d, e, V2c, tau2c, ar, d_info);
+        ar.release(mk1);
+        if (tm) tm->end(HGV_ST_HB2ST, 24.0 * N * N * nb);
+    } else {
+        hb2st_batch_plan<float2>(n, nb, ar, *hb);
+        hb->V2 = V2c;
+        hb->tau2 = tau2c;
+        hb->d_info = d_info;
+        if (run && phase == 1) hb2st_batch_prep<float2>(ctx, *hb, Ac, n);
+        if (phase == 1) {
+            if (!run) {
+                // size query: the rest of the solve's scratch
+                ar.release(mk1);
+                phase = 0;
+            } else {
+                return;
+            }
+        } else {
+            if (run) hb2st_batch_finish<float2>(ctx, *hb, d, e);
+            ar.release(mk1);
+        }
+    }
 
     if (tm) tm->begin(HGV_ST_STEDC);
     stedc_run(ctx, n, d, e, il2, iu2, lam, Z, n, ar, d_info);
