@@ -33,7 +33,7 @@ def solve_flops(n, m):
 
 def gemm_traffic():
     """HBM bytes per launch of the complex-double GEMM tile kernel, from the committed counter
-    summary, or None when the kernel source has changed since the counters were taken."""
+    summary, or None when the kernel's device code has changed since the counters were taken."""
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         text = open(os.path.join(root, "profiles", "gemm_tz_hbm_traffic_fp64_n10000.md")).read()
@@ -43,8 +43,10 @@ def gemm_traffic():
     import hashlib
     import re
     mb = re.search(r"^hbm_bytes_per_launch: (\d+)$", text, re.M)
-    mh = re.search(r"^gemm\.hip sha256: ([0-9a-f]{64})$", text, re.M)
-    if not mb or not mh or hashlib.sha256(src).hexdigest() != mh.group(1):
+    mh = re.search(r"^gemm\.hip tile kernel sha256: ([0-9a-f]{64})$", text, re.M)
+    s = src.decode()
+    b0, b1 = s.find("// ---- device code of the tile kernel (begin) ----"), s.find("// ---- device code of the tile kernel (end) ----")
+    if not mb or not mh or b0 < 0 or b1 < 0 or hashlib.sha256(s[b0:b1].encode()).hexdigest() != mh.group(1):
         return None
     return int(mb.group(1))
 

@@ -24,9 +24,13 @@
 //    second kernel) for outputs with too few tiles to fill 256 CUs.
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "hgv_internal.h"
 
 namespace hgv {
+
+// ---- device code of the tile kernel (begin) ----
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -433,6 +437,8 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
     }
 }
 
+// ---- device code of the tile kernel (end) ----
+
 // C = alpha * sum_z P[z] + beta * C  (fixed summation order)
 template <class T>
 __global__ __launch_bounds__(256) void splitk_reduce(GemmDev<T> g) {
@@ -528,13 +534,17 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         }
         e0 = ctx->ev_free.back(); ctx->ev_free.pop_back();
         e1 = ctx->ev_free.back(); ctx->ev_free.pop_back();
-        HGV_HIP(hipEventRecord(e0, ctx->stream));
     }
     dim3 grid(tiles, splits);
-    hipLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, g);
+    if (timed) {
+        // the start and stop events ride on the kernel's own dispatch (no separate
+        // marker packets between the launches)
+        hipExtLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, e0, e1, 0, g);
+    } else {
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, g);
+    }
     HGV_LAUNCH_CHECK();
     if (timed) {
-        HGV_HIP(hipEventRecord(e1, ctx->stream));
         ctx->ev_pending.push_back({e0, e1});
         ctx->ev_flops.push_back(flops);
     }
