@@ -126,8 +126,12 @@ int hgv_default_nb(int n, int precision);
  * HGV_TEST_NAN_RESIDUAL: the mixed-precision refinement sees a NaN residual,
  *   so it never meets its tolerance (FP64 fallback, or d_info = 2n+1 under
  *   graph capture).
+ * HGV_TEST_HB2ST_SWEEPS: the bulge chasing of single solves runs the
+ *   sweep-per-workgroup schedule (otherwise used only when the windows of the
+ *   window-owner pipeline do not all fit on the device at once), so that both
+ *   schedules can be tested.
  * Returns -2 for unknown bits. */
-enum { HGV_TEST_WAIT_FAIL = 1, HGV_TEST_NAN_RESIDUAL = 2 };
+enum { HGV_TEST_WAIT_FAIL = 1, HGV_TEST_NAN_RESIDUAL = 2, HGV_TEST_HB2ST_SWEEPS = 4 };
 int hgv_test_hooks(hgv_ctx_t ctx, int mask);
 
 /* ---- full generalized solve (Algorithm 1) -------------------------------- */

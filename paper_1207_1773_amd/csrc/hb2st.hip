@@ -360,6 +360,388 @@ __global__ __launch_bounds__(NT) void hb2st_kernel(HbArgs<E> a0, HbBatch<E> bt) 
     }
 }
 
+// ---- window-owner pipeline ---------------------------------------------------------------
+// The same tasks and reflectors, scheduled by window instead of by sweep.
+// Workgroup w owns, for every sweep s, the rows I_w(s) = [s+1+w*b, s+(w+1)*b]:
+// the diagonal block D_w = A[I_w, I_w] (registers, thread (row, q) holding
+// D[row][q + TPR*u]) and the block below it E_w = A[I_{w+1}, I_w] (LDS), both
+// kept resident from sweep to sweep.  Index i sits at slot i mod b, so moving
+// the window one index down (sweep s -> s+1) replaces one slot t: index
+// c = s+(w+1)*b enters, c - b leaves; row c of E_w becomes the new last row of
+// D_w, and the rest of column c (its diagonal element and the b elements below
+// it) comes from workgroup w+1, which drops index c at the same sweep.
+// Per task (s, w):
+//   wait for H_{s,w} (posted by w-1) and for column c (posted by w+1 after its
+//   task of sweep s-1); shift the window; E <- E H_{s,w}; H_{s,w+1} from E's
+//   first column, posted to w+1; D <- H^H D H; the band column of the
+//   window's first index (D's column, beta of H_{s,w+1} below it) posted to w-1;
+//   E <- H_{s,w+1}^H E.
+// Workgroup 0 makes H_{s,0} from column s, which it keeps from its window of
+// sweep s-1, and writes d_s and e_s.  A message is one reflector or one band
+// column (b + 1 values), so no block travels through memory between tasks.
+// Task (s, w) waits for (s, w-1), (s-1, w+1) and follows (s-1, w) on its own
+// workgroup: all three have a smaller 2s + w, so with every workgroup resident
+// (cooperative launch) the smallest unfinished task can always run.  A mailbox
+// is written again only after its reader has posted a message that depends on
+// having read it (one buffer per mailbox would do; two are kept, by sweep
+// parity).  Every task's arithmetic is fixed, so the result does not depend on
+// timing.
+template <class E>
+struct HbOwnArgs {
+    int n, b, ldb, J;
+    const E *AB;
+    E *V2, *tau2;
+    double *d, *e;                 // the tridiagonal (written by workgroup 0)
+    unsigned long long *boxH;      // per workgroup: 2 (sweep parity) x (BM + 1) values x 4 words
+    unsigned long long *boxS;
+    int *err;                      // set when a wait gives up
+};
+
+// Messages.  A complex value travels as four 64-bit words, each holding the
+// tag of its message (the sweep it is for, plus one) in the upper half and 32
+// bits of the value in the lower half, written and read as relaxed device-scope
+// atomics.  Every word is one atomic location, so a reader that sees the
+// expected tag in all four words has read the value that was sent with it: the
+// receiver polls the data itself (no separate flag, no fences), and the sender
+// does not wait for its stores.  A mailbox is zeroed before the launch (tag 0
+// is never expected).
+__device__ inline void msg_put(unsigned long long *p, double2 v, unsigned tag) {
+    const unsigned long long t = (unsigned long long)tag << 32;
+    const unsigned long long x = (unsigned long long)__double_as_longlong(v.x);
+    const unsigned long long y = (unsigned long long)__double_as_longlong(v.y);
+    __hip_atomic_store(p + 0, t | (x & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, t | (x >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 2, t | (y & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 3, t | (y >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// true when all four words carry the tag; v is then the value sent
+__device__ inline bool msg_get(const unsigned long long *p, unsigned tag, double2 &v) {
+    const unsigned long long a = __hip_atomic_load(p + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long c = __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long d = __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v.x = __longlong_as_double((long long)(((b & 0xffffffffull) << 32) | (a & 0xffffffffull)));
+    v.y = __longlong_as_double((long long)(((d & 0xffffffffull) << 32) | (c & 0xffffffffull)));
+    return (a >> 32) == tag && (b >> 32) == tag && (c >> 32) == tag && (d >> 32) == tag;
+}
+
+// Reductions of the pipeline kernel by DPP lane moves (no LDS round trips).  A
+// double moves as its two 32-bit halves.  Each step adds a lane's value to its
+// partner's under a pairing (xor 1, xor 2, mirror within 8, mirror within 16),
+// so both partners form the same sum and every lane of the group ends with the
+// same bits.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double lane_f64(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// sum over aligned groups of 8 lanes
+__device__ inline double sum8_dpp(double x) {
+    x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]: xor 1
+    x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]: xor 2
+    x += dpp_f64<0x141>(x);   // row_half_mirror: lane i <-> 7 - i
+    return x;
+}
+__device__ inline double2 sum8_dpp(double2 x) { return make_double2(sum8_dpp(x.x), sum8_dpp(x.y)); }
+// sum over the wave (the same value in every lane)
+__device__ inline double wave_sum_dpp(double x) {
+    x = sum8_dpp(x);
+    x += dpp_f64<0x140>(x);   // row_mirror: lane i <-> 15 - i
+    return (lane_f64(x, 0) + lane_f64(x, 16)) + (lane_f64(x, 32) + lane_f64(x, 48));
+}
+
+// Householder reflector of the slot-ordered vector x held by the lanes of one
+// wave (lane = slot, alpha at slot f, lanes with valid == false hold no
+// element): H^H x = beta e_f with beta real; returns v (v_f = 1) of this lane.
+__device__ inline double2 hb_refl_slots(double2 x, bool valid, int f, double2 &tau, double &beta) {
+    const int lane = threadIdx.x & 63;
+    x = zsel(valid, x, make_double2(0.0, 0.0));
+    const double t2 = wave_sum_dpp(lane != f ? zabs2(x) : 0.0);
+    const double2 alpha = make_double2(lane_f64(x.x, f), lane_f64(x.y, f));
+    double2 scale;
+    if (t2 == 0.0 && alpha.y == 0.0) {
+        beta = alpha.x;
+        tau = make_double2(0.0, 0.0);
+        scale = make_double2(0.0, 0.0);
+    } else {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + t2);
+        beta = -copysign(nrm, alpha.x);
+        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        scale = zdiv(make_double2(1.0, 0.0), make_double2(alpha.x - beta, alpha.y));
+    }
+    return zsel(valid, zsel(lane == f, make_double2(1.0, 0.0), zmul(scale, x)), make_double2(0.0, 0.0));
+}
+
+template <int BM, int NT, class E>
+__global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
+    constexpr int TPR = NT / BM;    // lanes per row
+    constexpr int NU = BM / TPR;    // row elements per lane
+    constexpr int NWV = NT / 64;    // waves
+    static_assert(BM <= 64 && NT % 64 == 0 && NWV >= 2 && TPR == 8, "one wave holds a reflector; two waves post; 8 lanes per row");
+    __shared__ double2 Es[BM][BM + 1];
+    __shared__ double2 vs[BM], v2s[BM], pv[BM], xs[BM], ms[BM + 1], colf[BM];
+    __shared__ double2 sh_tau;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = tid / TPR, q = tid % TPR;
+    const int w = blockIdx.x;
+    const int n = a.n, b = a.b, ldb = a.ldb, J = a.J;
+    const E *AB = a.AB;
+    const double2 zero = make_double2(0.0, 0.0);
+    double2 Dr[NU];
+    const int nsw = n - 1 - w * b;   // sweeps with a nonempty window w
+    for (int s = 0; s < nsw; ++s) {
+        const int r0 = s + 1 + w * b;
+        const int L = min(b, n - r0), Le = min(b, n - r0 - b);
+        const int f = r0 % b;   // slot of the window's first index
+        // window position of slot k (b for slots beyond the band width)
+        auto widx = [&](int k) { return k >= b ? b : (k >= f ? k - f : k - f + b); };
+        const int ir = widx(row);
+        if (s == 0) {
+            // ---- first window, read from the band ---------------------------------------
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int ik = widx(q + TPR * u);
+                const bool in = ir < L && ik < L;
+                const int i = in ? ir : 0, k = in ? ik : 0;
+                const bool low = i >= k;
+                const double2 d = El<E>::to(AB[(low ? i - k : k - i) + (size_t)(r0 + (low ? k : i)) * ldb]);
+                Dr[u] = zsel(in, make_double2(d.x, low ? d.y : -d.y), zero);
+            }
+            for (int t = tid; t < BM * BM; t += NT) {
+                const int rho = t % BM, kap = t / BM;
+                const int i = widx(rho), k = widx(kap);
+                const bool in = i < Le && k < L;
+                const double2 ev = El<E>::to(AB[in ? (b + i - k) + (size_t)(r0 + k) * ldb : (size_t)r0 * ldb]);
+                Es[rho][kap] = zsel(in, ev, zero);
+            }
+            if (w == 0 && tid < BM) {
+                const int i = widx(tid);
+                xs[tid] = zsel(i < L, El<E>::to(AB[1 + (i < L ? i : 0)]), zero);
+                if (tid == 0) a.d[0] = El<E>::to(AB[0]).x;
+            }
+        } else if (w == 0) {
+            // ---- column s (index r0 - 1, slot t) from the previous window --------------
+            const int t = f > 0 ? f - 1 : b - 1;
+            if (q == t % TPR) {
+                double2 dv = zero;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) dv = zsel(u == t / TPR, Dr[u], dv);
+                if (row == t) {
+                    xs[row] = Es[t][t];
+                    a.d[r0 - 1] = dv.x;   // d_s
+                } else if (row < b) {
+                    xs[row] = zsel(ir < L, dv, zero);
+                }
+            }
+        }
+        // ---- wave 0: receive the reflector (from w-1) and the entering column (from
+        // w+1) into LDS ----------------------------------------------------------------------
+        const int c = r0 - 1 + b;
+        const bool shift_in = s > 0 && c <= n - 1;
+        if (wave == 0) {
+            const unsigned tag = (unsigned)s + 1;
+            const unsigned long long *bh = a.boxH + ((size_t)w * 2 + (s & 1)) * (BM + 1) * 4;
+            const unsigned long long *bs = a.boxS + ((size_t)w * 2 + (s & 1)) * (BM + 1) * 4;
+            // lane i takes entry i of each message; lane 0 also the last entry (tau of the
+            // reflector at BM, the element below the column at b)
+            double2 h0 = zero, h1 = zero, s0 = zero, s1 = zero;
+            if (w > 0 || shift_in) {
+                // bounded: a wait that gives up sets *err, and every wait that sees *err
+                // set returns at once, so the launch always ends (the host side then
+                // reports d_info = 2n+2: the band is not valid)
+                long spins = 0;
+                for (;;) {
+                    bool ok = true;
+                    if (w > 0) {
+                        if (lane < BM) ok &= msg_get(bh + 4 * lane, tag, h0);
+                        if (lane == 0) ok &= msg_get(bh + 4 * BM, tag, h1);
+                    }
+                    if (shift_in) {
+                        if (lane <= b) ok &= msg_get(bs + 4 * lane, tag, s0);
+                        if (lane == 0 && b == 64) ok &= msg_get(bs + 4 * 64, tag, s1);
+                    }
+                    if (__all(ok)) break;
+                    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1L << 27)) {
+                        __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+            }
+            if (w > 0 && lane < BM) {
+                // window order -> slots
+                if (lane < b) vs[(f + lane) % b] = zsel(lane < L, h0, zero);
+                else vs[lane] = zero;
+                if (lane == 0) sh_tau = h1;
+            }
+            if (s > 0) {
+                if (lane <= BM) ms[lane] = zsel(shift_in && lane <= b, s0, zero);
+                if (lane == 0 && BM == 64) ms[64] = zsel(shift_in && b == 64, s1, zero);
+            }
+        }
+        __syncthreads();
+        if (s > 0) {
+            // ---- move the window: slot t now holds index c ------------------------------
+            const int t = f > 0 ? f - 1 : b - 1;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = q + TPR * u;
+                if (row == t) Dr[u] = zsel(k == t, make_double2(ms[0].x, 0.0), Es[t][k]);
+                else if (k == t) Dr[u] = zconj(Es[t][row]);
+            }
+            __syncthreads();
+            if (tid < BM) {
+                if (tid != t) {
+                    Es[t][tid] = zero;
+                    Es[tid][t] = zsel(tid < b, ms[tid < b ? (tid > t ? tid - t : tid - t + b) : 0], zero);
+                } else {
+                    Es[t][t] = ms[b];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- H_{s,0}: workgroup 0 makes it from column s ---------------------------------
+        if (w == 0) {
+            if (tid < 64) {
+                double2 tau;
+                double beta;
+                const bool valid = lane < BM && widx(lane) < L;
+                const double2 v = hb_refl_slots(xs[lane < BM ? lane : 0], valid, f, tau, beta);
+                if (lane < BM) vs[lane] = v;
+                if (lane == 0) {
+                    sh_tau = tau;
+                    a.e[r0 - 1] = beta;   // e_s
+                }
+                if (a.V2) {
+                    const int src = lane < b ? (f + lane) % b : 0;
+                    const double2 vi = make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+                    const size_t base = ((size_t)(s / b) * J + 0) * b + s % b;
+                    if (lane < b) a.V2[base * b + lane] = El<E>::from(vi);
+                    if (lane == 0) a.tau2[base] = El<E>::from(tau);
+                }
+            }
+            __syncthreads();
+        }
+        const double2 tau = sh_tau;
+        // ---- y = E v (E <- E H_{s,w}) and p = tau D v, in one pass ------------------------
+        {
+            double2 ay = zero, ap = zero;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = q + TPR * u;
+                const double2 vk = vs[k];
+                ay = zadd(ay, zmul(Es[row][k], vk));
+                ap = zadd(ap, zmul(Dr[u], vk));
+            }
+            const double2 y = zmul(tau, sum8_dpp(ay));
+            const double2 prow = zmul(tau, sum8_dpp(ap));
+            if (Le > 0) {
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int k = q + TPR * u;
+                    Es[row][k] = zsub(Es[row][k], zmul(y, zconj(vs[k])));
+                }
+            }
+            if (q == 0) pv[row] = prow;
+        }
+        __syncthreads();
+        // ---- every wave: H_{s,w+1} from E's first column and the scalar of the D update
+        // (the same operations in the same order in every wave, so every wave holds the
+        // same values and no wave waits for another) ------------------------------------
+        double2 v2 = zero, tau2 = zero;
+        double beta2 = 0.0;
+        if (Le > 0) {
+            const bool valid = lane < BM && widx(lane) < Le;
+            v2 = hb_refl_slots(Es[lane < BM ? lane : 0][f], valid, f, tau2, beta2);
+        }
+        const double2 c1 = zsel(lane < BM, zcmul(vs[lane < BM ? lane : 0], pv[lane < BM ? lane : 0]), zero);
+        const double half = 0.5 * zcmul(tau, make_double2(wave_sum_dpp(c1.x), wave_sum_dpp(c1.y))).x;
+        const bool post_h = Le > 0 && wave == 0;
+        if (post_h) {
+            // H_{s,w+1} to w+1, in the window order of window w+1 (position i at slot
+            // (f + i) mod b)
+            if (lane < BM) v2s[lane] = v2;
+            const int src = lane < b ? (f + lane) % b : 0;
+            const double2 vi = make_double2(__shfl(v2.x, src, 64), __shfl(v2.y, src, 64));
+            unsigned long long *bx = a.boxH + ((size_t)(w + 1) * 2 + (s & 1)) * (BM + 1) * 4;
+            if (lane < BM) msg_put(bx + 4 * lane, zsel(lane < b, vi, zero), (unsigned)s + 1);
+            if (lane == 0) msg_put(bx + 4 * BM, tau2, (unsigned)s + 1);
+            if (a.V2) {
+                const size_t base = ((size_t)(s / b) * J + (w + 1)) * b + s % b;
+                if (lane < b) a.V2[base * b + lane] = El<E>::from(vi);
+                if (lane == 0) a.tau2[base] = El<E>::from(tau2);
+            }
+        }
+        // ---- D <- H^H D H  with  w = p - 1/2 conj(tau) (v^H p) v ----------------------------
+        {
+            const double2 vrow = vs[row];
+            const double2 wrow = zsub(pv[row], zscale(half, vrow));
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = q + TPR * u;
+                const double2 wk = zsub(pv[k], zscale(half, vs[k]));
+                double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(vs[k])));
+                if (k == row) val.y = 0.0;
+                Dr[u] = val;
+            }
+        }
+        // ---- the band column of index r0 (it leaves this window next sweep) -> w-1 ----------
+        if (w > 0 && q == f % TPR && row < b) {
+            double2 dv = zero;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) dv = zsel(u == f / TPR, Dr[u], dv);
+            colf[ir] = zsel(ir < L, dv, zero);
+        }
+        __syncthreads();
+        if (w > 0 && wave == NWV - 1) {
+            // for sweep s+1 of w-1: entries 0 .. b-1 the column, entry b the element below it
+            unsigned long long *bx = a.boxS + ((size_t)(w - 1) * 2 + ((s + 1) & 1)) * (BM + 1) * 4;
+            const double2 below = zsel(Le > 0, make_double2(beta2, 0.0), zero);
+            if (lane < b) msg_put(bx + 4 * lane, colf[lane], (unsigned)s + 2);
+            else if (lane == b) msg_put(bx + 4 * b, below, (unsigned)s + 2);
+            if (lane == 0 && b == 64) msg_put(bx + 4 * 64, below, (unsigned)s + 2);
+        }
+        if (Le > 0) {
+            // ---- E <- H_{s,w+1}^H E; its first column becomes beta e_f ----------------------
+            const int cc = row;   // lane group -> column
+            double2 acc = zero;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int i = q + TPR * u;
+                acc = zadd(acc, zcmul(v2s[i], Es[i][cc]));
+            }
+            const double2 wc = zcmul(tau2, sum8_dpp(acc));
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int i = q + TPR * u;
+                Es[i][cc] = zsel(cc == f, zsel(i == f, make_double2(beta2, 0.0), zero),
+                                 zsub(Es[i][cc], zmul(v2s[i], wc)));
+            }
+        }
+        __syncthreads();
+    }
+    if (w == 0 && n >= 2) {
+        // d_{n-1}: the last diagonal element, in the one-element window of the last sweep
+        const int t = (n - 1) % b;
+        if (row == t && q == t % TPR) {
+            double2 dv = zero;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) dv = zsel(u == t / TPR, Dr[u], dv);
+            a.d[n - 1] = dv.x;
+        }
+    }
+}
+
 // Copy the lower band (offsets 0..b) of A into band storage; offsets b+1..2b-1 zero.
 template <class E>
 __global__ void band_copy_kernel(int n, int b, const E *A, int lda, E *AB, int ldb) {
@@ -419,14 +801,33 @@ static void launch_hb2st(hgv_ctx_s *ctx, HbArgs<E> &a) {
                                        args, 0, ctx->stream));
 }
 
+// The window-owner pipeline needs one resident workgroup per window of sweep 0;
+// returns false (use the sweep-per-workgroup kernel) when they do not fit.
+template <int BM, int NT, class E>
+static bool launch_hb2st_owner(hgv_ctx_s *ctx, HbOwnArgs<E> &a) {
+    int dev = ctx->device, cus = 0, per = 0;
+    HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, hb2st_owner_kernel<BM, NT, E>, NT, 0));
+    if (a.J < 1 || a.J > cus * per) return false;
+    void *args[] = {&a};
+    HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(hb2st_owner_kernel<BM, NT, E>), dim3(a.J), dim3(NT),
+                                       args, 0, ctx->stream));
+    return true;
+}
+
 template <class E>
 void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, double *e, E *V2, E *tau2, Arena &ar,
              int *d_info) {
     if (nb > 64) throw HipFail{hipErrorInvalidValue};
     const int b = nb, ldb = 2 * nb;
+    const int BM = b <= 32 ? 32 : 64, J = hb_J(n, b);
     E *AB = ar.take<E>((size_t)ldb * std::max(n, 1));
     int *prog = ar.take<int>(std::max(n, 1) + 1);
     int *err = prog + std::max(n, 1);
+    // mailboxes of the window-owner pipeline (both zeroed together before a launch)
+    const size_t box_words = (size_t)std::max(J, 1) * 2 * (BM + 1) * 4;
+    unsigned long long *boxH = ar.take<unsigned long long>(2 * box_words);
+    unsigned long long *boxS = boxH + box_words;
     if (ar.measuring() || n == 0) return;
     hipLaunchKernelGGL(band_copy_kernel<E>, dim3(cdiv(n, 256 / ldb)), dim3(256), 0, ctx->stream, n, b, A, lda, AB,
                        ldb);
@@ -439,12 +840,26 @@ void hb2st_t(hgv_ctx_s *ctx, int n, int nb, const E *A, int lda, double *d, doub
     HGV_LAUNCH_CHECK();
     if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, err, 1);
     if (n >= 2) {
-        HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, hb_J(n, b)};
-        // 64-wide bands: 512 threads (8 elements of a task's diagonal block per
-        // thread), which shortens the arithmetic of the dependent task chain
-        if (b <= 32) launch_hb2st<32, 256, E>(ctx, a);
-        else launch_hb2st<64, 512, E>(ctx, a);
+        bool done = false;
+        // (not while problems run concurrently on side streams: the pipeline's
+        // workgroups must all be resident at once)
+        if (!(ctx->test_hooks & HGV_TEST_HB2ST_SWEEPS) && !ctx->concurrent) {
+            const int words = (int)(4 * box_words);   // as ints
+            hipLaunchKernelGGL(zero_int_kernel, dim3(std::min(cdiv(words, 256), 4096)), dim3(256), 0, ctx->stream,
+                               reinterpret_cast<int *>(boxH), words);
+            HGV_LAUNCH_CHECK();
+            HbOwnArgs<E> o{n, b, ldb, J, AB, V2, tau2, d, e, boxH, boxS, err};
+            done = b <= 32 ? launch_hb2st_owner<32, 256, E>(ctx, o) : launch_hb2st_owner<64, 512, E>(ctx, o);
+        }
+        if (!done) {
+            HbArgs<E> a{n, b, ldb, AB, V2, tau2, prog, err, J};
+            // 64-wide bands: 512 threads (8 elements of a task's diagonal block per
+            // thread), which shortens the arithmetic of the dependent task chain
+            if (b <= 32) launch_hb2st<32, 256, E>(ctx, a);
+            else launch_hb2st<64, 512, E>(ctx, a);
+        }
         report_wait_fail(ctx, err, d_info, 2 * n + 2);
+        if (done) return;   // the pipeline wrote d and e
     }
     hipLaunchKernelGGL(tridiag_out_kernel<E>, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, AB, ldb, d, e);
     HGV_LAUNCH_CHECK();

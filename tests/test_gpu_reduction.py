@@ -57,9 +57,19 @@ def test_he2hb_reconstruction(ctx, n, nb):
     np.testing.assert_allclose(np.linalg.eigvalsh(band), np.linalg.eigvalsh(A), atol=_tol(n) * np.abs(A).max() * n)
 
 
+@pytest.fixture(params=["owners", "sweeps"])
+def schedule(request, ctx):
+    """The two bulge-chasing schedules: one workgroup per window for all sweeps (the
+    default), or one workgroup per sweep (used when the windows do not all fit)."""
+    import paper_1207_1773_amd as hgv
+    hgv.hgv_test_hooks(ctx.handle, hgv.HGV_TEST_HB2ST_SWEEPS if request.param == "sweeps" else 0)
+    yield request.param
+    hgv.hgv_test_hooks(ctx.handle, 0)
+
+
 @pytest.mark.parametrize("n,b", [(1, 3), (2, 1), (3, 2), (10, 3), (64, 8), (100, 32), (101, 7), (257, 16),
-                                 (300, 32), (150, 64)])
-def test_hb2st_properties(ctx, n, b):
+                                 (300, 32), (150, 64), (130, 64), (129, 64), (200, 48), (66, 33), (7, 64)])
+def test_hb2st_properties(ctx, schedule, n, b):
     band = random_band(n, b, 200 + n)
     d, e, V2, tau2 = ctx.hb2st(to_dev(band), b)
     d, e = to_np(d), to_np(e)
@@ -71,13 +81,34 @@ def test_hb2st_properties(ctx, n, b):
     assert np.linalg.norm(Q2.conj().T @ Q2 - np.eye(n)) < _tol(n) * np.sqrt(n)
 
 
-def test_hb2st_bitwise_repeatable(ctx):
-    n, b = 700, 32
+@pytest.mark.parametrize("n,b", [(700, 32), (1500, 64)])
+def test_hb2st_bitwise_repeatable(ctx, schedule, n, b):
     band = random_band(n, b, 7)
     runs = [ctx.hb2st(to_dev(band), b) for _ in range(3)]
     for r in runs[1:]:
         for x, y in zip(runs[0], r):
             assert torch_equal(x, y)
+
+
+@pytest.mark.parametrize("n,b", [(1000, 64), (777, 32), (500, 48)])
+def test_hb2st_schedules_agree(ctx, n, b):
+    """Both schedules apply the same reflectors in the same order (only the summation
+    order inside a task differs), so T and Q2 agree to rounding."""
+    import paper_1207_1773_amd as hgv
+    band = random_band(n, b, 11 + n)
+    out = {}
+    for mode in (0, hgv.HGV_TEST_HB2ST_SWEEPS):
+        hgv.hgv_test_hooks(ctx.handle, mode)
+        try:
+            d, e, V2, tau2 = ctx.hb2st(to_dev(band), b)
+        finally:
+            hgv.hgv_test_hooks(ctx.handle, 0)
+        out[mode] = (to_np(d), to_np(e), to_np(V2), to_np(tau2))
+    (d0, e0, V0, t0), (d1, e1, V1, t1) = out[0], out[hgv.HGV_TEST_HB2ST_SWEEPS]
+    scale = np.abs(band).max() * n
+    assert np.abs(d0 - d1).max() < 1e-13 * scale
+    assert np.abs(e0 - e1).max() < 1e-13 * scale
+    assert np.abs(V0 - V1).max() < 1e-10 and np.abs(t0 - t1).max() < 1e-10
 
 
 def torch_equal(x, y):
