@@ -415,15 +415,32 @@ __device__ inline void msg_put(unsigned long long *p, double2 v, unsigned tag) {
     __hip_atomic_store(p + 3, t | (y >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// true when all four words carry the tag; v is then the value sent
-__device__ inline bool msg_get(const unsigned long long *p, unsigned tag, double2 &v) {
-    const unsigned long long a = __hip_atomic_load(p + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long c = __hip_atomic_load(p + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long d = __hip_atomic_load(p + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    v.x = __longlong_as_double((long long)(((b & 0xffffffffull) << 32) | (a & 0xffffffffull)));
-    v.y = __longlong_as_double((long long)(((d & 0xffffffffull) << 32) | (c & 0xffffffffull)));
-    return (a >> 32) == tag && (b >> 32) == tag && (c >> 32) == tag && (d >> 32) == tag;
+// One poll of a lane: the four words of up to four message entries (e0, e1 for
+// every lane; e2, e3 only used by lane 0).
+struct MsgPoll {
+    unsigned long long x[16];
+};
+__device__ inline void msg_issue(MsgPoll &P, const unsigned long long *e0, const unsigned long long *e1,
+                                 const unsigned long long *e2, const unsigned long long *e3) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        P.x[k] = __hip_atomic_load(e0 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.x[4 + k] = __hip_atomic_load(e1 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.x[8 + k] = __hip_atomic_load(e2 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.x[12 + k] = __hip_atomic_load(e3 + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+// entry k of the poll carries the tag (or is not wanted)
+__device__ inline bool msg_ok(const MsgPoll &P, unsigned tag, unsigned want) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ok &= !((want >> (k >> 2)) & 1u) || (P.x[k] >> 32) == tag;
+    return ok;
+}
+__device__ inline double2 msg_val(const MsgPoll &P, int k) {
+    const unsigned long long *x = P.x + 4 * k;
+    return make_double2(__longlong_as_double((long long)(((x[1] & 0xffffffffull) << 32) | (x[0] & 0xffffffffull))),
+                        __longlong_as_double((long long)(((x[3] & 0xffffffffull) << 32) | (x[2] & 0xffffffffull))));
 }
 
 // Reductions of the pipeline kernel by DPP lane moves (no LDS round trips).  A
@@ -488,7 +505,7 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
     constexpr int NWV = NT / 64;    // waves
     static_assert(BM <= 64 && NT % 64 == 0 && NWV >= 2 && TPR == 8, "one wave holds a reflector; two waves post; 8 lanes per row");
     __shared__ double2 Es[BM][BM + 1];
-    __shared__ double2 vs[BM], v2s[BM], pv[BM], xs[BM], ms[BM + 1], colf[BM];
+    __shared__ double2 vs[BM], v2s[BM], pv[BM], yv[BM], xs[BM], ms[BM + 1];
     __shared__ double2 sh_tau;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int row = tid / TPR, q = tid % TPR;
@@ -529,17 +546,31 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
                 if (tid == 0) a.d[0] = El<E>::to(AB[0]).x;
             }
         } else if (w == 0) {
-            // ---- column s (index r0 - 1, slot t) from the previous window --------------
-            const int t = f > 0 ? f - 1 : b - 1;
-            if (q == t % TPR) {
+            // ---- column s (index r0 - 1, slot t0) from the previous window -------------
+            const int t0 = f > 0 ? f - 1 : b - 1;
+            if (q == t0 % TPR) {
                 double2 dv = zero;
 #pragma unroll
-                for (int u = 0; u < NU; ++u) dv = zsel(u == t / TPR, Dr[u], dv);
-                if (row == t) {
-                    xs[row] = Es[t][t];
+                for (int u = 0; u < NU; ++u) dv = zsel(u == t0 / TPR, Dr[u], dv);
+                if (row == t0) {
+                    xs[row] = Es[t0][t0];
                     a.d[r0 - 1] = dv.x;   // d_s
                 } else if (row < b) {
                     xs[row] = zsel(ir < L, dv, zero);
+                }
+            }
+        }
+        // ---- move the window (slot t: index c - b leaves, c enters), first the part
+        // that uses only local data: row c of E becomes the new row (and column) c of D
+        const int t = f > 0 ? f - 1 : b - 1;
+        if (s > 0) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int k = q + TPR * u;
+                if (row == t) {
+                    if (k != t) Dr[u] = Es[t][k];
+                } else if (k == t) {
+                    Dr[u] = zconj(Es[t][row]);
                 }
             }
         }
@@ -555,24 +586,38 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
             // reflector at BM, the element below the column at b)
             double2 h0 = zero, h1 = zero, s0 = zero, s1 = zero;
             if (w > 0 || shift_in) {
-                // bounded: a wait that gives up sets *err, and every wait that sees *err
+                const unsigned want = (w > 0 && lane < BM ? 1u : 0u) | (shift_in && lane <= b ? 2u : 0u) |
+                                      (w > 0 && lane == 0 ? 4u : 0u) | (shift_in && lane == 0 && b == 64 ? 8u : 0u);
+                const unsigned long long *e0 = bh + 4 * (lane < BM ? lane : 0);
+                const unsigned long long *e1 = bs + 4 * (lane <= b ? lane : 0);
+                const unsigned long long *e2 = bh + 4 * BM;
+                const unsigned long long *e3 = bs + 4 * (b == 64 ? 64 : 0);
+                // two polls in flight: each is checked while the next one is out, which
+                // halves the time between a message landing and a poll reading it.
+                // Bounded: a wait that gives up sets *err, and every wait that sees *err
                 // set returns at once, so the launch always ends (the host side then
                 // reports d_info = 2n+2: the band is not valid)
-                long spins = 0;
-                for (;;) {
-                    bool ok = true;
-                    if (w > 0) {
-                        if (lane < BM) ok &= msg_get(bh + 4 * lane, tag, h0);
-                        if (lane == 0) ok &= msg_get(bh + 4 * BM, tag, h1);
+                MsgPoll PA, PB;
+                msg_issue(PA, e0, e1, e2, e3);
+                for (long spins = 0;; spins += 2) {
+                    msg_issue(PB, e0, e1, e2, e3);
+                    if (__all(msg_ok(PA, tag, want))) {
+                        h0 = msg_val(PA, 0);
+                        s0 = msg_val(PA, 1);
+                        h1 = msg_val(PA, 2);
+                        s1 = msg_val(PA, 3);
+                        break;
                     }
-                    if (shift_in) {
-                        if (lane <= b) ok &= msg_get(bs + 4 * lane, tag, s0);
-                        if (lane == 0 && b == 64) ok &= msg_get(bs + 4 * 64, tag, s1);
+                    msg_issue(PA, e0, e1, e2, e3);
+                    if (__all(msg_ok(PB, tag, want))) {
+                        h0 = msg_val(PB, 0);
+                        s0 = msg_val(PB, 1);
+                        h1 = msg_val(PB, 2);
+                        s1 = msg_val(PB, 3);
+                        break;
                     }
-                    if (__all(ok)) break;
                     if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1L << 27)) {
+                    if (spins > (1L << 28)) {
                         __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         break;
                     }
@@ -591,24 +636,19 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
         }
         __syncthreads();
         if (s > 0) {
-            // ---- move the window: slot t now holds index c ------------------------------
-            const int t = f > 0 ? f - 1 : b - 1;
+            // ---- the rest of the move, each thread on its own elements: E's row t now
+            // holds row c + b (in the band only at column c), its column t column c below
+            // the diagonal, D[t][t] the diagonal element of index c
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int k = q + TPR * u;
-                if (row == t) Dr[u] = zsel(k == t, make_double2(ms[0].x, 0.0), Es[t][k]);
-                else if (k == t) Dr[u] = zconj(Es[t][row]);
-            }
-            __syncthreads();
-            if (tid < BM) {
-                if (tid != t) {
-                    Es[t][tid] = zero;
-                    Es[tid][t] = zsel(tid < b, ms[tid < b ? (tid > t ? tid - t : tid - t + b) : 0], zero);
-                } else {
-                    Es[t][t] = ms[b];
+                if (row == t) {
+                    Es[t][k] = zsel(k == t, ms[b], zero);
+                    if (k == t) Dr[u] = make_double2(ms[0].x, 0.0);
+                } else if (k == t) {
+                    Es[row][t] = zsel(row < b, ms[row < b ? (row > t ? row - t : row - t + b) : 0], zero);
                 }
             }
-            __syncthreads();
         }
         // ---- H_{s,0}: workgroup 0 makes it from column s ---------------------------------
         if (w == 0) {
@@ -623,65 +663,61 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
                     a.e[r0 - 1] = beta;   // e_s
                 }
                 if (a.V2) {
-                    const int src = lane < b ? (f + lane) % b : 0;
-                    const double2 vi = make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+                    // slot lane -> window position widx(lane)
                     const size_t base = ((size_t)(s / b) * J + 0) * b + s % b;
-                    if (lane < b) a.V2[base * b + lane] = El<E>::from(vi);
+                    if (lane < b) a.V2[base * b + widx(lane)] = El<E>::from(v);
                     if (lane == 0) a.tau2[base] = El<E>::from(tau);
                 }
             }
             __syncthreads();
         }
         const double2 tau = sh_tau;
-        // ---- y = E v (E <- E H_{s,w}) and p = tau D v, in one pass ------------------------
+        // ---- y = tau E v and p = tau D v, one pass over the thread's row (E is
+        // updated once, after both messages are out) -----------------------------------------
+        double2 vr[NU];   // v at the thread's column slots
+#pragma unroll
+        for (int u = 0; u < NU; ++u) vr[u] = vs[q + TPR * u];
         {
             double2 ay = zero, ap = zero;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                const int k = q + TPR * u;
-                const double2 vk = vs[k];
-                ay = zadd(ay, zmul(Es[row][k], vk));
-                ap = zadd(ap, zmul(Dr[u], vk));
+                ay = zadd(ay, zmul(Es[row][q + TPR * u], vr[u]));
+                ap = zadd(ap, zmul(Dr[u], vr[u]));
             }
             const double2 y = zmul(tau, sum8_dpp(ay));
             const double2 prow = zmul(tau, sum8_dpp(ap));
-            if (Le > 0) {
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int k = q + TPR * u;
-                    Es[row][k] = zsub(Es[row][k], zmul(y, zconj(vs[k])));
-                }
+            if (q == 0) {
+                yv[row] = y;
+                pv[row] = prow;
             }
-            if (q == 0) pv[row] = prow;
         }
         __syncthreads();
-        // ---- every wave: H_{s,w+1} from E's first column and the scalar of the D update
-        // (the same operations in the same order in every wave, so every wave holds the
-        // same values and no wave waits for another) ------------------------------------
+        // ---- every wave: H_{s,w+1} from the first column of E H_{s,w} = E - y v^H, and
+        // the scalars of the updates (the same operations in the same order in every wave,
+        // so every wave holds the same values and none waits for another) ----------------
+        const double2 vf = vs[f];
+        const int l = lane < BM ? lane : 0;
         double2 v2 = zero, tau2 = zero;
         double beta2 = 0.0;
         if (Le > 0) {
             const bool valid = lane < BM && widx(lane) < Le;
-            v2 = hb_refl_slots(Es[lane < BM ? lane : 0][f], valid, f, tau2, beta2);
-        }
-        const double2 c1 = zsel(lane < BM, zcmul(vs[lane < BM ? lane : 0], pv[lane < BM ? lane : 0]), zero);
-        const double half = 0.5 * zcmul(tau, make_double2(wave_sum_dpp(c1.x), wave_sum_dpp(c1.y))).x;
-        const bool post_h = Le > 0 && wave == 0;
-        if (post_h) {
-            // H_{s,w+1} to w+1, in the window order of window w+1 (position i at slot
-            // (f + i) mod b)
-            if (lane < BM) v2s[lane] = v2;
-            const int src = lane < b ? (f + lane) % b : 0;
-            const double2 vi = make_double2(__shfl(v2.x, src, 64), __shfl(v2.y, src, 64));
-            unsigned long long *bx = a.boxH + ((size_t)(w + 1) * 2 + (s & 1)) * (BM + 1) * 4;
-            if (lane < BM) msg_put(bx + 4 * lane, zsel(lane < b, vi, zero), (unsigned)s + 1);
-            if (lane == 0) msg_put(bx + 4 * BM, tau2, (unsigned)s + 1);
-            if (a.V2) {
-                const size_t base = ((size_t)(s / b) * J + (w + 1)) * b + s % b;
-                if (lane < b) a.V2[base * b + lane] = El<E>::from(vi);
-                if (lane == 0) a.tau2[base] = El<E>::from(tau2);
+            v2 = hb_refl_slots(zsub(Es[l][f], zmul(yv[l], zconj(vf))), valid, f, tau2, beta2);
+            if (wave == 0) {
+                // H_{s,w+1} to w+1, in the window order of window w+1: slot lane goes to
+                // position widx(lane) (positions b .. BM-1 are zero)
+                if (lane < BM) v2s[lane] = v2;
+                unsigned long long *bx = a.boxH + ((size_t)(w + 1) * 2 + (s & 1)) * (BM + 1) * 4;
+                if (lane < BM) msg_put(bx + 4 * (lane < b ? widx(lane) : lane), v2, (unsigned)s + 1);
+                if (lane == 0) msg_put(bx + 4 * BM, tau2, (unsigned)s + 1);
+                if (a.V2) {
+                    const size_t base = ((size_t)(s / b) * J + (w + 1)) * b + s % b;
+                    if (lane < b) a.V2[base * b + widx(lane)] = El<E>::from(v2);
+                    if (lane == 0) a.tau2[base] = El<E>::from(tau2);
+                }
             }
         }
+        const double2 c1 = zsel(lane < BM, zcmul(vs[l], pv[l]), zero);
+        const double half = 0.5 * zcmul(tau, make_double2(wave_sum_dpp(c1.x), wave_sum_dpp(c1.y))).x;
         // ---- D <- H^H D H  with  w = p - 1/2 conj(tau) (v^H p) v ----------------------------
         {
             const double2 vrow = vs[row];
@@ -689,43 +725,46 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int k = q + TPR * u;
-                const double2 wk = zsub(pv[k], zscale(half, vs[k]));
-                double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(vs[k])));
+                const double2 wk = zsub(pv[k], zscale(half, vr[u]));
+                double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(vr[u])));
                 if (k == row) val.y = 0.0;
                 Dr[u] = val;
             }
         }
-        // ---- the band column of index r0 (it leaves this window next sweep) -> w-1 ----------
-        if (w > 0 && q == f % TPR && row < b) {
-            double2 dv = zero;
-#pragma unroll
-            for (int u = 0; u < NU; ++u) dv = zsel(u == f / TPR, Dr[u], dv);
-            colf[ir] = zsel(ir < L, dv, zero);
-        }
-        __syncthreads();
-        if (w > 0 && wave == NWV - 1) {
-            // for sweep s+1 of w-1: entries 0 .. b-1 the column, entry b the element below it
+        // ---- the band column of index r0 (it leaves this window next sweep) -> w-1, for
+        // its sweep s+1: positions 0 .. b-1 the column, position b the element below it;
+        // each thread of column f sends its own element ----------------------------------
+        if (w > 0) {
             unsigned long long *bx = a.boxS + ((size_t)(w - 1) * 2 + ((s + 1) & 1)) * (BM + 1) * 4;
-            const double2 below = zsel(Le > 0, make_double2(beta2, 0.0), zero);
-            if (lane < b) msg_put(bx + 4 * lane, colf[lane], (unsigned)s + 2);
-            else if (lane == b) msg_put(bx + 4 * b, below, (unsigned)s + 2);
-            if (lane == 0 && b == 64) msg_put(bx + 4 * 64, below, (unsigned)s + 2);
+            if (q == f % TPR && row < b) {
+                double2 dv = zero;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) dv = zsel(u == f / TPR, Dr[u], dv);
+                msg_put(bx + 4 * ir, zsel(ir < L, dv, zero), (unsigned)s + 2);
+            }
+            if (tid == 0) msg_put(bx + 4 * b, zsel(Le > 0, make_double2(beta2, 0.0), zero), (unsigned)s + 2);
         }
         if (Le > 0) {
-            // ---- E <- H_{s,w+1}^H E; its first column becomes beta e_f ----------------------
+            // ---- E <- H_{s,w+1}^H (E - y v^H), first column beta e_f:  with
+            // u = v2^H E and vy = v2^H y,  E[i][c] -= y_i conj(v_c) + conj(tau2) v2_i
+            // (u_c - vy conj(v_c)) ----------------------------------------------------------
+            const double2 c2 = zsel(lane < BM, zcmul(v2, yv[l]), zero);
+            const double2 vy = make_double2(wave_sum_dpp(c2.x), wave_sum_dpp(c2.y));
+            __syncthreads();   // v2s
             const int cc = row;   // lane group -> column
+            const double2 vc = zconj(vs[cc]);
             double2 acc = zero;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = q + TPR * u;
                 acc = zadd(acc, zcmul(v2s[i], Es[i][cc]));
             }
-            const double2 wc = zcmul(tau2, sum8_dpp(acc));
+            const double2 wc = zcmul(tau2, zsub(sum8_dpp(acc), zmul(vy, vc)));
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = q + TPR * u;
-                Es[i][cc] = zsel(cc == f, zsel(i == f, make_double2(beta2, 0.0), zero),
-                                 zsub(Es[i][cc], zmul(v2s[i], wc)));
+                const double2 upd = zsub(zsub(Es[i][cc], zmul(yv[i], vc)), zmul(v2s[i], wc));
+                Es[i][cc] = zsel(cc == f, zsel(i == f, make_double2(beta2, 0.0), zero), upd);
             }
         }
         __syncthreads();
