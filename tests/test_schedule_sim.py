@@ -15,6 +15,16 @@ I_j = rows s+1+j*b .. s+(j+1)*b), and run
   * with the rule weakened to min(j + 1, all), where some order must differ (the rule is
     not slack: one task less of lag lets a task read a block its predecessor sweep has not
     finished).
+
+The second part models the window-owner schedule of the same tasks: owner w keeps, for
+every sweep s, the diagonal block of the rows I_w(s) and the block below it, index i at
+slot i mod b, and talks to its neighbours only through mailboxes: the reflector H_{s,w+1}
+to owner w+1, and the band column of the index leaving its window to owner w-1.  Owners
+are generators that yield before every mailbox read; a random scheduler runs them.  Checked:
+no order deadlocks, no mailbox is written again before its reader has taken the previous
+message (so one buffer per mailbox would suffice), every order gives the same d, e and
+reflectors bit for bit, d and e agree with the sequential dense model to rounding, and the
+reflectors reproduce Q^H A Q = T.
 """
 import numpy as np
 import pytest
@@ -145,3 +155,160 @@ def test_one_task_less_of_lag_breaks_the_result():
         got = simulate(A0, b, np.random.default_rng(seed), lag=1, workers=4)
         differs += not np.array_equal(got, ref)
     assert differs > 0
+
+
+# ---- window-owner schedule ----------------------------------------------------------------
+
+
+class Box:
+    def __init__(self):
+        self.tag = -1
+        self.data = None
+        self.consumed = True
+
+
+def owner(w, n, b, A0, boxH, boxS, out):
+    """Owner w of the window pipeline (a generator yielding ('wait', box, tag))."""
+    D = np.zeros((b, b), complex)
+    E = np.zeros((b, b), complex)
+    for s in range(n - 1 - w * b):
+        r0 = s + 1 + w * b
+        L = min(b, n - r0)
+        Le = min(b, n - r0 - b)
+        f = r0 % b
+        if s == 0:
+            for i in range(L):
+                for k in range(L):
+                    D[(r0 + i) % b, (r0 + k) % b] = A0[r0 + i, r0 + k]
+            for i in range(max(Le, 0)):
+                for k in range(L):
+                    E[(r0 + i) % b, (r0 + k) % b] = A0[r0 + b + i, r0 + k]
+            if w == 0:
+                x = A0[1:1 + L, 0].copy()
+                out["d"][0] = A0[0, 0].real
+        else:
+            t = (r0 - 1) % b
+            c = r0 - 1 + b
+            if w == 0:   # column s = r0 - 1, the index leaving the window
+                x = np.array([D[(r0 + i) % b, t] if i < b - 1 else E[t, t] for i in range(L)])
+                out["d"][r0 - 1] = D[t, t].real
+            if c <= n - 1:
+                yield ("wait", boxS[w], s)
+                msg = boxS[w].data.copy()
+                boxS[w].consumed = True
+            else:
+                msg = np.zeros(b + 1, complex)
+            row = E[t, :].copy()
+            D[t, :] = row
+            D[:, t] = np.conj(row)
+            D[t, t] = msg[0].real
+            E[t, :] = 0.0
+            for i in range(1, b):
+                E[(c + i) % b, t] = msg[i]
+            E[t, t] = msg[b]
+        if w == 0:
+            v, tau, beta = refl(x)
+            out["e"][r0 - 1] = beta
+            out["V"][(r0 - 1, 0)] = (np.pad(v, (0, b - L)), tau)
+        else:
+            yield ("wait", boxH[w], s)
+            vv, tau = boxH[w].data
+            boxH[w].consumed = True
+            v = vv[:L]
+        vs = np.zeros(b, complex)
+        for i in range(L):
+            vs[(r0 + i) % b] = v[i]
+        if Le > 0:
+            E -= tau * np.outer(E @ vs, np.conj(vs))
+            v2, tau2, beta2 = refl(np.array([E[(r0 + i) % b, f] for i in range(Le)]))
+            bx = boxH[w + 1]
+            assert bx.consumed, "reflector mailbox written before it was read"
+            bx.data, bx.tag, bx.consumed = (np.pad(v2, (0, b - Le)), tau2), s, False
+            out["V"][(s, w + 1)] = (np.pad(v2, (0, b - Le)), tau2)
+            yield ("posted",)
+        p = tau * (D @ vs)
+        half = 0.5 * (np.conj(tau) * np.vdot(vs, p)).real
+        wv = p - half * vs
+        D = D - np.outer(vs, np.conj(wv)) - np.outer(wv, np.conj(vs))
+        D[np.diag_indices(b)] = D.diagonal().real
+        if w >= 1:
+            msg = np.zeros(b + 1, complex)
+            for i in range(L):
+                msg[i] = D[(r0 + i) % b, f]
+            if Le > 0:
+                msg[b] = beta2
+            bx = boxS[w - 1]
+            assert bx.consumed, "column mailbox written before it was read"
+            bx.data, bx.tag, bx.consumed = msg, s + 1, False
+            yield ("posted",)
+        if Le > 0:
+            v2s = np.zeros(b, complex)
+            for i in range(Le):
+                v2s[(r0 + i) % b] = v2[i]
+            E -= np.conj(tau2) * np.outer(v2s, np.conj(v2s) @ E)
+            E[:, f] = 0.0
+            E[f, f] = beta2
+    if w == 0:
+        out["d"][n - 1] = D[(n - 1) % b, (n - 1) % b].real
+
+
+def run_owners(A0, b, rng=None):
+    n = A0.shape[0]
+    J = tasks(n, b, 0)
+    boxH = [Box() for _ in range(J + 1)]
+    boxS = [Box() for _ in range(J + 1)]
+    out = {"d": np.zeros(n), "e": np.zeros(n - 1), "V": {}}
+    gens = {w: owner(w, n, b, A0, boxH, boxS, out) for w in range(J)}
+    pending = {}
+    for w in list(gens):
+        try:
+            pending[w] = next(gens[w])
+        except StopIteration:
+            del gens[w]
+    while gens:
+        ready = [w for w in gens if pending[w][0] != "wait" or pending[w][1].tag == pending[w][2]]
+        assert ready, "schedule deadlocked"
+        w = ready[0] if rng is None else ready[rng.integers(len(ready))]
+        try:
+            pending[w] = gens[w].send(None)
+        except StopIteration:
+            del gens[w]
+    return out
+
+
+def q_from(V, n, b):
+    Q = np.eye(n, dtype=complex)
+    for s in range(n - 1):
+        for j in range(tasks(n, b, s)):
+            v, tau = V[(s, j)]
+            r0 = s + 1 + j * b
+            L = min(b, n - r0)
+            vv = np.zeros(n, complex)
+            vv[r0:r0 + L] = v[:L]
+            Q = Q - tau * np.outer(Q @ vv, np.conj(vv))
+    return Q
+
+
+@pytest.mark.parametrize("n,b", [(12, 2), (20, 3), (33, 4), (40, 8), (29, 2), (70, 16), (9, 1), (5, 8), (17, 16)])
+def test_owner_schedule_matches_the_sequential_reduction(n, b):
+    A0 = band_matrix(n, min(b, n - 1), 3 * n + b)   # a band at least as wide as the matrix is full
+    T = simulate(A0, b)
+    o = run_owners(A0, b)
+    scale = np.abs(A0).sum(0).max()
+    assert np.abs(o["d"] - np.diag(T).real).max() < 1e-13 * scale
+    assert np.abs(o["e"] - np.diag(T, -1).real).max() < 1e-13 * scale
+    Tt = np.diag(o["d"]) + np.diag(o["e"], 1) + np.diag(o["e"], -1)
+    Q = q_from(o["V"], n, b)
+    assert np.abs(Q.conj().T @ A0 @ Q - Tt).max() < 1e-13 * scale
+    assert np.abs(Q.conj().T @ Q - np.eye(n)).max() < 1e-13 * n
+
+
+@pytest.mark.parametrize("n,b", [(20, 3), (40, 8), (29, 2), (70, 16)])
+def test_owner_schedule_random_orders_are_bitwise_equal(n, b):
+    A0 = band_matrix(n, b, 5 * n + b)
+    ref = run_owners(A0, b)
+    for seed in range(8):
+        got = run_owners(A0, b, np.random.default_rng(seed))
+        assert np.array_equal(got["d"], ref["d"]) and np.array_equal(got["e"], ref["e"]), seed
+        for key, (v, tau) in ref["V"].items():
+            assert np.array_equal(got["V"][key][0], v) and got["V"][key][1] == tau, (seed, key)
