@@ -144,17 +144,19 @@ __device__ void panel_chunk_compute(const PanelArgs<E> &a, PanelShared<E> &sh, i
         const int c = tid & 63, qq = tid >> 6;
         double2 acc = make_double2(0.0, 0.0);
         if (c < ncol) {
-            // partials q = qq, qq + 4, ... in ascending order, eight loads in flight
+            // partials q = qq, qq + 4, ... in ascending order, PQ loads in flight (the
+            // partials come from memory, so the number of dependent batches sets the time)
+            constexpr int PQ = 24;
             const double2 *src = part_in + j + c;
-            for (int q0 = qq; q0 < a.G; q0 += 32) {
-                double2 pq[8];
+            for (int q0 = qq; q0 < a.G; q0 += 4 * PQ) {
+                double2 pq[PQ];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < PQ; ++u) {
                     const int q = q0 + 4 * u;
                     pq[u] = zsel(q < a.G, src[(size_t)(q < a.G ? q : qq) * PNB], make_double2(0.0, 0.0));
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc = zadd(acc, pq[u]);
+                for (int u = 0; u < PQ; ++u) acc = zadd(acc, pq[u]);
             }
         }
         red[qq][c] = acc;
