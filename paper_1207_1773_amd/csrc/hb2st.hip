@@ -448,13 +448,6 @@ __device__ inline double2 msg_val(const MsgPoll &P, int k) {
 // partner's under a pairing (xor 1, xor 2, mirror within 8, mirror within 16),
 // so both partners form the same sum and every lane of the group ends with the
 // same bits.
-template <int CTRL>
-__device__ inline double dpp_f64(double x) {
-    const long long v = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 __device__ inline double lane_f64(double x, int l) {
     const long long v = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);

@@ -122,6 +122,16 @@ __host__ __device__ inline double2 zdiv(double2 a, double2 b) {
     return make_double2((a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s);
 }
 
+// A double moved between the lanes of a wave by a DPP control (as its two 32-bit
+// halves): the cross-lane step of the reductions that avoid LDS round trips.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 inline size_t cdivz(size_t a, size_t b) { return (a + b - 1) / b; }
 
