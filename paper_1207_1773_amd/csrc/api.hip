@@ -1103,6 +1103,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             } catch (...) {
                 ctx->stream = user;
                 ctx->concurrent = false;
+                ctx->panel_share = 0;
                 throw;
             }
             ctx->stream = user;
@@ -1117,6 +1118,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             const int its = opts->max_refine_iters < 0 ? 0 : iters;
             std::vector<HbBatchProblem> hbm(batch);
             // (A) FP64 factorisation and reduction to standard form, complex64 band reduction
+            ctx->panel_share = K;
             fan_out([&](int idx) {
                 int *inf = d_info ? d_info + idx : nullptr;
                 if (n[idx] == 0) {
@@ -1136,6 +1138,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
                                reinterpret_cast<double2 *>(X[idx]), ldx[idx], ar, nbi, its, tol, true, inf, nullptr,
                                &mr, 1, &hbm[idx]);
             });
+            ctx->panel_share = 0;
             // (B) one grouped complex64 bulge chasing
             std::vector<HbBatchProblem> hbs;
             for (int i = 0; i < batch; ++i)
@@ -1187,7 +1190,8 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             p.d_info = d_info ? d_info + i : nullptr;
             if (n[i] > 0) batch_take(p, arenas[i]);
         }
-        // (A) factorisations and band reductions
+        // (A) factorisations and band reductions (persistent panels side by side)
+        ctx->panel_share = K;
         fan_out([&](int idx) {
             if (n[idx] == 0) {
                 set_info(ctx, probs[idx].d_info, 0);
@@ -1195,6 +1199,7 @@ int hgv_zhegvx_batched(hgv_ctx_t ctx, int batch, const int *n, hgv_c128 *const *
             }
             batch_phase_a(ctx, probs[idx], arenas[idx]);
         });
+        ctx->panel_share = 0;
         // (B) one grouped bulge chasing over every problem
         std::vector<HbBatchProblem> hbs;
         for (int i = 0; i < batch; ++i)

@@ -390,7 +390,12 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
     PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
     a.part = part; a.rowb = rowb;
-    if (G <= capacity) {
+    if (G <= capacity && ctx->concurrent) {
+        // side by side with the panels of other problems: a plain launch (the
+        // share in `capacity` keeps every concurrent grid resident-able at once)
+        hipLaunchKernelGGL(panel_persist_kernel<E>, dim3(G), dim3(256), 0, ctx->stream, a, flags, gen, err);
+        HGV_LAUNCH_CHECK();
+    } else if (G <= capacity) {
         void *args[] = {&a, &flags, &gen, &err};
         HGV_HIP(hipLaunchCooperativeKernel(reinterpret_cast<void *>(panel_persist_kernel<E>), dim3(G), dim3(256),
                                            args, 0, ctx->stream));
@@ -439,7 +444,11 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     hipLaunchKernelGGL(fill_int_kernel, dim3(cdiv(Gmax + 1, 256)), dim3(256), 0, ctx->stream, flags, Gmax + 1, 0);
     HGV_LAUNCH_CHECK();
     if (ctx->test_hooks & HGV_TEST_WAIT_FAIL) set_info(ctx, flags + Gmax, 1);
-    const int capacity = ctx->concurrent ? 0 : panel_persist_capacity<E>(ctx);
+    // concurrent problems: the persistent panel only with a share of the device
+    // that every side-by-side panel fits in (see hgv_ctx_s::panel_share)
+    const int capacity = !ctx->concurrent         ? panel_persist_capacity<E>(ctx)
+                         : ctx->panel_share > 0 ? panel_persist_capacity<E>(ctx) / ctx->panel_share
+                                                : 0;
     // Look-ahead (the panel of step p + 1 factored while the update of step p
     // runs, as the paper overlaps its CPU panel with the GPU update): the
     // update first applies to the next panel's columns, then the next panel

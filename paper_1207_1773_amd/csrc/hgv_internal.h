@@ -33,6 +33,13 @@ struct hgv_ctx_s {
     // workgroups wait for each other (and so need to be resident together)
     // then use their launch-per-step forms where they have one.
     bool concurrent = false;
+    // While problems run concurrently: the number of band-reduction panels that
+    // may run side by side (one per side stream) when nothing else that waits
+    // on other workgroups runs beside them (the factorisation and band-reduction
+    // phase of a grouped batch); each panel's persistent grid then takes at most
+    // that share of the device, so all of them fit at once.  0: panels use their
+    // launch-per-step form while concurrent.
+    int panel_share = 0;
     // Side streams of one solve (created on first use, default priority) and
     // their events: [0] runs the next panel of the band reduction under the
     // current update (events 0, 1), [1] the left triangular solves of the
