@@ -40,11 +40,17 @@ __device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LE
         }
         double2 s = make_double2(0.0, 0.0);
         for (int k = c + q; k < i; k += QN) s = zadd(s, zmul(S[i][k], Inv[k][c]));
-#pragma unroll
-        for (int o = 1; o < QN; o <<= 1) {
-            s.x += __shfl_xor(s.x, o, 64);
-            s.y += __shfl_xor(s.y, o, 64);
-        }
+        // sum over the column's QN = 16 lanes (one DPP row) by lane moves: xor 1,
+        // xor 2, mirror within 8, mirror within 16
+        static_assert(QN == 16, "one DPP row of lanes per column");
+        s.x += dpp_f64<0xB1>(s.x);
+        s.y += dpp_f64<0xB1>(s.y);
+        s.x += dpp_f64<0x4E>(s.x);
+        s.y += dpp_f64<0x4E>(s.y);
+        s.x += dpp_f64<0x141>(s.x);
+        s.y += dpp_f64<0x141>(s.y);
+        s.x += dpp_f64<0x140>(s.x);
+        s.y += dpp_f64<0x140>(s.y);
         const double2 rhs = (i == c) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
         // the butterfly leaves the same sum in the QN lanes, so each lane
         // stores the (identical) value and later reads only what it stored
@@ -53,57 +59,62 @@ __device__ inline void tri_inverse_lds(double2 (*S)[LEAF + 1], double2 (*Inv)[LE
 }
 
 // ---- leaf Cholesky (n <= 64), one workgroup -----------------------------------
-// Right-looking unblocked Cholesky of the lower triangle held in LDS.  A
-// non-positive (or NaN) pivot at local column j records info = base + j + 1
-// (first failure wins) and stops the factorisation of this block.  The
-// inverse of the factor is written to Linv (64 x 64, column-major).  The work
-// is a chain of 64 dependent column steps of short arithmetic, so the kernel
-// runs NT = 1024 threads (four waves per SIMD keep the dependent instructions
-// of one another overlapped).
+// Right-looking unblocked Cholesky of the lower triangle held in LDS, with the
+// scaling of each column deferred to the end: step j subtracts
+// S[i][j] conj(S[k][j]) / S[j][j] from the trailing elements (k > j, i >= k),
+// which reads column j and writes only later columns, so a step needs one
+// barrier; afterwards L[k][k] = sqrt(S[k][k]) and L[i][k] = S[i][k] / L[k][k].
+// A non-positive (or NaN) pivot at local column j records info = base + j + 1
+// (first failure wins) and stops the factorisation of this block (the columns
+// before it are returned factored).  The inverse of the factor is written to
+// Linv (64 x 64, column-major).  Each of the NT = 1024 threads owns four fixed
+// elements.
 template <int NT, class E>
 __global__ __launch_bounds__(NT) void potf2_kernel(int n, E *A, int lda, int *info, int base, E *Linv) {
+    constexpr int NE = LEAF * LEAF / NT;
     __shared__ double2 S[LEAF][LEAF + 1];
     __shared__ double2 Iv[LEAF][LEAF + 1];
-    __shared__ int fail;
+    __shared__ double dk[LEAF];
     const int tid = threadIdx.x;
     for (int t = tid; t < LEAF * LEAF; t += NT) {
         int i = t % LEAF, j = t / LEAF;
         S[i][j] = (i < n && j < n && i >= j) ? El<E>::to(A[i + (size_t)j * lda]) : make_double2(0.0, 0.0);
     }
-    if (tid == 0) fail = 0;
     __syncthreads();
+    int jfail = n;
     for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            double piv = S[j][j].x;
-            if (!(piv > 0.0)) {
-                fail = 1;
-                if (info && *info == 0) *info = base + j + 1;
-            } else {
-                S[j][j] = make_double2(sqrt(piv), 0.0);
-            }
+        const double piv = S[j][j].x;   // the same value in every thread
+        if (!(piv > 0.0)) {
+            jfail = j;
+            break;
         }
-        __syncthreads();
-        if (fail) break;
-        double inv = 1.0 / S[j][j].x;
-        for (int i = j + 1 + tid; i < n; i += NT) S[i][j] = zscale(inv, S[i][j]);
-        __syncthreads();
-        int m = n - j - 1;
-        for (int t = tid; t < m * m; t += NT) {
-            int i = j + 1 + t % m, k = j + 1 + t / m;
-            if (i >= k) {
-                double2 a = S[i][j], b = S[k][j];
-                double2 p = make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);  // a * conj(b)
-                S[i][k] = zsub(S[i][k], p);
+        const double ip = 1.0 / piv;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int e = tid + NT * q, i = e % LEAF, k = e / LEAF;
+            if (k > j && i >= k && i < n) {
+                const double2 a = S[i][j], b = S[k][j];
+                S[i][k] = zsub(S[i][k], zscale(ip, make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y)));
             }
         }
         __syncthreads();
     }
+    if (jfail < n && tid == 0 && info) atomicCAS(info, 0, base + jfail + 1);
+    if (tid < jfail) dk[tid] = sqrt(S[tid][tid].x);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + NT * q, i = e % LEAF, k = e / LEAF;
+        if (k < jfail && i >= k && i < n) S[i][k] = i == k ? make_double2(dk[k], 0.0) : zscale(1.0 / dk[k], S[i][k]);
+    }
+    __syncthreads();
     for (int t = tid; t < n * n; t += NT) {
         int i = t % n, j = t / n;
         if (i >= j) A[i + (size_t)j * lda] = El<E>::from(S[i][j]);
     }
     if (Linv) {
-        if (fail) {   // keep the solves finite; the result is flagged through info
+        if (jfail < n) {   // keep the solves finite; the result is flagged through info
+            __syncthreads();
             for (int t = tid; t < LEAF * LEAF; t += NT) {
                 int i = t % LEAF, j = t / LEAF;
                 S[i][j] = (i == j) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
