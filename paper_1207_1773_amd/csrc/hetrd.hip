@@ -63,10 +63,16 @@ __global__ __launch_bounds__(256) void trd_colupd_kernel(int n, int c, int j, do
     if (r < n) {
         x = A[r + (size_t)c * lda];
         const double2 *vrow = Vp + (size_t)r * nbw, *wrow = Wp + (size_t)r * nbw;
-        for (int l = 0; l < j; ++l) {
-            x = zsub(x, zmul(vrow[l], wr[l]));
-            x = zsub(x, zmul(wrow[l], vr[l]));
+        // four independent partial sums (fixed order), so the loads and the
+        // multiply-adds of consecutive l overlap instead of forming one chain
+        double2 q[4] = {zero2d(), zero2d(), zero2d(), zero2d()};
+        int l = 0;
+        for (; l + 4 <= j; l += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q[u] = zadd(q[u], zadd(zmul(vrow[l + u], wr[l + u]), zmul(wrow[l + u], vr[l + u])));
         }
+        for (; l < j; ++l) q[0] = zadd(q[0], zadd(zmul(vrow[l], wr[l]), zmul(wrow[l], vr[l])));
+        x = zsub(x, zadd(zadd(q[0], q[1]), zadd(q[2], q[3])));
         if (r == c) x.y = 0.0;
         A[r + (size_t)c * lda] = x;
     }
@@ -314,17 +320,33 @@ __global__ __launch_bounds__(256) void trd_wfin_kernel(int N, int c, int j, doub
     const int i = blockIdx.x * 256 + tid;
     if (i >= N) return;
     const int I = i / 64, g = c + 1 + i;
-    double2 y = zero2d();
-    for (int J = 0; J < I; ++J) y = zadd(y, P[(size_t)J * ldp + i]);
+    // y_i: the block-column partials of the product, then the panel's earlier
+    // transformations; four independent partial sums each (fixed order)
+    double2 yq[4] = {zero2d(), zero2d(), zero2d(), zero2d()};
+    {
+        int J = 0;
+        for (; J + 4 <= I; J += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yq[u] = zadd(yq[u], P[(size_t)(J + u) * ldp + i]);
+        }
+        for (; J < I; ++J) yq[0] = zadd(yq[0], P[(size_t)J * ldp + i]);
+    }
     const int lb = I - blockIdx.x * 4;
-    for (int q = 0; q < qcnt[lb]; ++q) y = zadd(y, Qv[(size_t)(qoff[lb] + q) * 64 + (i & 63)]);
+    for (int q = 0; q < qcnt[lb]; ++q) yq[1] = zadd(yq[1], Qv[(size_t)(qoff[lb] + q) * 64 + (i & 63)]);
     const double2 scale = st->scale, tau = st->tau;
     const double2 v = i == 0 ? make_double2(1.0, 0.0) : zmul(scale, A[g + (size_t)c * lda]);
     double2 *vrow = Vp + (size_t)g * nbw, *wrow = Wp + (size_t)g * nbw;
-    for (int l = 0; l < j; ++l) {
-        y = zsub(y, zmul(vrow[l], st->t1[l]));
-        y = zsub(y, zmul(wrow[l], st->t2[l]));
+    double2 zq[4] = {zero2d(), zero2d(), zero2d(), zero2d()};
+    {
+        int l = 0;
+        for (; l + 4 <= j; l += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                zq[u] = zadd(zq[u], zadd(zmul(vrow[l + u], st->t1[l + u]), zmul(wrow[l + u], st->t2[l + u])));
+        }
+        for (; l < j; ++l) zq[0] = zadd(zq[0], zadd(zmul(vrow[l], st->t1[l]), zmul(wrow[l], st->t2[l])));
     }
+    const double2 y = zsub(zadd(zadd(yq[0], yq[1]), zadd(yq[2], yq[3])), zadd(zadd(zq[0], zq[1]), zadd(zq[2], zq[3])));
     const double2 w = zadd(zmul(tau, y), zscale(alpha_s, v));
     wrow[j] = w;
     vrow[j] = v;
