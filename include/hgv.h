@@ -130,8 +130,12 @@ int hgv_default_nb(int n, int precision);
  *   sweep-per-workgroup schedule (otherwise used only when the windows of the
  *   window-owner pipeline do not all fit on the device at once), so that both
  *   schedules can be tested.
+ * HGV_TEST_HOUSEHOLDER_PANELS: every band-reduction panel is factored by the
+ *   Householder column steps (otherwise a complex double panel of full column
+ *   rank and condition number at most 1e5 is factored by Cholesky QR twice
+ *   with Householder reconstruction), so that both forms can be tested.
  * Returns -2 for unknown bits. */
-enum { HGV_TEST_WAIT_FAIL = 1, HGV_TEST_NAN_RESIDUAL = 2, HGV_TEST_HB2ST_SWEEPS = 4 };
+enum { HGV_TEST_WAIT_FAIL = 1, HGV_TEST_NAN_RESIDUAL = 2, HGV_TEST_HB2ST_SWEEPS = 4, HGV_TEST_HOUSEHOLDER_PANELS = 8 };
 int hgv_test_hooks(hgv_ctx_t ctx, int mask);
 
 /* ---- full generalized solve (Algorithm 1) -------------------------------- */

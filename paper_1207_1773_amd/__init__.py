@@ -38,6 +38,7 @@ HGV_DSTEBZ_NOALLOC_MAX = 262144
 HGV_TEST_WAIT_FAIL = 1
 HGV_TEST_NAN_RESIDUAL = 2
 HGV_TEST_HB2ST_SWEEPS = 4
+HGV_TEST_HOUSEHOLDER_PANELS = 8
 
 
 class c128(ctypes.Structure):

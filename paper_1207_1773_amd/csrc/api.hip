@@ -334,7 +334,8 @@ int hgv_last_hip_error(hgv_ctx_t ctx) { return ctx_ok(ctx) ? ctx->last_hip_error
 
 int hgv_test_hooks(hgv_ctx_t ctx, int mask) {
     if (!ctx_ok(ctx)) return HGV_E_CTX;
-    if (mask & ~(HGV_TEST_WAIT_FAIL | HGV_TEST_NAN_RESIDUAL | HGV_TEST_HB2ST_SWEEPS)) return -2;
+    if (mask & ~(HGV_TEST_WAIT_FAIL | HGV_TEST_NAN_RESIDUAL | HGV_TEST_HB2ST_SWEEPS | HGV_TEST_HOUSEHOLDER_PANELS))
+        return -2;
     ctx->test_hooks = mask;
     return HGV_OK;
 }

@@ -89,6 +89,8 @@ struct GemmDev {
     int lower_tiles;   // grid enumerates only the tiles on or below the diagonal
     E *P;              // partial tiles when splits > 1: splits x (m x n), ld m
     int tiles_m, tiles_n;
+    const int *gate;   // non-null: run only if *gate == gate_val
+    int gate_val;
 };
 
 // Tile shape per element type: output BM x BN per workgroup, k depth of a
@@ -277,6 +279,7 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
     __shared__ E As[2][BK * (BM + PAD)];
     __shared__ E Bs[2][BK * (BN + PAD)];
 
+    if (g.gate && *g.gate != g.gate_val) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -443,6 +446,7 @@ __global__ __launch_bounds__(NW * 64, 2) void gemm_kernel(GemmDev<T> g) {
 template <class T>
 __global__ __launch_bounds__(256) void splitk_reduce(GemmDev<T> g) {
     typedef typename T::E E;
+    if (g.gate && *g.gate != g.gate_val) return;
     size_t total = (size_t)g.m * g.n;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
         int row = (int)(t % g.m), col = (int)(t / g.m);
@@ -482,6 +486,8 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     g.alpha = a.alpha; g.beta = a.beta;
     g.C = a.C; g.ldc = a.ldc;
     g.lower = a.lower;
+    g.gate = a.gate;
+    g.gate_val = a.gate_val;
     g.P = nullptr;
     {
         const char *pb = reinterpret_cast<const char *>(&a.beta);
@@ -589,6 +595,8 @@ struct DGemmArgs {
     double *C; int ldc;
     int lower;
     int allow_split;
+    const int *gate = nullptr;
+    int gate_val = 0;
 };
 
 void dgemm_nn(hgv_ctx_s *ctx, int m, int n, int k, double alpha, const double *A, int lda,

@@ -448,12 +448,6 @@ __device__ inline double2 msg_val(const MsgPoll &P, int k) {
 // partner's under a pairing (xor 1, xor 2, mirror within 8, mirror within 16),
 // so both partners form the same sum and every lane of the group ends with the
 // same bits.
-__device__ inline double lane_f64(double x, int l) {
-    const long long v = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
-    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 // sum over aligned groups of 8 lanes
 __device__ inline double sum8_dpp(double x) {
     x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]: xor 1

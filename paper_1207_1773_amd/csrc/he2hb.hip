@@ -21,6 +21,7 @@
 // the mixed-precision solve); the panel's inner products, norms, reflector
 // scalars and the T factors are always computed in FP64.
 #include <algorithm>
+#include <type_traits>
 
 #include "hgv_internal.h"
 
@@ -43,6 +44,7 @@ struct PanelArgs {
     double2 *rowb;         // [2][PNB] pivot row of the next column (double-buffered)
     double2 *tau;          // [jb]
     int G;
+    const int *skip;       // non-null and set: the panel was factored another way
 };
 
 // Reflector of x = (alpha, x_1..) with tail = ||x_1..||^2:  H^H x = beta e_1,
@@ -241,6 +243,7 @@ __device__ void panel_chunk_compute(const PanelArgs<E> &a, PanelShared<E> &sh, i
 template <class E>
 __global__ __launch_bounds__(256) void panel_step_kernel(PanelArgs<E> a, int j) {
     __shared__ PanelShared<E> sh;
+    if (a.skip && *a.skip) return;
     const int c0 = max(j, 0);
     panel_chunk_load<E>(a, sh, blockIdx.x, c0);
     panel_chunk_compute<E>(a, sh, j, blockIdx.x);
@@ -282,6 +285,7 @@ __device__ inline void panel_wait(const int *flags, int G, int target, int *err)
 template <class E>
 __global__ __launch_bounds__(256) void panel_persist_kernel(PanelArgs<E> a, int *flags, int gen, int *err) {
     __shared__ PanelShared<E> sh;
+    if (a.skip && *a.skip) return;   // the same value in every workgroup: none waits
     const int g = blockIdx.x;
     const int r = min(a.N, a.jb);
     panel_chunk_load<E>(a, sh, g, 0);
@@ -312,7 +316,9 @@ __global__ void extract_v_kernel(int N, int r, const E *P, int ldp, E *V, int ld
 // combined).  The columns form a chain of short dependent steps, so NT = 1024
 // (four waves per SIMD, a quarter of the chain per lane).
 template <class E, int NT>
-__global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, const E *G, int ldg, E *T, int ldt) {
+__global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, const E *G, int ldg, E *T, int ldt,
+                                                    const int *skip) {
+    if (skip && *skip) return;
     constexpr int QN = NT / 64;
     __shared__ double2 Ts[PNB][PNB + 1];
     __shared__ double2 Gs[PNB][PNB + 1];
@@ -342,6 +348,396 @@ __global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, 
         __syncthreads();
     }
     for (int t = tid; t < r * r; t += NT) T[t % r + (size_t)(t / r) * ldt] = El<E>::from(Ts[t % r][t / r]);
+}
+
+// ---- panel QR in a fixed number of launches -------------------------------------
+// A panel of full column rank that is not too ill-conditioned is factored
+// without the column steps:
+//   Cholesky QR twice: G1 = P^H P = L1 L1^H, Q1 = P L1^-H; G2 = Q1^H Q1 = L2 L2^H,
+//   Q = Q1 L2^-H, so P = Q R with R = (L1 L2)^H (the second pass restores the
+//   orthogonality the first loses to the rounding of G1);
+//   Householder reconstruction: the LU factorisation without pivoting
+//   Q - [S; 0] = V U, with the unitary diagonal S chosen column by column as
+//   S_jj = -u/|u| (u the current diagonal entry, -1 if zero) so that every pivot
+//   has modulus at least 1, gives the unit lower-trapezoidal V of the block
+//   reflector Q_h = I - V T V^H whose first r columns are Q S^H; hence
+//   P = Q_h [S R; 0] and the reflectors' scalars are tau_j = -U_jj conj(S_jj)
+//   (T is then formed from tau and V^H V as for the column steps).
+// (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya, ETNA 44, 2015, for the two
+// passes; Ballard, Demmel, Grigori, Jacquelin, Knight and Nguyen, IPDPS 2014,
+// for the reconstruction, here in complex arithmetic.)  The results satisfy
+// the same contract as the column steps: V below the diagonal of P, the band
+// block S R on and above it (its diagonal complex), tau.
+// A device flag decides between the two methods without a host round trip: the
+// first factorisation sets it when G1 is numerically positive definite with
+// ||L1||_F ||L1^-1||_F <= 1e5 (condition number at most 1e5), the second clears
+// it unless G2 is within 1e-2 of the identity and positive definite.  It gates
+// the reconstruction and the product that finishes V on, the column-step
+// kernels off.
+
+constexpr int CQ_NW = 8;             // waves per workgroup
+constexpr int CQ_T = 64 / CQ_NW;      // consecutive columns per wave
+constexpr int CQ_MC = 8;              // rows of a product's operands staged in LDS at a time
+
+__device__ inline double2 lane_z(double2 v, int l) { return make_double2(lane_f64(v.x, l), lane_f64(v.y, l)); }
+
+// a[t] for a wave-uniform t, without indexing the register array
+template <int NN>
+__device__ inline double2 pick_reg(const double2 (&a)[NN], int t) {
+    double2 r = a[0];
+#pragma unroll
+    for (int u = 1; u < NN; ++u) r = zsel(u == t, a[u], r);
+    return r;
+}
+template <int NN>
+__device__ inline void put_reg(double2 (&a)[NN], int t, double2 v) {
+#pragma unroll
+    for (int u = 0; u < NN; ++u) a[u] = zsel(u == t, v, a[u]);
+}
+
+// Sum (max when MAX, NaN winning) over the workgroup; the result in every thread.
+template <bool MAX>
+__device__ inline double cq_reduce(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o);
+        v = MAX ? ((u > v || u != u) ? u : v) : v + u;
+    }
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) sh[tid >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int q = 1; q < CQ_NW; ++q) r = MAX ? ((sh[q] > r || sh[q] != sh[q]) ? sh[q] : r) : r + sh[q];
+    return r;
+}
+
+// Layout of the 64 x 64 matrices of the two kernels below: lane i holds row i,
+// wave w the columns CQ_T w .. CQ_T w + CQ_T - 1 (r x r padded with the identity).
+// C += A B for such a C, the operands staged in LDS CQ_MC rows of B (columns of A)
+// at a time by sa(m0) (As[mm][i] = A[i][m0 + mm]) and sb(m0) (Bs[mm][k] =
+// B[m0 + mm][k]); a wave reads B's entries of its columns as broadcasts.
+template <class SA, class SB>
+__device__ inline void cq_product(double2 (&c)[CQ_T], SA sa, SB sb, double2 (*As)[65], double2 (*Bs)[65], int w,
+                                  int i) {
+    for (int m0 = 0; m0 < 64; m0 += CQ_MC) {
+        __syncthreads();
+        sa(m0);
+        sb(m0);
+        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < CQ_MC; ++mm) {
+            const double2 av = As[mm][i];
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) c[t] = zadd(c[t], zmul(av, Bs[mm][CQ_T * w + t]));
+        }
+    }
+}
+
+// G = L L^H (r x r Hermitian, r <= 64, lower triangle read) and X = L^-1, one
+// workgroup.  Step j eliminates column j below the diagonal (the wave holding
+// it publishes it in LDS; one barrier per step) and applies the same row
+// operations to an identity held beside it, which ends as the inverse of the
+// unit lower factor; the pivots' square roots scale both at the end.  The
+// updates are branch-free within a wave (a zero multiplier, or a zero entry of
+// the triangular inverse, leaves an element unchanged), so that the chains of
+// a wave's columns overlap.  stage 1 sets *ok; stage 2 keeps it only if it holds.
+__global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const double2 *__restrict__ G, int ldg,
+                                                              double2 *__restrict__ L, double2 *__restrict__ X,
+                                                              int ldo, int *ok, int stage) {
+    __shared__ double2 col[2][64];
+    __shared__ double red[CQ_NW];
+    const int tid = threadIdx.x, i = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double2 a[CQ_T], x[CQ_T];
+    double tr = 0.0, dev = 0.0;
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        const bool in = i < r && k < r;
+        const double id = i == k ? 1.0 : 0.0;
+        const double2 v = zsel(in, G[in ? i + (size_t)k * ldg : 0], make_double2(id, 0.0));
+        a[t] = v;
+        x[t] = make_double2(id, 0.0);
+        if (in && i == k) tr += v.x;
+        const double e = (in && i >= k) ? sqrt(zabs2(zsub(v, make_double2(id, 0.0)))) : 0.0;
+        dev = (e > dev || e != e) ? e : dev;
+    }
+    double myd = 1.0;
+    bool bad = false;
+    for (int j = 0; j < 64; ++j) {
+        const int buf = j & 1, wj = j / CQ_T;
+        if (w == wj) col[buf][i] = pick_reg(a, j - CQ_T * w);
+        __syncthreads();
+        const double2 c = col[buf][i];
+        const double d = lane_f64(c.x, j);   // the same pivot in every wave
+        bad = bad || !(d > 0.0);
+        if (i == j) myd = d;
+        const double2 m = zsel(i > j && !bad, zscale(1.0 / d, c), make_double2(0.0, 0.0));
+        if (w >= wj) {   // columns k > j: G[i][k] -= m_i conj(G[k][j])
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) {
+                const int k = CQ_T * w + t;
+                const double2 mk = zsel(k > j, m, make_double2(0.0, 0.0));
+                a[t] = zsub(a[t], zmul(mk, zconj(lane_z(c, k))));
+            }
+        }
+        if (w <= wj) {   // columns k <= j of the inverse (X[j][k] = 0 for k > j)
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) x[t] = zsub(x[t], zmul(m, lane_z(x[t], j)));
+        }
+    }
+    const double si = bad ? 1.0 : 1.0 / sqrt(myd);
+    double xs = 0.0;
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        const double dk = bad ? 1.0 : lane_f64(myd, k);
+        const double sk = sqrt(dk);
+        const double2 l = zsel(i == k, make_double2(sk, 0.0), zsel(i > k, zscale(1.0 / sk, a[t]), make_double2(0.0, 0.0)));
+        const double2 xv = zscale(si, x[t]);
+        if (i < r && k < r) {
+            L[i + (size_t)k * ldo] = l;
+            X[i + (size_t)k * ldo] = xv;
+            xs += zabs2(xv);
+        }
+    }
+    const double trs = cq_reduce<false>(tr, red);
+    const double xss = cq_reduce<false>(xs, red);
+    const double devm = cq_reduce<true>(dev, red);
+    if (tid == 0) {
+        bool good = !bad;
+        if (stage == 1) good = good && trs * xss <= 1e10;
+        else good = good && devm <= 1e-2 && *ok != 0;
+        *ok = good ? 1 : 0;
+    }
+}
+
+// The reconstruction, one workgroup in the layout above, when *ok:
+//   Q_top = Q1[0:r, :] L2^-H;
+//   its modified LU Q_top - S = V1 U, with V1^-1 formed beside it (V1 goes below
+//   the diagonal of P's top block, tau_j = -U_jj conj(S_jj));
+//   Y = U^-1;  M = L2^-H Y (so that V2 = Q1[r:, :] M, a GEMM);
+//   T = -(U S^H) V1^-H, the block reflector's triangular factor
+//   (the first r columns of I - V T V^H are Q S^H: V T V1^H = E - Q S^H);
+//   the band block S (L1 L2)^H on and above the diagonal of P's top block.
+__global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const double2 *__restrict__ Q1, int ldq,
+                                                               const double2 *__restrict__ L1,
+                                                               const double2 *__restrict__ L2,
+                                                               const double2 *__restrict__ X2, int ldo, double2 *P,
+                                                               int ldp, double2 *tau, double2 *__restrict__ T,
+                                                               int ldt, double2 *__restrict__ M, const int *ok) {
+    if (*ok == 0) return;
+    __shared__ double2 col[2][64];
+    __shared__ double2 sv[64];
+    __shared__ double2 As[CQ_MC][65], Bs[CQ_MC][65];
+    const int tid = threadIdx.x, i = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
+    constexpr int NT = CQ_NW * 64;
+    double2 a[CQ_T], vx[CQ_T];
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) a[t] = zero;
+    // Q_top = Q1[0:r, 0:r] X2^H
+    cq_product(
+        a,
+        [&](int m0) {
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int ii = e & 63, m = m0 + (e >> 6);
+                const bool in = ii < r && m < r;
+                As[e >> 6][ii] = zsel(in, Q1[in ? ii + (size_t)m * ldq : 0], zero);
+            }
+        },
+        [&](int m0) {
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int k = e & 63, m = m0 + (e >> 6);
+                const bool in = k < r && m <= k;
+                Bs[e >> 6][k] = zsel(in, zconj(X2[in ? k + (size_t)m * ldo : 0]), zero);
+            }
+        },
+        As, Bs, w, i);
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        if (i >= r || k >= r) a[t] = zsel(i == k, one, zero);
+        vx[t] = zsel(i == k, one, zero);
+    }
+    // modified LU: at step j the pivot is a_jj - S_jj with S_jj = -a_jj / |a_jj|
+    for (int j = 0; j < 64; ++j) {
+        const int buf = j & 1, wj = j / CQ_T;
+        if (w == wj) {
+            const int tj = j - CQ_T * w;
+            const double2 cur = pick_reg(a, tj);
+            const double2 ajj = lane_z(cur, j);
+            const double nrm = sqrt(zabs2(ajj));
+            const double2 sj = zsel(nrm > 0.0, make_double2(-ajj.x / nrm, -ajj.y / nrm), make_double2(-1.0, 0.0));
+            const double2 u = zsub(ajj, sj);
+            const double2 l = zdiv(cur, u);
+            put_reg(a, tj, zsel(i > j, l, zsel(i == j, u, cur)));
+            col[buf][i] = zsel(i > j, l, zero);
+            if (i == j) {
+                sv[j] = sj;
+                if (j < r) tau[j] = zsub(zero, zmul(u, zconj(sj)));
+            }
+        }
+        __syncthreads();
+        const double2 l = col[buf][i];
+        if (w >= wj) {
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) {
+                const int k = CQ_T * w + t;
+                a[t] = zsub(a[t], zmul(zsel(k > j, l, zero), lane_z(a[t], j)));
+            }
+        }
+        if (w <= wj) {   // V1^-1: the same row operations on the identity
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) vx[t] = zsub(vx[t], zmul(l, lane_z(vx[t], j)));
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        if (i > k && i < r && k < r) P[i + (size_t)k * ldp] = a[t];
+    }
+    // T = -(U S^H) V1^-H: A[i][m] = U[i][m] conj(S_m) (upper), B[m][k] = conj(V1^-1[k][m])
+    double2 c[CQ_T];
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) c[t] = zero;
+    cq_product(
+        c,
+        [&](int m0) {
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) {
+                const int m = CQ_T * w + t;
+                if (m >= m0 && m < m0 + CQ_MC) As[m - m0][i] = zsel(i <= m, zmul(a[t], zconj(sv[m])), zero);
+            }
+        },
+        [&](int m0) {
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) {
+                const int m = CQ_T * w + t;
+                if (m >= m0 && m < m0 + CQ_MC) Bs[m - m0][i] = zconj(vx[t]);
+            }
+        },
+        As, Bs, w, i);
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        if (i < r && k < r) T[i + (size_t)k * ldt] = zsub(zero, c[t]);
+    }
+    // Y = U^-1 (upper), right-looking backward substitution from Y = I
+    __syncthreads();
+    double2 y[CQ_T];
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) y[t] = zsel(CQ_T * w + t == i, one, zero);
+    for (int j = 63; j >= 0; --j) {
+        const int buf = j & 1, wj = j / CQ_T;
+        if (w == wj) col[buf][i] = zsel(i <= j, pick_reg(a, j - CQ_T * w), zero);
+        __syncthreads();
+        const double2 cj = col[buf][i];
+        const double2 iu = zdiv(one, lane_z(cj, j));
+        const double2 cu = zsel(i < j, cj, zero);
+        if (w >= wj) {   // Y[j][k] = 0 for k < j
+#pragma unroll
+            for (int t = 0; t < CQ_T; ++t) {
+                y[t] = zsel(i == j, zmul(y[t], iu), y[t]);
+                y[t] = zsub(y[t], zmul(cu, lane_z(y[t], j)));
+            }
+        }
+    }
+    // M = X2^H Y: A[i][m] = conj(X2[m][i]), B = Y
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) c[t] = zero;
+    cq_product(
+        c,
+        [&](int m0) {
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int ii = e & 63, m = m0 + (e >> 6);
+                const bool in = m < r && ii <= m;
+                As[e >> 6][ii] = zsel(in, zconj(X2[in ? m + (size_t)ii * ldo : 0]), zero);
+            }
+        },
+        [&](int m0) {
+            if (i >= m0 && i < m0 + CQ_MC) {
+#pragma unroll
+                for (int t = 0; t < CQ_T; ++t) Bs[i - m0][CQ_T * w + t] = y[t];
+            }
+        },
+        As, Bs, w, i);
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        if (i < r && k < r) M[i + (size_t)k * r] = c[t];
+    }
+    // Z = L1 L2 (lower); band block (S R)[k][i] = S_kk conj(Z[i][k]) for k <= i
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) c[t] = zero;
+    cq_product(
+        c,
+        [&](int m0) {
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int ii = e & 63, m = m0 + (e >> 6);
+                const bool in = ii < r && m <= ii;
+                As[e >> 6][ii] = zsel(in, L1[in ? ii + (size_t)m * ldo : 0], zero);
+            }
+        },
+        [&](int m0) {
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int k = e & 63, m = m0 + (e >> 6);
+                const bool in = m < r && k <= m;
+                Bs[e >> 6][k] = zsel(in, L2[in ? m + (size_t)k * ldo : 0], zero);
+            }
+        },
+        As, Bs, w, i);
+#pragma unroll
+    for (int t = 0; t < CQ_T; ++t) {
+        const int k = CQ_T * w + t;
+        if (k < r && i >= k && i < r) P[k + (size_t)i * ldp] = zmul(sv[k], zconj(c[t]));
+    }
+}
+
+struct CqrScratch {
+    double2 *G, *L1, *X1, *L2, *X2, *M, *Q;   // r x r (ld r) each; Q: N x r (ld N)
+    int *ok;
+};
+
+// Launches the fixed sequence for panel P (N x r, N >= r); sets up the flag
+// that gates the column-step kernels launched after it.
+static void cholqr_panel(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int r, double2 *tau, double2 *T, int ldt,
+                         const CqrScratch &c, void *ws, size_t wsb) {
+    ZGemm g;   // G1 = P^H P
+    g.m = r; g.n = r; g.k = N;
+    g.opa = 'C'; g.A = P; g.lda = ldp;
+    g.opb = 'N'; g.B = P; g.ldb = ldp;
+    g.C = c.G; g.ldc = r;
+    zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.G, r, c.L1, c.X1, r, c.ok, 1);
+    HGV_LAUNCH_CHECK();
+    g = ZGemm();   // Q1 = P L1^-H
+    g.m = N; g.n = r; g.k = r;
+    g.opa = 'N'; g.A = P; g.lda = ldp;
+    g.opb = 'C'; g.B = c.X1; g.ldb = r;
+    g.C = c.Q; g.ldc = N;
+    zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
+    g = ZGemm();   // G2 = Q1^H Q1
+    g.m = r; g.n = r; g.k = N;
+    g.opa = 'C'; g.A = c.Q; g.lda = N;
+    g.opb = 'N'; g.B = c.Q; g.ldb = N;
+    g.C = c.G; g.ldc = r;
+    zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.G, r, c.L2, c.X2, r, c.ok, 2);
+    HGV_LAUNCH_CHECK();
+    hipLaunchKernelGGL(cqr_recon_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.Q, N, c.L1, c.L2, c.X2, r,
+                       P, ldp, tau, T, ldt, c.M, c.ok);
+    HGV_LAUNCH_CHECK();
+    if (N > r) {
+        g = ZGemm();   // V2 = Q1[r:, :] M, into P below the top block
+        g.m = N - r; g.n = r; g.k = r;
+        g.A = c.Q + r; g.lda = N;
+        g.B = c.M; g.ldb = r;
+        g.C = P + r; g.ldc = ldp;
+        g.gate = c.ok; g.gate_val = 1;
+        zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
+    }
 }
 
 template <class E>
@@ -383,13 +779,22 @@ __global__ void fill_int_kernel(int *p, int n, int v) {
 template <class E>
 static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau, double2 *part, double2 *rowb,
                      E *Vw, E *Gm, E *T, int ldt, void *ws, size_t wsb, int *flags, int *err, int gen,
-                     int capacity) {
+                     int capacity, const CqrScratch *cq) {
     typedef typename El<E>::Gemm Gm_t;
     const int r = std::min(N, jb);
     const int G = cdiv(N, pch<E>());
     PanelArgs<E> a;
     a.P = P; a.ldp = ldp; a.N = N; a.jb = jb; a.tau = tau; a.G = G;
     a.part = part; a.rowb = rowb;
+    a.skip = nullptr;
+    if constexpr (std::is_same<E, double2>::value) {
+        // complex double panels at least as tall as wide: the fixed-launch form
+        // first, the column steps only where its flag says it did not apply
+        if (cq && N >= jb && !(ctx->test_hooks & HGV_TEST_HOUSEHOLDER_PANELS)) {
+            cholqr_panel(ctx, P, ldp, N, jb, tau, reinterpret_cast<double2 *>(T), ldt, *cq, ws, wsb);
+            a.skip = cq->ok;
+        }
+    }
     if (G <= capacity && ctx->concurrent) {
         // side by side with the panels of other problems: a plain launch (the
         // share in `capacity` keeps every concurrent grid resident-able at once)
@@ -408,13 +813,15 @@ static void panel_qr(hgv_ctx_s *ctx, E *P, int ldp, int N, int jb, double2 *tau,
     hipLaunchKernelGGL(extract_v_kernel<E>, dim3(cdiv(N, 64), cdiv(r, 4)), dim3(256), 0, ctx->stream, N, r, P, ldp,
                        Vw, N);
     HGV_LAUNCH_CHECK();
+    // T from tau and G = V^H V, unless the fixed-launch form has written it
     Gm_t gg;  // G = V^H V
     gg.m = r; gg.n = r; gg.k = N;
     gg.opa = 'C'; gg.A = Vw; gg.lda = N;
     gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
     gg.C = Gm; gg.ldc = r;
+    gg.gate = a.skip; gg.gate_val = 0;
     gemm_any(ctx, gg, ws, wsb);
-    hipLaunchKernelGGL((build_t_kernel<E, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    hipLaunchKernelGGL((build_t_kernel<E, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt, a.skip);
     HGV_LAUNCH_CHECK();
 }
 
@@ -438,6 +845,14 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     E *M = ar.take<E>((size_t)nb * nb);
     E *M2 = ar.take<E>((size_t)nb * nb);
     int *flags = ar.take<int>(Gmax + 1);   // Gmax progress flags, then the give-up flag
+    CqrScratch cq{};
+    const bool use_cq = std::is_same<E, double2>::value;
+    if (use_cq) {
+        double2 *b = ar.take<double2>((size_t)6 * PNB * PNB + (size_t)std::max(n, 1) * nb);
+        cq.G = b; cq.L1 = b + PNB * PNB; cq.X1 = b + 2 * PNB * PNB; cq.L2 = b + 3 * PNB * PNB;
+        cq.X2 = b + 4 * PNB * PNB; cq.M = b + 5 * PNB * PNB; cq.Q = b + 6 * PNB * PNB;
+        cq.ok = ar.take<int>(1);
+    }
     if (ar.measuring() || n == 0) return;
     const E one = El<E>::mk(1.0, 0.0), mone = El<E>::mk(-1.0, 0.0), mhalf = El<E>::mk(-0.5, 0.0);
     zero_async(ctx, T1, (size_t)std::max(np, 1) * nb * nb);
@@ -465,7 +880,8 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
         ctx->stream = st;
         try {
             panel_qr<E>(ctx, A + (k + nb) + (size_t)k * lda, lda, N, jb, tau, part, rowb, Vp, Gm,
-                        T1 + (size_t)p * nb * nb, nb, wsp, wsb, flags, flags + Gmax, p * (PNB + 2), capacity);
+                        T1 + (size_t)p * nb * nb, nb, wsp, wsb, flags, flags + Gmax, p * (PNB + 2), capacity,
+                        use_cq ? &cq : nullptr);
         } catch (...) {
             ctx->stream = main;
             throw;
@@ -697,7 +1113,7 @@ void panel_t_build(hgv_ctx_s *ctx, int N, int r, const double2 *P, int ldp, cons
     gg.opb = 'N'; gg.B = Vw; gg.ldb = N;
     gg.C = Gm; gg.ldc = r;
     zgemm(ctx, gg, static_cast<double2 *>(ws), wsb);
-    hipLaunchKernelGGL((build_t_kernel<double2, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt);
+    hipLaunchKernelGGL((build_t_kernel<double2, 1024>), dim3(1), dim3(1024), 0, ctx->stream, r, tau, Gm, r, T, ldt, nullptr);
     HGV_LAUNCH_CHECK();
 }
 

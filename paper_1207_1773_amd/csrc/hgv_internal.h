@@ -139,6 +139,15 @@ __device__ inline double dpp_f64(double x) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// The value of a double in lane l of the wave (l wave-uniform), as its two
+// 32-bit halves.
+__device__ inline double lane_f64(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 inline size_t cdivz(size_t a, size_t b) { return (a + b - 1) / b; }
 
@@ -160,6 +169,8 @@ struct ZGemm {
     double2 *C = nullptr; int ldc = 1;
     int lower = 0;
     int allow_split = 1;   // 0: never split K (lets C alias B when one tile spans n)
+    const int *gate = nullptr;   // non-null: the product runs only if *gate == gate_val
+    int gate_val = 0;            // (a device flag set by an earlier kernel on the stream)
 };
 // Workspace for split-K partial sums reserved by every stage that calls zgemm.
 size_t zgemm_splitk_bytes(int n);
@@ -182,6 +193,8 @@ struct CGemm {
     float2 *C = nullptr; int ldc = 1;
     int lower = 0;
     int allow_split = 1;
+    const int *gate = nullptr;
+    int gate_val = 0;
 };
 void cgemm(hgv_ctx_s *ctx, const CGemm &g, float2 *splitk_ws, size_t splitk_bytes);
 

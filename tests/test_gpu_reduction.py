@@ -43,18 +43,82 @@ def random_band(n, b, seed):
     return B
 
 
-@pytest.mark.parametrize("n,nb", [(1, 4), (2, 1), (5, 3), (40, 8), (100, 32), (129, 16), (300, 32), (513, 32),
-                                  (200, 64), (97, 1)])
-def test_he2hb_reconstruction(ctx, n, nb):
-    A = rand_herm(n, 100 + n)
+@pytest.fixture(params=["fixed", "householder"])
+def panels(request, ctx):
+    """The two forms of the band reduction's panel QR: Cholesky QR twice with
+    Householder reconstruction where the panel allows it (the default), or the
+    Householder column steps for every panel."""
+    import paper_1207_1773_amd as hgv
+    hgv.hgv_test_hooks(ctx.handle, hgv.HGV_TEST_HOUSEHOLDER_PANELS if request.param == "householder" else 0)
+    yield request.param
+    hgv.hgv_test_hooks(ctx.handle, 0)
+
+
+def check_he2hb(ctx, A, nb):
+    """A' = Q1 Band Q1^H, Q1 unitary, eig(Band) = eig(A'); returns the band."""
+    n = A.shape[0]
     Ab, T1 = ctx.he2hb(to_dev(np.tril(A)), nb)
-    Abn = to_np(Ab)
-    i, j = np.indices((n, n))
-    band = band_part(Abn, nb)
+    band = band_part(to_np(Ab), nb)
     Q1 = to_np(ctx.q1(Ab, T1, to_dev(np.eye(n, dtype=complex)), nb))
-    assert rel_fro(Q1 @ band @ Q1.conj().T, A) < _tol(n)
+    scale = max(np.abs(A).max(), 1e-300)
+    assert np.linalg.norm(Q1 @ band @ Q1.conj().T - A) <= _tol(n) * max(np.linalg.norm(A), scale)
     assert np.linalg.norm(Q1.conj().T @ Q1 - np.eye(n)) < _tol(n) * np.sqrt(n)
-    np.testing.assert_allclose(np.linalg.eigvalsh(band), np.linalg.eigvalsh(A), atol=_tol(n) * np.abs(A).max() * n)
+    np.testing.assert_allclose(np.linalg.eigvalsh(band), np.linalg.eigvalsh(A), atol=_tol(n) * scale * n)
+    return band
+
+
+def panel_diagonals(band, n, nb):
+    """Entry (k + nb + i, k + i) of the band for every panel k and i < nb: the diagonal
+    of the panel's triangular factor (real for the Householder column steps)."""
+    out = []
+    for k in range(0, n - nb - 1, nb):
+        r = min(nb, n - k - nb)
+        out.append(np.array([band[k + nb + i, k + i] for i in range(r)]))
+    return out
+
+
+@pytest.mark.parametrize("n,nb", [(1, 4), (2, 1), (5, 3), (40, 8), (100, 32), (129, 16), (300, 32), (513, 32),
+                                  (200, 64), (97, 1), (130, 64), (256, 48)])
+def test_he2hb_reconstruction(ctx, panels, n, nb):
+    A = rand_herm(n, 100 + n)
+    band = check_he2hb(ctx, A, nb)
+    diags = panel_diagonals(band, n, nb)
+    if panels == "householder":
+        assert all(np.all(d.imag == 0) for d in diags)
+    elif diags and n - nb >= nb:
+        # the first panel (at least nb rows below the band) takes the fixed-launch form,
+        # whose triangular factor has complex diagonal entries
+        assert np.any(diags[0].imag != 0)
+
+
+def _fallback_inputs(n, nb):
+    rng = np.random.default_rng(7)
+    A = rand_herm(n, 41)
+    rankdef = A.copy()   # panel 0: two equal columns below the band
+    rankdef[nb:, 1] = rankdef[nb:, 0]
+    rankdef = np.tril(rankdef) + np.tril(rankdef, -1).conj().T
+    graded = A.copy()    # panel 0: columns scaled from 1 to 1e-9 (condition number ~1e9)
+    graded[nb:, :nb] *= np.logspace(0, -9, nb)[None, :]
+    graded = np.tril(graded) + np.tril(graded, -1).conj().T
+    blockdiag = A.copy()  # panel 0 identically zero below the band
+    blockdiag[nb:, :nb] = 0
+    blockdiag = np.tril(blockdiag) + np.tril(blockdiag, -1).conj().T
+    diag = np.diag(rng.standard_normal(n)).astype(complex)   # every panel zero
+    return {"rank_deficient": rankdef, "graded": graded, "zero_panel": blockdiag, "diagonal": diag}
+
+
+@pytest.mark.parametrize("kind", ["rank_deficient", "graded", "zero_panel", "diagonal"])
+def test_he2hb_panel_fallback(ctx, kind):
+    """Panels that Cholesky QR cannot factor accurately (rank deficient, condition
+    number beyond 1e5, zero) are factored by the column steps, chosen on the device; the
+    later panels of the same reduction still take the fixed-launch form."""
+    n, nb = 300, 32
+    A = _fallback_inputs(n, nb)[kind]
+    band = check_he2hb(ctx, A, nb)
+    diags = panel_diagonals(band, n, nb)
+    assert np.all(diags[0].imag == 0)   # the first panel: column steps
+    if kind != "diagonal":
+        assert np.any(diags[1].imag != 0)   # the next one: fixed-launch form
 
 
 @pytest.fixture(params=["owners", "sweeps"])
