@@ -355,7 +355,10 @@ __global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, 
 // without the column steps:
 //   Cholesky QR twice: G1 = P^H P = L1 L1^H, Q1 = P L1^-H; G2 = Q1^H Q1 = L2 L2^H,
 //   Q = Q1 L2^-H, so P = Q R with R = (L1 L2)^H (the second pass restores the
-//   orthogonality the first loses to the rounding of G1);
+//   orthogonality the first loses to the rounding of G1).  G2 = I + E with E of
+//   the order of cond(P)^2 eps, so its factor is taken to first order,
+//   L2 = I + tril(E) with the diagonal halved and L2^-1 = I - (L2 - I): the
+//   neglected terms are O(|E|^2), below rounding while max |E| <= 1e-9;
 //   Householder reconstruction: the LU factorisation without pivoting
 //   Q - [S; 0] = V U, with the unitary diagonal S chosen column by column as
 //   S_jj = -u/|u| (u the current diagonal entry, -1 if zero) so that every pivot
@@ -369,11 +372,11 @@ __global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, 
 // the same contract as the column steps: V below the diagonal of P, the band
 // block S R on and above it (its diagonal complex), tau.
 // A device flag decides between the two methods without a host round trip: the
-// first factorisation sets it when G1 is numerically positive definite with
-// ||L1||_F ||L1^-1||_F <= 1e5 (condition number at most 1e5), the second clears
-// it unless G2 is within 1e-2 of the identity and positive definite.  It gates
-// the reconstruction and the product that finishes V on, the column-step
-// kernels off.
+// factorisation of G1 sets it when G1 is numerically positive definite with
+// ||L1||_F ||L1^-1||_F <= 1e5, the reconstruction clears it unless
+// max |G2 - I| <= 1e-9 (so the panels taken have condition numbers up to about
+// 1e4).  It gates the reconstruction and the product that finishes V on, the
+// column-step kernels off.
 
 constexpr int CQ_NW = 8;             // waves per workgroup
 constexpr int CQ_T = 64 / CQ_NW;      // consecutive columns per wave
@@ -440,16 +443,17 @@ __device__ inline void cq_product(double2 (&c)[CQ_T], SA sa, SB sb, double2 (*As
 // unit lower factor; the pivots' square roots scale both at the end.  The
 // updates are branch-free within a wave (a zero multiplier, or a zero entry of
 // the triangular inverse, leaves an element unchanged), so that the chains of
-// a wave's columns overlap.  stage 1 sets *ok; stage 2 keeps it only if it holds.
+// a wave's columns overlap.  Sets *ok to whether the factorisation succeeded with
+// ||L||_F ||L^-1||_F <= 1e5.
 __global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const double2 *__restrict__ G, int ldg,
                                                               double2 *__restrict__ L, double2 *__restrict__ X,
-                                                              int ldo, int *ok, int stage) {
+                                                              int ldo, int *ok) {
     __shared__ double2 col[2][64];
     __shared__ double red[CQ_NW];
     const int tid = threadIdx.x, i = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     double2 a[CQ_T], x[CQ_T];
-    double tr = 0.0, dev = 0.0;
+    double tr = 0.0;
 #pragma unroll
     for (int t = 0; t < CQ_T; ++t) {
         const int k = CQ_T * w + t;
@@ -459,8 +463,6 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const doubl
         a[t] = v;
         x[t] = make_double2(id, 0.0);
         if (in && i == k) tr += v.x;
-        const double e = (in && i >= k) ? sqrt(zabs2(zsub(v, make_double2(id, 0.0)))) : 0.0;
-        dev = (e > dev || e != e) ? e : dev;
     }
     double myd = 1.0;
     bool bad = false;
@@ -503,16 +505,12 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const doubl
     }
     const double trs = cq_reduce<false>(tr, red);
     const double xss = cq_reduce<false>(xs, red);
-    const double devm = cq_reduce<true>(dev, red);
-    if (tid == 0) {
-        bool good = !bad;
-        if (stage == 1) good = good && trs * xss <= 1e10;
-        else good = good && devm <= 1e-2 && *ok != 0;
-        *ok = good ? 1 : 0;
-    }
+    if (tid == 0) *ok = (!bad && trs * xss <= 1e10) ? 1 : 0;
 }
 
-// The reconstruction, one workgroup in the layout above, when *ok:
+// The second pass and the reconstruction, one workgroup in the layout above,
+// when *ok (cleared here unless max |G2 - I| <= 1e-9):
+//   L2 and L2^-1 to first order from E = G2 - I (lower triangle read);
 //   Q_top = Q1[0:r, :] L2^-H;
 //   its modified LU Q_top - S = V1 U, with V1^-1 formed beside it (V1 goes below
 //   the diagonal of P's top block, tau_j = -U_jj conj(S_jj));
@@ -522,18 +520,44 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const doubl
 //   the band block S (L1 L2)^H on and above the diagonal of P's top block.
 __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const double2 *__restrict__ Q1, int ldq,
                                                                const double2 *__restrict__ L1,
-                                                               const double2 *__restrict__ L2,
-                                                               const double2 *__restrict__ X2, int ldo, double2 *P,
+                                                               const double2 *__restrict__ G2, int ldo, double2 *P,
                                                                int ldp, double2 *tau, double2 *__restrict__ T,
-                                                               int ldt, double2 *__restrict__ M, const int *ok) {
+                                                               int ldt, double2 *M, int *ok) {
     if (*ok == 0) return;
     __shared__ double2 col[2][64];
     __shared__ double2 sv[64];
     __shared__ double2 As[CQ_MC][65], Bs[CQ_MC][65];
+    __shared__ double red[CQ_NW];
     const int tid = threadIdx.x, i = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double2 zero = make_double2(0.0, 0.0), one = make_double2(1.0, 0.0);
     constexpr int NT = CQ_NW * 64;
+    {
+        double dev = 0.0;
+        for (int e = tid; e < r * r; e += NT) {
+            const int ii = e % r, k = e / r;
+            if (ii >= k) {
+                const double2 v = G2[ii + (size_t)k * ldo];
+                const double d = sqrt(zabs2(zsub(v, make_double2(ii == k ? 1.0 : 0.0, 0.0))));
+                dev = (d > dev || d != d) ? d : dev;
+            }
+        }
+        const double devm = cq_reduce<true>(dev, red);
+        if (!(devm <= 1e-9)) {
+            if (tid == 0) *ok = 0;
+            return;
+        }
+    }
+    // L2[k][m] (k >= m) = E[k][m] below the diagonal, 1 + E[k][k] / 2 on it;
+    // X2 = L2^-1 = 2 I - L2 to first order
+    auto l2 = [&](int k, int m) -> double2 {
+        const double2 v = G2[k + (size_t)m * ldo];
+        return zsel(k == m, make_double2(1.0 + 0.5 * (v.x - 1.0), 0.0), v);
+    };
+    auto x2 = [&](int k, int m) -> double2 {
+        const double2 v = G2[k + (size_t)m * ldo];
+        return zsel(k == m, make_double2(1.0 - 0.5 * (v.x - 1.0), 0.0), zsub(zero, v));
+    };
     double2 a[CQ_T], vx[CQ_T];
 #pragma unroll
     for (int t = 0; t < CQ_T; ++t) a[t] = zero;
@@ -551,7 +575,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
             for (int e = tid; e < CQ_MC * 64; e += NT) {
                 const int k = e & 63, m = m0 + (e >> 6);
                 const bool in = k < r && m <= k;
-                Bs[e >> 6][k] = zsel(in, zconj(X2[in ? k + (size_t)m * ldo : 0]), zero);
+                Bs[e >> 6][k] = zsel(in, zconj(x2(in ? k : 0, in ? m : 0)), zero);
             }
         },
         As, Bs, w, i);
@@ -597,6 +621,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
     for (int t = 0; t < CQ_T; ++t) {
         const int k = CQ_T * w + t;
         if (i > k && i < r && k < r) P[i + (size_t)k * ldp] = a[t];
+        M[i + (size_t)k * 64] = vx[t];   // V1^-1 (64 x 64) parked in M's space until M is formed
     }
     // T = -(U S^H) V1^-H: A[i][m] = U[i][m] conj(S_m) (upper), B[m][k] = conj(V1^-1[k][m])
     double2 c[CQ_T];
@@ -612,10 +637,9 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
             }
         },
         [&](int m0) {
-#pragma unroll
-            for (int t = 0; t < CQ_T; ++t) {
-                const int m = CQ_T * w + t;
-                if (m >= m0 && m < m0 + CQ_MC) Bs[m - m0][i] = zconj(vx[t]);
+            for (int e = tid; e < CQ_MC * 64; e += NT) {
+                const int k = e & 63, m = m0 + (e >> 6);
+                Bs[e >> 6][k] = zconj(M[k + (size_t)m * 64]);
             }
         },
         As, Bs, w, i);
@@ -653,7 +677,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
             for (int e = tid; e < CQ_MC * 64; e += NT) {
                 const int ii = e & 63, m = m0 + (e >> 6);
                 const bool in = m < r && ii <= m;
-                As[e >> 6][ii] = zsel(in, zconj(X2[in ? m + (size_t)ii * ldo : 0]), zero);
+                As[e >> 6][ii] = zsel(in, zconj(x2(in ? m : 0, in ? ii : 0)), zero);
             }
         },
         [&](int m0) {
@@ -684,7 +708,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
             for (int e = tid; e < CQ_MC * 64; e += NT) {
                 const int k = e & 63, m = m0 + (e >> 6);
                 const bool in = m < r && k <= m;
-                Bs[e >> 6][k] = zsel(in, L2[in ? m + (size_t)k * ldo : 0], zero);
+                Bs[e >> 6][k] = zsel(in, l2(in ? m : 0, in ? k : 0), zero);
             }
         },
         As, Bs, w, i);
@@ -696,7 +720,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
 }
 
 struct CqrScratch {
-    double2 *G, *L1, *X1, *L2, *X2, *M, *Q;   // r x r (ld r) each; Q: N x r (ld N)
+    double2 *G, *L1, *X1, *M, *Q;   // r x r (ld r) each; Q: N x r (ld N)
     int *ok;
 };
 
@@ -710,7 +734,7 @@ static void cholqr_panel(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int r, doub
     g.opb = 'N'; g.B = P; g.ldb = ldp;
     g.C = c.G; g.ldc = r;
     zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
-    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.G, r, c.L1, c.X1, r, c.ok, 1);
+    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.G, r, c.L1, c.X1, r, c.ok);
     HGV_LAUNCH_CHECK();
     g = ZGemm();   // Q1 = P L1^-H
     g.m = N; g.n = r; g.k = r;
@@ -724,10 +748,8 @@ static void cholqr_panel(hgv_ctx_s *ctx, double2 *P, int ldp, int N, int r, doub
     g.opb = 'N'; g.B = c.Q; g.ldb = N;
     g.C = c.G; g.ldc = r;
     zgemm(ctx, g, static_cast<double2 *>(ws), wsb);
-    hipLaunchKernelGGL(cqr_chol_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.G, r, c.L2, c.X2, r, c.ok, 2);
-    HGV_LAUNCH_CHECK();
-    hipLaunchKernelGGL(cqr_recon_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.Q, N, c.L1, c.L2, c.X2, r,
-                       P, ldp, tau, T, ldt, c.M, c.ok);
+    hipLaunchKernelGGL(cqr_recon_kernel, dim3(1), dim3(CQ_NW * 64), 0, ctx->stream, r, c.Q, N, c.L1, c.G, r, P, ldp,
+                       tau, T, ldt, c.M, c.ok);
     HGV_LAUNCH_CHECK();
     if (N > r) {
         g = ZGemm();   // V2 = Q1[r:, :] M, into P below the top block
@@ -848,9 +870,9 @@ void he2hb_t(hgv_ctx_s *ctx, int n, int nb, E *A, int lda, E *T1, Arena &ar, int
     CqrScratch cq{};
     const bool use_cq = std::is_same<E, double2>::value;
     if (use_cq) {
-        double2 *b = ar.take<double2>((size_t)6 * PNB * PNB + (size_t)std::max(n, 1) * nb);
-        cq.G = b; cq.L1 = b + PNB * PNB; cq.X1 = b + 2 * PNB * PNB; cq.L2 = b + 3 * PNB * PNB;
-        cq.X2 = b + 4 * PNB * PNB; cq.M = b + 5 * PNB * PNB; cq.Q = b + 6 * PNB * PNB;
+        double2 *b = ar.take<double2>((size_t)4 * PNB * PNB + (size_t)std::max(n, 1) * nb);
+        cq.G = b; cq.L1 = b + PNB * PNB; cq.X1 = b + 2 * PNB * PNB; cq.M = b + 3 * PNB * PNB;
+        cq.Q = b + 4 * PNB * PNB;
         cq.ok = ar.take<int>(1);
     }
     if (ar.measuring() || n == 0) return;

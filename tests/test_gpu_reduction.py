@@ -100,18 +100,23 @@ def _fallback_inputs(n, nb):
     graded = A.copy()    # panel 0: columns scaled from 1 to 1e-9 (condition number ~1e9)
     graded[nb:, :nb] *= np.logspace(0, -9, nb)[None, :]
     graded = np.tril(graded) + np.tril(graded, -1).conj().T
+    nearpar = A.copy()   # panel 0: two nearly parallel columns (condition number ~2e4): its
+    nearpar[nb:, 1] = nearpar[nb:, 0] + 1e-4 * nearpar[nb:, 1]   # Gram matrix factors, but
+    nearpar = np.tril(nearpar) + np.tril(nearpar, -1).conj().T   # one pass leaves |G2 - I| ~ 1e-8
     blockdiag = A.copy()  # panel 0 identically zero below the band
     blockdiag[nb:, :nb] = 0
     blockdiag = np.tril(blockdiag) + np.tril(blockdiag, -1).conj().T
     diag = np.diag(rng.standard_normal(n)).astype(complex)   # every panel zero
-    return {"rank_deficient": rankdef, "graded": graded, "zero_panel": blockdiag, "diagonal": diag}
+    return {"rank_deficient": rankdef, "graded": graded, "near_parallel": nearpar, "zero_panel": blockdiag,
+            "diagonal": diag}
 
 
-@pytest.mark.parametrize("kind", ["rank_deficient", "graded", "zero_panel", "diagonal"])
+@pytest.mark.parametrize("kind", ["rank_deficient", "graded", "near_parallel", "zero_panel", "diagonal"])
 def test_he2hb_panel_fallback(ctx, kind):
-    """Panels that Cholesky QR cannot factor accurately (rank deficient, condition
-    number beyond 1e5, zero) are factored by the column steps, chosen on the device; the
-    later panels of the same reduction still take the fixed-launch form."""
+    """Panels that Cholesky QR cannot factor accurately (rank deficient; condition number
+    beyond 1e5, caught when G1 is factored; nearly parallel columns, caught by the second
+    Gram matrix; zero) are factored by the column steps, chosen on the device; the later
+    panels of the same reduction still take the fixed-launch form."""
     n, nb = 300, 32
     A = _fallback_inputs(n, nb)[kind]
     band = check_he2hb(ctx, A, nb)
