@@ -113,6 +113,7 @@ struct KDepth {
 };
 constexpr int PAD = 1;
 
+
 __device__ inline int remap_xcd(int bid, int total) {
     int full = (total / 8) * 8;
     if (bid < full) return (bid % 8) * (total / 8) + bid / 8;
@@ -503,11 +504,52 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     // real (one MFMA per 16x16x4 block, so the larger tile keeps the operand
     // bytes per flop as low as the complex tile's)
     constexpr int BM = Shape<T>::BM, BN = Shape<T>::BN, NW = Shape<T>::NW;
-    g.tiles_m = cdiv(a.m, BM);
-    g.tiles_n = cdiv(a.n, BN);
+    // small complex-double products (fewer than 128 tiles of 64 x 64, K <= 512): a
+    // one-tile product's 768 MFMAs per 16 of K run on one CU, so the output is cut
+    // into 32 x 32 tiles instead, spreading the same MFMAs over four times the
+    // CUs (each output element keeps its order of summation).  A product computed
+    // in place keeps one tile across the aliased operand's other dimension:
+    // 32 x 64 when C is A (n <= 64), 64 x 32 when C is B (m <= 64), so that no
+    // workgroup writes rows or columns another one still reads; any other overlap
+    // of C with an operand keeps the 64 x 64 tiles.
+    int bm = BM, bn = BN;
+    if constexpr (std::is_same<T, TZ>::value) {
+        if (cdiv(a.m, 64) * cdiv(a.n, 64) < 128 && a.k <= 512) {
+            const char *c0 = reinterpret_cast<const char *>(a.C);
+            const char *c1 = c0 + ((size_t)a.ldc * (a.n - 1) + a.m) * sizeof(E);
+            // the bytes an operand spans (rows x cols stored, leading dimension ld)
+            auto overlaps = [&](const void *p, int ld, int rows, int cols) {
+                if (!p || rows <= 0 || cols <= 0) return false;
+                const char *p0 = static_cast<const char *>(p);
+                const char *p1 = p0 + ((size_t)ld * (cols - 1) + rows) * sizeof(E);
+                return p0 < c1 && c0 < p1;
+            };
+            const bool ta = a.opa != 'N' && a.opa != 'n', tb = a.opb != 'N' && a.opb != 'n';
+            const bool ta2 = a.opa2 != 'N' && a.opa2 != 'n', tb2 = a.opb2 != 'N' && a.opb2 != 'n';
+            const bool seg2 = a.A2 && a.B2;
+            const bool ovA = overlaps(a.A, a.lda, ta ? a.k : a.m, ta ? a.m : a.k);
+            const bool ovB = overlaps(a.B, a.ldb, tb ? a.n : a.k, tb ? a.k : a.n);
+            const bool ov2 = seg2 && (overlaps(a.A2, a.lda2, ta2 ? a.k : a.m, ta2 ? a.m : a.k) ||
+                                      overlaps(a.B2, a.ldb2, tb2 ? a.n : a.k, tb2 ? a.k : a.n));
+            const bool sameA = static_cast<const void *>(a.C) == static_cast<const void *>(a.A) && !ta &&
+                               a.lda == a.ldc;
+            const bool sameB = static_cast<const void *>(a.C) == static_cast<const void *>(a.B) && !tb &&
+                               a.ldb == a.ldc;
+            if (!ovA && !ovB && !ov2) {
+                bm = 32; bn = 32;
+            } else if (sameA && !ovB && !ov2 && a.n <= 64) {
+                bm = 32; bn = 64;
+            } else if (sameB && !ovA && !ov2 && a.m <= 64) {
+                bm = 64; bn = 32;
+            }
+        }
+    }
+    const bool small = bm != BM || bn != BN;
+    g.tiles_m = cdiv(a.m, bm);
+    g.tiles_n = cdiv(a.n, bn);
     int tiles = g.tiles_m * g.tiles_n;
     g.lower_tiles = 0;
-    if (a.lower && BM == BN) {
+    if (a.lower && bm == bn) {
         // lower tiles of row tile tm: tn = 0 .. min(tm, tiles_n - 1)
         const int K = std::min(g.tiles_m, g.tiles_n);
         tiles = K * (K + 1) / 2 + (g.tiles_m - K) * g.tiles_n;
@@ -517,7 +559,7 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     int splits = 1;
     // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
     // (every split keeps at least 4 chunks)
-    while (a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 4) splits *= 2;
+    while (!small && a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 4) splits *= 2;
     size_t need = (size_t)splits * a.m * a.n * sizeof(E);
     while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
         splits /= 2;
@@ -526,9 +568,10 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     g.splits = splits;
     g.P = splits > 1 ? ws : nullptr;
 
-    // optional accounting of the complex-double tile kernel alone (the events
-    // bracket gemm_kernel<TZ>; the split-K reduction is a separate kernel)
-    const bool timed = ctx->time_gemm && std::is_same<T, TZ>::value;
+    // optional accounting of the 64 x 64 complex-double tile kernel alone (the
+    // events bracket gemm_kernel<TZ, 64, 64, 4>; the split-K reduction and the
+    // small-product tiles are separate kernels)
+    const bool timed = ctx->time_gemm && std::is_same<T, TZ>::value && !small;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
         if (ctx->ev_free.size() < 2) {
@@ -546,6 +589,12 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
         // the start and stop events ride on the kernel's own dispatch (no separate
         // marker packets between the launches)
         hipExtLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, e0, e1, 0, g);
+    } else if (small && bn == 32 && bm == 32) {
+        hipLaunchKernelGGL((gemm_kernel<T, 32, 32, 4>), grid, dim3(256), 0, ctx->stream, g);
+    } else if (small && bm == 32) {
+        hipLaunchKernelGGL((gemm_kernel<T, 32, 64, 4>), grid, dim3(256), 0, ctx->stream, g);
+    } else if (small) {
+        hipLaunchKernelGGL((gemm_kernel<T, 64, 32, 4>), grid, dim3(256), 0, ctx->stream, g);
     } else {
         hipLaunchKernelGGL((gemm_kernel<T, BM, BN, NW>), grid, dim3(NW * 64), 0, ctx->stream, g);
     }

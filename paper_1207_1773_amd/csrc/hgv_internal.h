@@ -168,7 +168,8 @@ struct ZGemm {
     double2 alpha = {1.0, 0.0}, beta = {0.0, 0.0};
     double2 *C = nullptr; int ldc = 1;
     int lower = 0;
-    int allow_split = 1;   // 0: never split K (lets C alias B when one tile spans n)
+    int allow_split = 1;   // 0: C may alias A or B: K is never split and one tile spans
+                           // the aliased operand's other dimension
     const int *gate = nullptr;   // non-null: the product runs only if *gate == gate_val
     int gate_val = 0;            // (a device flag set by an earlier kernel on the stream)
 };

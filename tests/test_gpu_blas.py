@@ -1,7 +1,10 @@
 """GPU parity of the level-3 building blocks and of Alg. 1 steps 1, 2 and 4.
 
 * zgemm (the MFMA tiles every stage uses) against numpy's fp64 product, over all
-  operand modes, ragged sizes that span several 64 x 64 tiles, and split-K shapes.
+  operand modes, ragged sizes that span several 64 x 64 tiles, small products on
+  32 x 32 tiles (fewer than 128 tiles of 64 x 64 and K <= 512), and split-K shapes.
+  The in-place tiles (32 x 64 and 64 x 32) run inside the Cholesky, reduction and
+  triangular-solve parity tests below.
 * Cholesky (Alg. 1 step 1) and the reduction to standard form (Alg. 1 step 2) have
   unique results, so they are compared entry by entry with the oracle.
 * The back-substitution X = L^-H Y (Alg. 1 step 4) against a triangular solve.
@@ -30,7 +33,7 @@ def _op(M, op):
 
 
 @pytest.mark.parametrize("m,n,k", [(1, 1, 1), (64, 64, 64), (65, 33, 17), (200, 130, 300), (16, 16, 5000),
-                                   (300, 64, 4096), (129, 257, 0)])
+                                   (300, 64, 4096), (129, 257, 0), (500, 301, 128), (100, 700, 512)])
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N"), ("T", "T"), ("C", "C"), ("N", "T")])
 def test_zgemm_parity(ctx, m, n, k, opa, opb):
     rng = np.random.default_rng(m * 7 + n * 3 + k)
