@@ -557,12 +557,35 @@ static void gemm_launch(hgv_ctx_s *ctx, const G &a, typename T::E *ws, size_t ws
     }
     int chunks = cdiv(std::max(a.k, 0), KDepth<T>::v) * g.nseg;
     int splits = 1;
-    // fewer than ~2 waves of tiles on 256 CUs and a long K: split the K loop
-    // (every split keeps at least 4 chunks)
-    while (!small && a.allow_split && splits < 64 && tiles * splits < 512 && chunks / (splits * 2) >= 4) splits *= 2;
+    // fewer tiles than resident workgroups and a long K: split the K loop into the
+    // number of parts that takes the fewest chunk steps on the critical path, the
+    // waves of resident workgroups times the chunks per part, plus the reduction
+    // (its launch, about two chunk steps, and its traffic, the parts written and
+    // read back at ~4 TB/s against ~2.5 us per chunk step); every part keeps at
+    // least 4 chunks
+    const int ti = std::is_same<T, TZ>::value ? 0 : (std::is_same<T, TC>::value ? 1 : 2);
+    if (ctx->gemm_slots[ti] == 0) {
+        int cus = 0, per = 0;
+        HGV_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        HGV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gemm_kernel<T, BM, BN, NW>, NW * 64, 0));
+        ctx->gemm_slots[ti] = std::max(1, cus * per);
+    }
+    const long slots = ctx->gemm_slots[ti];
+    if (!small && a.allow_split && tiles < slots) {
+        double best = chunks;
+        const double out = (double)a.m * a.n * sizeof(E) * 1e-7;   // chunk steps per pass over C
+        for (int s = 2; s <= 64 && chunks / s >= 4; ++s) {
+            const double cost = (double)(((long)tiles * s + slots - 1) / slots * ((chunks + s - 1) / s)) + 2.0 +
+                                (s + 1) * out;
+            if (cost < best) {
+                best = cost;
+                splits = s;
+            }
+        }
+    }
     size_t need = (size_t)splits * a.m * a.n * sizeof(E);
     while (splits > 1 && (ws == nullptr || need > ws_bytes)) {
-        splits /= 2;
+        --splits;
         need = (size_t)splits * a.m * a.n * sizeof(E);
     }
     g.splits = splits;

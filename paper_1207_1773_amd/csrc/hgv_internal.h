@@ -40,6 +40,10 @@ struct hgv_ctx_s {
     // that share of the device, so all of them fit at once.  0: panels use their
     // launch-per-step form while concurrent.
     int panel_share = 0;
+    // workgroups of the 64 x 64 (128 x 128 for real) GEMM tile kernel resident on
+    // the device at once, per element type (complex double, complex float, real
+    // double); 0 until the first product of that type
+    int gemm_slots[3] = {0, 0, 0};
     // Side streams of one solve (created on first use, default priority) and
     // their events: [0] runs the next panel of the band reduction under the
     // current update (events 0, 1), [1] the left triangular solves of the
