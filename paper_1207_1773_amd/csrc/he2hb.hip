@@ -351,7 +351,8 @@ __global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, 
 }
 
 // ---- panel QR in a fixed number of launches -------------------------------------
-// A panel of full column rank that is not too ill-conditioned is factored
+// The panel QR of step (a) of the reduction to band (Sec. 4.2, Fig. 1): a complex
+// double panel of full column rank that is not too ill-conditioned is factored
 // without the column steps:
 //   Cholesky QR twice: G1 = P^H P = L1 L1^H, Q1 = P L1^-H; G2 = Q1^H Q1 = L2 L2^H,
 //   Q = Q1 L2^-H, so P = Q R with R = (L1 L2)^H (the second pass restores the
@@ -364,19 +365,19 @@ __global__ __launch_bounds__(NT) void build_t_kernel(int r, const double2 *tau, 
 //   S_jj = -u/|u| (u the current diagonal entry, -1 if zero) so that every pivot
 //   has modulus at least 1, gives the unit lower-trapezoidal V of the block
 //   reflector Q_h = I - V T V^H whose first r columns are Q S^H; hence
-//   P = Q_h [S R; 0] and the reflectors' scalars are tau_j = -U_jj conj(S_jj)
-//   (T is then formed from tau and V^H V as for the column steps).
+//   P = Q_h [S R; 0], the reflectors' scalars are tau_j = -U_jj conj(S_jj), and
+//   T = -(U S^H) V1^-H (from V T V1^H = E - Q S^H, E the first r columns of I).
 // (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya, ETNA 44, 2015, for the two
 // passes; Ballard, Demmel, Grigori, Jacquelin, Knight and Nguyen, IPDPS 2014,
 // for the reconstruction, here in complex arithmetic.)  The results satisfy
 // the same contract as the column steps: V below the diagonal of P, the band
-// block S R on and above it (its diagonal complex), tau.
+// block S R on and above it (its diagonal complex), tau, T.
 // A device flag decides between the two methods without a host round trip: the
 // factorisation of G1 sets it when G1 is numerically positive definite with
 // ||L1||_F ||L1^-1||_F <= 1e5, the reconstruction clears it unless
 // max |G2 - I| <= 1e-9 (so the panels taken have condition numbers up to about
-// 1e4).  It gates the reconstruction and the product that finishes V on, the
-// column-step kernels off.
+// 1e4).  It gates the reconstruction and the product that finishes V on, and
+// the column-step kernels, the product V^H V and the T recurrence off.
 
 constexpr int CQ_NW = 8;             // waves per workgroup
 constexpr int CQ_T = 64 / CQ_NW;      // consecutive columns per wave
