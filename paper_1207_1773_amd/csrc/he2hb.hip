@@ -432,7 +432,7 @@ __device__ inline void cq_product(double2 (&c)[CQ_T], SA sa, SB sb, double2 (*As
         for (int mm = 0; mm < CQ_MC; ++mm) {
             const double2 av = As[mm][i];
 #pragma unroll
-            for (int t = 0; t < CQ_T; ++t) c[t] = zadd(c[t], zmul(av, Bs[mm][CQ_T * w + t]));
+            for (int t = 0; t < CQ_T; ++t) zfma(c[t], av, Bs[mm][CQ_T * w + t]);
         }
     }
 }
@@ -481,12 +481,12 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_chol_kernel(int r, const doubl
             for (int t = 0; t < CQ_T; ++t) {
                 const int k = CQ_T * w + t;
                 const double2 mk = zsel(k > j, m, make_double2(0.0, 0.0));
-                a[t] = zsub(a[t], zmul(mk, zconj(lane_z(c, k))));
+                zfma(a[t], make_double2(-mk.x, -mk.y), zconj(lane_z(c, k)));
             }
         }
         if (w <= wj) {   // columns k <= j of the inverse (X[j][k] = 0 for k > j)
 #pragma unroll
-            for (int t = 0; t < CQ_T; ++t) x[t] = zsub(x[t], zmul(m, lane_z(x[t], j)));
+            for (int t = 0; t < CQ_T; ++t) zfma(x[t], make_double2(-m.x, -m.y), lane_z(x[t], j));
         }
     }
     const double si = bad ? 1.0 : 1.0 / sqrt(myd);
@@ -610,12 +610,13 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
 #pragma unroll
             for (int t = 0; t < CQ_T; ++t) {
                 const int k = CQ_T * w + t;
-                a[t] = zsub(a[t], zmul(zsel(k > j, l, zero), lane_z(a[t], j)));
+                const double2 lk = zsel(k > j, l, zero);
+                zfma(a[t], make_double2(-lk.x, -lk.y), lane_z(a[t], j));
             }
         }
         if (w <= wj) {   // V1^-1: the same row operations on the identity
 #pragma unroll
-            for (int t = 0; t < CQ_T; ++t) vx[t] = zsub(vx[t], zmul(l, lane_z(vx[t], j)));
+            for (int t = 0; t < CQ_T; ++t) zfma(vx[t], make_double2(-l.x, -l.y), lane_z(vx[t], j));
         }
     }
 #pragma unroll
@@ -665,7 +666,7 @@ __global__ __launch_bounds__(CQ_NW * 64) void cqr_recon_kernel(int r, const doub
 #pragma unroll
             for (int t = 0; t < CQ_T; ++t) {
                 y[t] = zsel(i == j, zmul(y[t], iu), y[t]);
-                y[t] = zsub(y[t], zmul(cu, lane_z(y[t], j)));
+                zfma(y[t], make_double2(-cu.x, -cu.y), lane_z(y[t], j));
             }
         }
     }
