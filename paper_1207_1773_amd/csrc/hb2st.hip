@@ -668,8 +668,8 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
             double2 ay = zero, ap = zero;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                ay = zadd(ay, zmul(Es[row][q + TPR * u], vr[u]));
-                ap = zadd(ap, zmul(Dr[u], vr[u]));
+                zfma(ay, Es[row][q + TPR * u], vr[u]);
+                zfma(ap, Dr[u], vr[u]);
             }
             const double2 y = zmul(tau, sum8_dpp(ay));
             const double2 prow = zmul(tau, sum8_dpp(ap));
@@ -713,7 +713,9 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
             for (int u = 0; u < NU; ++u) {
                 const int k = q + TPR * u;
                 const double2 wk = zsub(pv[k], zscale(half, vr[u]));
-                double2 val = zsub(zsub(Dr[u], zmul(vrow, zconj(wk))), zmul(wrow, zconj(vr[u])));
+                double2 val = Dr[u];
+                zfma(val, make_double2(-vrow.x, -vrow.y), zconj(wk));
+                zfma(val, make_double2(-wrow.x, -wrow.y), zconj(vr[u]));
                 if (k == row) val.y = 0.0;
                 Dr[u] = val;
             }
@@ -744,13 +746,15 @@ __global__ __launch_bounds__(NT) void hb2st_owner_kernel(HbOwnArgs<E> a) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = q + TPR * u;
-                acc = zadd(acc, zcmul(v2s[i], Es[i][cc]));
+                zcfma(acc, v2s[i], Es[i][cc]);
             }
             const double2 wc = zcmul(tau2, zsub(sum8_dpp(acc), zmul(vy, vc)));
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 const int i = q + TPR * u;
-                const double2 upd = zsub(zsub(Es[i][cc], zmul(yv[i], vc)), zmul(v2s[i], wc));
+                double2 upd = Es[i][cc];
+                zfma(upd, make_double2(-yv[i].x, -yv[i].y), vc);
+                zfma(upd, make_double2(-v2s[i].x, -v2s[i].y), wc);
                 Es[i][cc] = zsel(cc == f, zsel(i == f, make_double2(beta2, 0.0), zero), upd);
             }
         }

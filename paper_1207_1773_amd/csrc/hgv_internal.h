@@ -128,6 +128,11 @@ __host__ __device__ inline void zfma(double2 &a, double2 b, double2 c) {
     a.x = fma(b.x, c.x, fma(-b.y, c.y, a.x));
     a.y = fma(b.x, c.y, fma(b.y, c.x, a.y));
 }
+// a += conj(b) * c
+__host__ __device__ inline void zcfma(double2 &a, double2 b, double2 c) {
+    a.x = fma(b.x, c.x, fma(b.y, c.y, a.x));
+    a.y = fma(b.x, c.y, fma(-b.y, c.x, a.y));
+}
 __host__ __device__ inline double2 zdiv(double2 a, double2 b) {
     double s = 1.0 / (b.x * b.x + b.y * b.y);
     return make_double2((a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s);
