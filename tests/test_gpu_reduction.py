@@ -78,7 +78,7 @@ def panel_diagonals(band, n, nb):
 
 
 @pytest.mark.parametrize("n,nb", [(1, 4), (2, 1), (5, 3), (40, 8), (100, 32), (129, 16), (300, 32), (513, 32),
-                                  (200, 64), (97, 1), (130, 64), (256, 48)])
+                                  (200, 64), (97, 1), (130, 64), (256, 48), (128, 64), (96, 32)])
 def test_he2hb_reconstruction(ctx, panels, n, nb):
     A = rand_herm(n, 100 + n)
     band = check_he2hb(ctx, A, nb)
