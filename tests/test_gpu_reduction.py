@@ -111,6 +111,24 @@ def _fallback_inputs(n, nb):
             "diagonal": diag}
 
 
+@pytest.mark.parametrize("kind", ["rank_deficient", "near_parallel", "zero_panel"])
+def test_solve_with_mixed_panel_forms(ctx, kind):
+    """A whole solve (B = 2I, so A' = A/2 keeps the panel structure) whose band reduction
+    takes the column steps for its first panel and the fixed-launch form for the rest:
+    eigenvalues against the oracle at the FP64 bars, residual and B-orthogonality."""
+    from tests.metrics import orthogonality, residual
+    n, nb = 300, 32
+    A = _fallback_inputs(n, nb)[kind]
+    B = 2.0 * np.eye(n, dtype=complex)
+    W, X, info, _ = ctx.zhegvx(to_dev(A), to_dev(B), 1, n, nb=nb)
+    assert info == 0
+    W, X = to_np(W), to_np(X)
+    Wo, _, _ = oracle.zhegv(A, B, 1, n)
+    np.testing.assert_allclose(W, Wo, rtol=0, atol=1e-12 * np.abs(Wo).max())
+    assert residual(A, B, W, X) <= 1e-14
+    assert orthogonality(B, X) <= 1e-13 * n
+
+
 @pytest.mark.parametrize("kind", ["rank_deficient", "graded", "near_parallel", "zero_panel", "diagonal"])
 def test_he2hb_panel_fallback(ctx, kind):
     """Panels that Cholesky QR cannot factor accurately (rank deficient; condition number
